@@ -1,0 +1,196 @@
+/*
+ * duplexgs.h -- C ABI of the MI355X (gfx950) Duplex-GS proxy-guided renderer.
+ *
+ * The renderer implements the per-frame hot path of Duplex-GS (arXiv
+ * 2508.03180):
+ *   1. cell rasterization (Sec. IV-B): project and near-cull the ellipsoidal
+ *      cell proxies (x_n, S_n, Q_n), bound their screen footprint, assign them
+ *      to 16x16 tiles and radix-sort one (tile, depth) key per (cell, tile);
+ *   2. the hybrid renderer (Sec. V-A, eq. hybrid_renderer, w_n = v_n T_n,
+ *      eq. dulpex_T): per pixel, walk the tile's cells front to back, sum each
+ *      cell's Gaussians order-free with alpha = sigma G'(x') (eq.
+ *      alpha_blending), blend across cells with the cell transmittance and
+ *      stop once it falls below eps (Sec. V-B), skipping Gaussians whose
+ *      bounding box misses the pixel (Sec. VI-A);
+ *   3. as a comparison path in the same library, per-Gaussian keys and
+ *      front-to-back alpha blending (eqs. alpha_blending, transmittance).
+ *
+ * Conventions shared by every entry point
+ *   - All array pointers are DEVICE pointers (HIP global memory) unless the
+ *     comment says "host".  All floating point data is IEEE binary32.
+ *   - Arrays are planar ("component-major"): a [3][N] array stores all x
+ *     components, then all y, then all z, each contiguous over N.  This keeps
+ *     every per-primitive load coalesced.
+ *   - The caller owns scene, image and gradient buffers; the library owns the
+ *     context, its workspace and its streams' work.  Nothing is retained past
+ *     a call except what the context documents (the last frame's state).
+ *   - Every call enqueues work on the context's stream and returns without a
+ *     host synchronisation, unless its comment says it synchronises.
+ *   - Errors that the host can see return at once and enqueue nothing.
+ *     Errors only the device can see (key capacity overflow, a look-back wait
+ *     that timed out) set a device flag that dgs_sync / dgs_get_stats report.
+ *     Outputs of a failed call are undefined.  Nothing throws across the ABI.
+ *   - A context is not thread-safe; use one per host thread / stream.
+ */
+#ifndef DUPLEXGS_H
+#define DUPLEXGS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dgs_ctx_s* dgs_ctx;
+
+typedef enum {
+    DGS_OK = 0,
+    DGS_ERR_INVALID_ARG = 1, /* bad pointer, size, degree or camera */
+    DGS_ERR_OOM = 2,         /* device allocation failed */
+    DGS_ERR_CAPACITY = 3,    /* more (tile, primitive) keys than reserved; reserve more, render again */
+    DGS_ERR_DEVICE = 4,      /* a HIP call failed */
+    DGS_ERR_UNSUPPORTED = 5, /* valid request this build does not implement */
+    DGS_ERR_TIMEOUT = 6      /* a bounded device-side wait gave up (results invalid) */
+} dgs_status;
+
+typedef enum {
+    DGS_MODE_DUPLEX = 0, /* per-cell keys + hybrid weighted-sum renderer (Sec. IV-V) */
+    DGS_MODE_ALPHA = 1   /* per-Gaussian keys + sorted alpha blending (comparison path) */
+} dgs_mode;
+
+#define DGS_FLAG_V_ONE 1u  /* v_n = 1 for every cell (the "w/o v_n" ablation) */
+#define DGS_FLAG_NO_ET 2u  /* no early termination (eps = 0) */
+#define DGS_FLAG_STATS 4u  /* also count N^val / N^rendered (termination ratio) */
+
+/*
+ * Scene (Sec. IV-A): N ellipsoidal cells, each emitting K Gaussians.
+ * Member k of cell n is Gaussian n*K + k; M = N*K.
+ */
+typedef struct {
+    int32_t num_cells;          /* N >= 0 */
+    int32_t gaussians_per_cell; /* K in 1..32 */
+    const float* cell_pos;      /* [3][N]  x_n */
+    const float* cell_scale;    /* [3][N]  S_n, semi-axes (> 0) */
+    const float* cell_rot;      /* [4][N]  Q_n as (w, x, y, z); normalised here */
+    const float* cell_v_sh;     /* [Cv][N] SH coefficients of logit(v_n), Cv = (v_sh_degree+1)^2 */
+    int32_t v_sh_degree;        /* 0..3 */
+    const float* means;         /* [3][M]  mu */
+    const float* scales;        /* [3][M]  s (> 0) */
+    const float* rots;          /* [4][M]  q as (w, x, y, z); normalised here */
+    const float* opacities;     /* [M]     sigma in [0, 1]; sigma <= 0 marks an invalid Gaussian */
+    const float* sh;            /* [C][3][M] colour SH, C = (sh_degree+1)^2, colour = max(0, 0.5 + sum sh Y) */
+    int32_t sh_degree;          /* 0..3 */
+} dgs_scene;
+
+/* Pinhole camera, host struct passed by pointer and copied at the call. */
+typedef struct {
+    float viewmat[16]; /* row-major world->camera [R | t; 0 0 0 1], OpenCV axes (x right, y down, z forward) */
+    float fx, fy, cx, cy;
+    int32_t width, height; /* 1..32767 */
+    float z_near;          /* primitives with camera depth <= z_near are culled */
+} dgs_camera;
+
+/* Render options, host struct.  dgs_default_opts fills the defaults. */
+typedef struct {
+    int32_t mode;          /* dgs_mode */
+    uint32_t flags;        /* DGS_FLAG_* */
+    float eps_T;           /* termination threshold on the transmittance in front of a cell (1e-4) */
+    float alpha_min;       /* alpha below this is skipped (1/255) */
+    float alpha_max;       /* alpha clamp (0.99) */
+    float cov2d_dilation;  /* screen-space variance added to every Gaussian, px^2 (0.3) */
+    float proxy_kappa;     /* cell footprint = kappa-sigma box of the projected proxy (1.0) */
+    float bg[3];           /* colour of pixels no Gaussian reaches (0, 0, 0) */
+} dgs_render_opts;
+
+/* Output image, caller-owned device buffers, row-major. */
+typedef struct {
+    float* color;      /* [3][H][W] */
+    float* weight_sum; /* [H][W] D = sum_n w_n sum_k alpha (Duplex) or 1 - T (alpha), nullable */
+    float* final_T;    /* [H][W] transmittance behind the last blended cell, nullable */
+    int32_t* last;     /* [H][W] 1 + tile-list position of the last contributing entry (0 = none), nullable */
+} dgs_image;
+
+typedef struct {
+    int64_t num_keys;      /* (tile, primitive) keys of the last render */
+    int64_t key_capacity;  /* reserved key capacity */
+    int64_t n_val;         /* sum over pixels of N^val (DGS_FLAG_STATS renders only) */
+    int64_t n_rendered;    /* sum over pixels of N^rendered (DGS_FLAG_STATS renders only) */
+    int32_t device_error;  /* dgs_status of the last device-side error, 0 if none */
+    int32_t sort_passes;   /* radix passes of the last sort */
+} dgs_stats;
+
+/* Fills *opts with the defaults listed above (mode Duplex, flags 0). */
+void dgs_default_opts(dgs_render_opts* opts);
+
+/* Creates a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  *out receives the handle. */
+dgs_status dgs_create(int device, void* hip_stream, dgs_ctx* out);
+
+/* Waits for the context's work and frees everything it owns. */
+dgs_status dgs_destroy(dgs_ctx ctx);
+
+/* Changes the stream later calls enqueue on. */
+dgs_status dgs_set_stream(dgs_ctx ctx, void* hip_stream);
+
+/* Sizes the workspace for up to max_keys (tile, primitive) keys,
+ * max_prims cells or Gaussians and max_tiles screen tiles.  Allocates (and
+ * synchronises) only when growing.  Render grows prims/tiles by itself;
+ * the key capacity only grows here, so call it before graph capture. */
+dgs_status dgs_reserve(dgs_ctx ctx, int64_t max_keys, int64_t max_prims, int64_t max_tiles);
+
+/* Renders one frame: all of Sec. IV-B, V-A, V-B and VI-A for DGS_MODE_DUPLEX,
+ * per-Gaussian alpha blending for DGS_MODE_ALPHA.  opts may be NULL
+ * (defaults).  The context keeps this frame's sorted lists, projected
+ * Gaussians and per-pixel state until its next render (used by
+ * dgs_render_backward and the dgs_read_* calls). */
+dgs_status dgs_render(dgs_ctx ctx, const dgs_scene* scene, const dgs_camera* cam, const dgs_render_opts* opts,
+                      const dgs_image* out);
+
+/* Waits for the context's stream; returns the first device-side error since
+ * the previous dgs_sync (DGS_ERR_CAPACITY, DGS_ERR_TIMEOUT) or DGS_OK. */
+dgs_status dgs_sync(dgs_ctx ctx);
+
+/* Synchronises and reports the counters of the last render. */
+dgs_status dgs_get_stats(dgs_ctx ctx, dgs_stats* out);
+
+/* Message of the last host-side error of this context (never NULL). */
+const char* dgs_last_error(dgs_ctx ctx);
+
+/* Introspection of the last render, for parity checks and tools.
+ * Copies (asynchronously) the sorted keys (u64: tile << 32 | depth bits),
+ * sorted values (u32 primitive ids) and per-tile [start, end) ranges (u32
+ * pairs) into caller buffers; any pointer may be NULL.  Buffers must hold
+ * num_keys / num_keys / 2*tiles entries (num_keys from dgs_get_stats). */
+dgs_status dgs_read_lists(dgs_ctx ctx, uint64_t* keys, uint32_t* values, uint32_t* ranges);
+
+/* Copies per-primitive discrete results of the last render: for cells
+ * (Duplex) or Gaussians (alpha mode), the inclusive pixel rectangle
+ * x0,x1,y0,y1 as int32 [P][4] (-1 when culled), the depth key bits [P] and
+ * the tile count [P].  Any pointer may be NULL. */
+dgs_status dgs_read_prims(dgs_ctx ctx, int32_t* rect, uint32_t* depth_bits, uint32_t* ntiles);
+
+/* Copies the inclusive pixel rectangles of all M Gaussians of the last
+ * render ([M][4] int32, -1 when culled or not projected). */
+dgs_status dgs_read_gauss_rects(dgs_ctx ctx, int32_t* rect);
+
+/* Stage timing.  While enabled, every render records HIP events on the
+ * context stream at the boundaries of its stages:
+ *   0 cell preprocess (or nothing in alpha mode), 1 Gaussian projection,
+ *   2 scan + key emission, 3 radix sort, 4 tile ranges, 5 compositor. */
+#define DGS_NUM_STAGES 6
+dgs_status dgs_set_timing(dgs_ctx ctx, int32_t enable);
+
+/* Synchronises; writes the summed milliseconds of each stage over the renders
+ * timed since the previous call into ms[0..n_stages-1] (host array) and their
+ * number into *frames (host), then starts a new tally. */
+dgs_status dgs_get_timing(dgs_ctx ctx, float* ms, int32_t n_stages, int32_t* frames);
+
+/* Stable in-place sort of n (key, value) pairs on the low key_bits bits
+ * (1..64) with the library's onesweep radix sort.  keys/values are device
+ * buffers of n entries. */
+dgs_status dgs_sort_pairs(dgs_ctx ctx, uint64_t* keys, uint32_t* values, int64_t n, int32_t key_bits);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DUPLEXGS_H */

@@ -1,0 +1,188 @@
+"""ctypes binding of include/duplexgs.h (argument marshalling only).
+
+The functions keep the C names.  Loading fails loudly when the HIP library
+has not been built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libduplexgs.so")
+
+DGS_OK = 0
+DGS_ERR_INVALID_ARG = 1
+DGS_ERR_OOM = 2
+DGS_ERR_CAPACITY = 3
+DGS_ERR_DEVICE = 4
+DGS_ERR_UNSUPPORTED = 5
+DGS_ERR_TIMEOUT = 6
+STATUS_NAMES = {0: "DGS_OK", 1: "DGS_ERR_INVALID_ARG", 2: "DGS_ERR_OOM", 3: "DGS_ERR_CAPACITY",
+                4: "DGS_ERR_DEVICE", 5: "DGS_ERR_UNSUPPORTED", 6: "DGS_ERR_TIMEOUT"}
+
+DGS_MODE_DUPLEX = 0
+DGS_MODE_ALPHA = 1
+DGS_FLAG_V_ONE = 1
+DGS_FLAG_NO_ET = 2
+DGS_FLAG_STATS = 4
+
+
+class dgs_scene(C.Structure):
+    _fields_ = [("num_cells", C.c_int32), ("gaussians_per_cell", C.c_int32),
+                ("cell_pos", C.c_void_p), ("cell_scale", C.c_void_p), ("cell_rot", C.c_void_p),
+                ("cell_v_sh", C.c_void_p), ("v_sh_degree", C.c_int32),
+                ("means", C.c_void_p), ("scales", C.c_void_p), ("rots", C.c_void_p),
+                ("opacities", C.c_void_p), ("sh", C.c_void_p), ("sh_degree", C.c_int32)]
+
+
+class dgs_camera(C.Structure):
+    _fields_ = [("viewmat", C.c_float * 16), ("fx", C.c_float), ("fy", C.c_float), ("cx", C.c_float),
+                ("cy", C.c_float), ("width", C.c_int32), ("height", C.c_int32), ("z_near", C.c_float)]
+
+
+class dgs_render_opts(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("flags", C.c_uint32), ("eps_T", C.c_float), ("alpha_min", C.c_float),
+                ("alpha_max", C.c_float), ("cov2d_dilation", C.c_float), ("proxy_kappa", C.c_float),
+                ("bg", C.c_float * 3)]
+
+
+class dgs_image(C.Structure):
+    _fields_ = [("color", C.c_void_p), ("weight_sum", C.c_void_p), ("final_T", C.c_void_p), ("last", C.c_void_p)]
+
+
+class dgs_stats(C.Structure):
+    _fields_ = [("num_keys", C.c_int64), ("key_capacity", C.c_int64), ("n_val", C.c_int64),
+                ("n_rendered", C.c_int64), ("device_error", C.c_int32), ("sort_passes", C.c_int32)]
+
+
+dgs_ctx = C.c_void_p
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "dgs_default_opts": (None, [C.POINTER(dgs_render_opts)]),
+    "dgs_create": (C.c_int, [C.c_int, C.c_void_p, C.POINTER(dgs_ctx)]),
+    "dgs_destroy": (C.c_int, [dgs_ctx]),
+    "dgs_set_stream": (C.c_int, [dgs_ctx, C.c_void_p]),
+    "dgs_reserve": (C.c_int, [dgs_ctx, C.c_int64, C.c_int64, C.c_int64]),
+    "dgs_render": (C.c_int, [dgs_ctx, C.POINTER(dgs_scene), C.POINTER(dgs_camera), C.POINTER(dgs_render_opts),
+                             C.POINTER(dgs_image)]),
+    "dgs_sync": (C.c_int, [dgs_ctx]),
+    "dgs_get_stats": (C.c_int, [dgs_ctx, C.POINTER(dgs_stats)]),
+    "dgs_last_error": (C.c_char_p, [dgs_ctx]),
+    "dgs_read_lists": (C.c_int, [dgs_ctx, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "dgs_read_prims": (C.c_int, [dgs_ctx, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "dgs_read_gauss_rects": (C.c_int, [dgs_ctx, C.c_void_p]),
+    "dgs_sort_pairs": (C.c_int, [dgs_ctx, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32]),
+    "dgs_set_timing": (C.c_int, [dgs_ctx, C.c_int32]),
+    "dgs_get_timing": (C.c_int, [dgs_ctx, C.POINTER(C.c_float), C.c_int32, C.POINTER(C.c_int32)]),
+}
+
+DGS_NUM_STAGES = 6
+STAGE_NAMES = ["cell_preprocess", "gauss_project", "scan_emit", "radix_sort", "tile_ranges", "composite"]
+
+_lib = None
+
+
+def lib():
+    """The loaded libduplexgs.so; raises if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build() "
+                               "(python -m paper_2508_03180_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_names():
+    return list(_SIGS)
+
+
+class DgsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def check(status, ctx=None):
+    if status != DGS_OK:
+        msg = lib().dgs_last_error(ctx).decode() if ctx else ""
+        raise DgsError(status, msg)
+    return status
+
+
+# C names, re-exported
+def dgs_default_opts(opts):
+    lib().dgs_default_opts(C.byref(opts))
+
+
+def dgs_create(device, stream):
+    h = dgs_ctx()
+    check(lib().dgs_create(int(device), C.c_void_p(stream), C.byref(h)))
+    return h
+
+
+def dgs_destroy(ctx):
+    return lib().dgs_destroy(ctx)
+
+
+def dgs_set_stream(ctx, stream):
+    return check(lib().dgs_set_stream(ctx, C.c_void_p(stream)), ctx)
+
+
+def dgs_reserve(ctx, max_keys, max_prims, max_tiles):
+    return check(lib().dgs_reserve(ctx, int(max_keys), int(max_prims), int(max_tiles)), ctx)
+
+
+def dgs_render(ctx, scene, cam, opts, image):
+    return lib().dgs_render(ctx, C.byref(scene), C.byref(cam), C.byref(opts), C.byref(image))
+
+
+def dgs_sync(ctx):
+    return lib().dgs_sync(ctx)
+
+
+def dgs_get_stats(ctx):
+    s = dgs_stats()
+    check(lib().dgs_get_stats(ctx, C.byref(s)), ctx)
+    return s
+
+
+def dgs_last_error(ctx):
+    return lib().dgs_last_error(ctx).decode()
+
+
+def dgs_read_lists(ctx, keys_ptr, values_ptr, ranges_ptr):
+    return check(lib().dgs_read_lists(ctx, C.c_void_p(keys_ptr), C.c_void_p(values_ptr),
+                                      C.c_void_p(ranges_ptr)), ctx)
+
+
+def dgs_read_prims(ctx, rect_ptr, depth_ptr, ntiles_ptr):
+    return check(lib().dgs_read_prims(ctx, C.c_void_p(rect_ptr), C.c_void_p(depth_ptr), C.c_void_p(ntiles_ptr)),
+                 ctx)
+
+
+def dgs_read_gauss_rects(ctx, rect_ptr):
+    return check(lib().dgs_read_gauss_rects(ctx, C.c_void_p(rect_ptr)), ctx)
+
+
+def dgs_sort_pairs(ctx, keys_ptr, values_ptr, n, key_bits):
+    return check(lib().dgs_sort_pairs(ctx, C.c_void_p(keys_ptr), C.c_void_p(values_ptr), int(n), int(key_bits)),
+                 ctx)
+
+
+def dgs_set_timing(ctx, enable):
+    return check(lib().dgs_set_timing(ctx, int(bool(enable))), ctx)
+
+
+def dgs_get_timing(ctx):
+    ms = (C.c_float * DGS_NUM_STAGES)()
+    frames = C.c_int32()
+    check(lib().dgs_get_timing(ctx, ms, DGS_NUM_STAGES, C.byref(frames)), ctx)
+    return list(ms), frames.value

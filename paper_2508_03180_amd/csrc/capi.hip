@@ -1,0 +1,480 @@
+// C ABI of the renderer: context, workspace and the per-frame pipeline.
+#include <math.h>
+#include <string.h>
+
+#include <array>
+#include <string>
+#include <vector>
+
+#include "../../include/duplexgs.h"
+#include "common.h"
+#include "launch.h"
+
+using namespace dgs;
+
+struct dgs_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    int64_t cap_prims = 0, cap_gauss = 0, cap_keys = 0, cap_tiles = 0;
+    uint32_t *p_depth = nullptr, *p_ntiles = nullptr, *p_offsets = nullptr;
+    uint64_t* p_rect = nullptr;
+    float* cell_v = nullptr;
+    GRec* recs = nullptr;
+    uint64_t* grect = nullptr;
+    uint64_t *keys0 = nullptr, *keys1 = nullptr;
+    uint32_t *vals0 = nullptr, *vals1 = nullptr;
+    uint32_t* ranges = nullptr;
+    uint32_t* scan_status = nullptr;
+    size_t scan_status_cap = 0;
+    uint32_t* sort_status = nullptr;
+    size_t sort_status_cap = 0;
+    uint32_t* hist = nullptr;     // [8][256]
+    uint32_t* misc = nullptr;     // [0] key total, [1] scan ticket, [2..9] sort tickets, [10] sort count
+    int* dev_err = nullptr;
+    unsigned long long* counters = nullptr;  // n_val, n_rendered
+
+    // last frame
+    int last_mode = -1, last_passes = 0;
+    int64_t last_prims = 0, last_gauss = 0, last_tiles = 0;
+    bool last_in_1 = false;
+
+    // stage timing
+    bool timing = false;
+    std::vector<std::array<hipEvent_t, DGS_NUM_STAGES + 1>> events;
+    size_t events_used = 0;
+};
+
+namespace {
+
+dgs_status fail(dgs_ctx c, dgs_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+template <class T>
+hipError_t grow(T*& p, int64_t want, hipStream_t st) {
+    if (p) {
+        hipStreamSynchronize(st);
+        hipFree(p);
+        p = nullptr;
+    }
+    return hipMalloc((void**)&p, sizeof(T) * (size_t)(want > 0 ? want : 1));
+}
+
+dgs_status ensure(dgs_ctx c, int64_t prims, int64_t gauss, int64_t keys, int64_t tiles) {
+    hipError_t e = hipSuccess;
+    if (prims > c->cap_prims) {
+        prims = prims + prims / 4;
+        if ((e = grow(c->p_depth, prims, c->stream)) != hipSuccess) goto oom;
+        if ((e = grow(c->p_ntiles, prims, c->stream)) != hipSuccess) goto oom;
+        if ((e = grow(c->p_offsets, prims, c->stream)) != hipSuccess) goto oom;
+        if ((e = grow(c->p_rect, prims, c->stream)) != hipSuccess) goto oom;
+        if ((e = grow(c->cell_v, prims, c->stream)) != hipSuccess) goto oom;
+        size_t sw = scan_status_words(prims);
+        if ((e = grow(c->scan_status, (int64_t)sw, c->stream)) != hipSuccess) goto oom;
+        c->scan_status_cap = sw;
+        c->cap_prims = prims;
+    }
+    if (gauss > c->cap_gauss) {
+        gauss = gauss + gauss / 4;
+        if ((e = grow(c->recs, gauss, c->stream)) != hipSuccess) goto oom;
+        if ((e = grow(c->grect, gauss, c->stream)) != hipSuccess) goto oom;
+        c->cap_gauss = gauss;
+    }
+    if (keys > c->cap_keys) {
+        if (keys > (int64_t)(1u << 30)) return fail(c, DGS_ERR_INVALID_ARG, "key capacity above 2^30");
+        if ((e = grow(c->keys0, keys, c->stream)) != hipSuccess) goto oom;
+        if ((e = grow(c->keys1, keys, c->stream)) != hipSuccess) goto oom;
+        if ((e = grow(c->vals0, keys, c->stream)) != hipSuccess) goto oom;
+        if ((e = grow(c->vals1, keys, c->stream)) != hipSuccess) goto oom;
+        size_t sw = sort_status_words(keys, 8);
+        if ((e = grow(c->sort_status, (int64_t)sw, c->stream)) != hipSuccess) goto oom;
+        c->sort_status_cap = sw;
+        c->cap_keys = keys;
+    }
+    if (tiles > c->cap_tiles) {
+        if ((e = grow(c->ranges, 2 * tiles, c->stream)) != hipSuccess) goto oom;
+        c->cap_tiles = tiles;
+    }
+    return DGS_OK;
+oom:
+    return fail(c, DGS_ERR_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+}
+
+bool finite_f(float x) { return x == x && x > -INFINITY && x < INFINITY; }
+
+dgs_status make_cam(dgs_ctx c, const dgs_camera* cam, CamK& k) {
+    if (!cam) return fail(c, DGS_ERR_INVALID_ARG, "camera is NULL");
+    if (cam->width < 1 || cam->height < 1 || cam->width > 32767 || cam->height > 32767)
+        return fail(c, DGS_ERR_INVALID_ARG, "image size must be in 1..32767");
+    for (int i = 0; i < 16; i++)
+        if (!finite_f(cam->viewmat[i])) return fail(c, DGS_ERR_INVALID_ARG, "viewmat is not finite");
+    if (!(cam->fx > 0) || !(cam->fy > 0) || !finite_f(cam->fx) || !finite_f(cam->fy) || !finite_f(cam->cx) ||
+        !finite_f(cam->cy))
+        return fail(c, DGS_ERR_INVALID_ARG, "focal lengths must be finite and > 0");
+    if (!(cam->z_near > 0) || !finite_f(cam->z_near)) return fail(c, DGS_ERR_INVALID_ARG, "z_near must be > 0");
+    for (int i = 0; i < 3; i++) {
+        for (int j = 0; j < 3; j++) {
+            k.R[i * 3 + j] = cam->viewmat[i * 4 + j];
+            k.Rd[i * 3 + j] = cam->viewmat[i * 4 + j];
+        }
+        k.t[i] = cam->viewmat[i * 4 + 3];
+        k.td[i] = cam->viewmat[i * 4 + 3];
+    }
+    for (int j = 0; j < 3; j++)
+        k.o[j] = (float)(-(k.Rd[0 * 3 + j] * k.td[0] + k.Rd[1 * 3 + j] * k.td[1] + k.Rd[2 * 3 + j] * k.td[2]));
+    k.fx = cam->fx; k.fy = cam->fy; k.cx = cam->cx; k.cy = cam->cy;
+    k.znear = cam->z_near;
+    k.W = cam->width; k.H = cam->height;
+    k.TX = (k.W + kTile - 1) / kTile;
+    k.TY = (k.H + kTile - 1) / kTile;
+    return DGS_OK;
+}
+
+dgs_status make_opts(dgs_ctx c, const dgs_render_opts* in, OptK& o, int& mode) {
+    dgs_render_opts d;
+    dgs_default_opts(&d);
+    const dgs_render_opts& p = in ? *in : d;
+    if (p.mode != DGS_MODE_DUPLEX && p.mode != DGS_MODE_ALPHA) return fail(c, DGS_ERR_INVALID_ARG, "unknown mode");
+    if (!(p.alpha_min > 0) || !(p.alpha_max > 0) || !(p.alpha_max <= 1.0f) || !(p.eps_T >= 0) ||
+        !(p.cov2d_dilation >= 0) || !(p.proxy_kappa > 0))
+        return fail(c, DGS_ERR_INVALID_ARG, "render options out of range");
+    mode = p.mode;
+    o.eps = p.eps_T;
+    o.alpha_max = p.alpha_max;
+    o.log2_alpha_min = log2f(p.alpha_min);
+    o.delta = p.cov2d_dilation;
+    o.kappa = p.proxy_kappa;
+    for (int i = 0; i < 3; i++) o.bg[i] = p.bg[i];
+    o.v_one = (p.flags & DGS_FLAG_V_ONE) != 0;
+    o.no_et = (p.flags & DGS_FLAG_NO_ET) != 0;
+    o.stats = (p.flags & DGS_FLAG_STATS) != 0;
+    return DGS_OK;
+}
+
+dgs_status check_scene(dgs_ctx c, const dgs_scene* s, int mode) {
+    if (!s) return fail(c, DGS_ERR_INVALID_ARG, "scene is NULL");
+    if (s->num_cells < 0) return fail(c, DGS_ERR_INVALID_ARG, "num_cells < 0");
+    if (s->gaussians_per_cell < 1 || s->gaussians_per_cell > kMaxK)
+        return fail(c, DGS_ERR_INVALID_ARG, "gaussians_per_cell must be in 1..32");
+    if ((int64_t)s->num_cells * s->gaussians_per_cell > (int64_t)(1 << 30))
+        return fail(c, DGS_ERR_INVALID_ARG, "too many Gaussians");
+    if (s->sh_degree < 0 || s->sh_degree > 3 || s->v_sh_degree < 0 || s->v_sh_degree > 3)
+        return fail(c, DGS_ERR_INVALID_ARG, "SH degree must be in 0..3");
+    if (s->num_cells == 0) return DGS_OK;
+    if (!s->means || !s->scales || !s->rots || !s->opacities || !s->sh)
+        return fail(c, DGS_ERR_INVALID_ARG, "Gaussian arrays must not be NULL");
+    if (mode == DGS_MODE_DUPLEX && (!s->cell_pos || !s->cell_scale || !s->cell_rot || !s->cell_v_sh))
+        return fail(c, DGS_ERR_INVALID_ARG, "cell arrays must not be NULL");
+    return DGS_OK;
+}
+
+int tile_bits(int tiles) {
+    int b = 0;
+    while ((1 << b) < tiles) b++;
+    return b;
+}
+
+dgs_status launched(dgs_ctx c) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(c, DGS_ERR_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    return DGS_OK;
+}
+
+// Event marking the start of stage `i` (i == DGS_NUM_STAGES: end of frame).
+struct StageMarks {
+    dgs_ctx c;
+    std::array<hipEvent_t, DGS_NUM_STAGES + 1>* ev = nullptr;
+    explicit StageMarks(dgs_ctx ctx) : c(ctx) {
+        if (!c->timing) return;
+        if (c->events_used == c->events.size()) {
+            std::array<hipEvent_t, DGS_NUM_STAGES + 1> a;
+            for (auto& e : a) hipEventCreate(&e);
+            c->events.push_back(a);
+        }
+        ev = &c->events[c->events_used++];
+    }
+    void mark(int i) {
+        if (ev) hipEventRecord((*ev)[i], c->stream);
+    }
+};
+
+__global__ void k_unpack_rects(const uint64_t* in, int64_t n, int32_t* out) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t r = in[i];
+    if (r == kEmptyRect) {
+        out[4 * i] = out[4 * i + 1] = out[4 * i + 2] = out[4 * i + 3] = -1;
+    } else {
+        out[4 * i] = rect_x0(r); out[4 * i + 1] = rect_x1(r);
+        out[4 * i + 2] = rect_y0(r); out[4 * i + 3] = rect_y1(r);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+void dgs_default_opts(dgs_render_opts* o) {
+    if (!o) return;
+    o->mode = DGS_MODE_DUPLEX;
+    o->flags = 0;
+    o->eps_T = 1e-4f;
+    o->alpha_min = 1.0f / 255.0f;
+    o->alpha_max = 0.99f;
+    o->cov2d_dilation = 0.3f;
+    o->proxy_kappa = 1.0f;
+    o->bg[0] = o->bg[1] = o->bg[2] = 0.0f;
+}
+
+dgs_status dgs_create(int device, void* hip_stream, dgs_ctx* out) {
+    if (!out) return DGS_ERR_INVALID_ARG;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return DGS_ERR_INVALID_ARG;
+    if (hipSetDevice(device) != hipSuccess) return DGS_ERR_DEVICE;
+    dgs_ctx c = new dgs_ctx_s();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    if (hipMalloc((void**)&c->hist, 8 * 256 * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc((void**)&c->misc, 16 * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc((void**)&c->dev_err, sizeof(int)) != hipSuccess ||
+        hipMalloc((void**)&c->counters, 2 * sizeof(unsigned long long)) != hipSuccess) {
+        dgs_destroy(c);
+        return DGS_ERR_OOM;
+    }
+    hipMemsetAsync(c->misc, 0, 16 * sizeof(uint32_t), c->stream);
+    hipMemsetAsync(c->dev_err, 0, sizeof(int), c->stream);
+    hipMemsetAsync(c->counters, 0, 2 * sizeof(unsigned long long), c->stream);
+    hipStreamSynchronize(c->stream);
+    *out = c;
+    return DGS_OK;
+}
+
+dgs_status dgs_destroy(dgs_ctx c) {
+    if (!c) return DGS_ERR_INVALID_ARG;
+    hipSetDevice(c->device);
+    hipStreamSynchronize(c->stream);
+    for (auto& a : c->events)
+        for (auto& e : a) hipEventDestroy(e);
+    void* ptrs[] = {c->p_depth, c->p_ntiles, c->p_offsets, c->p_rect, c->cell_v, c->recs, c->grect,
+                    c->keys0, c->keys1, c->vals0, c->vals1, c->ranges, c->scan_status, c->sort_status,
+                    c->hist, c->misc, c->dev_err, c->counters};
+    for (void* p : ptrs)
+        if (p) hipFree(p);
+    delete c;
+    return DGS_OK;
+}
+
+dgs_status dgs_set_stream(dgs_ctx c, void* hip_stream) {
+    if (!c) return DGS_ERR_INVALID_ARG;
+    c->stream = (hipStream_t)hip_stream;
+    return DGS_OK;
+}
+
+dgs_status dgs_reserve(dgs_ctx c, int64_t max_keys, int64_t max_prims, int64_t max_tiles) {
+    if (!c) return DGS_ERR_INVALID_ARG;
+    if (max_keys < 0 || max_prims < 0 || max_tiles < 0) return fail(c, DGS_ERR_INVALID_ARG, "negative size");
+    hipSetDevice(c->device);
+    return ensure(c, max_prims, max_prims, max_keys, max_tiles);
+}
+
+dgs_status dgs_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* cam, const dgs_render_opts* opts,
+                      const dgs_image* out) {
+    if (!c) return DGS_ERR_INVALID_ARG;
+    CamK k;
+    OptK o;
+    int mode = 0;
+    dgs_status st;
+    if ((st = make_cam(c, cam, k)) != DGS_OK) return st;
+    if ((st = make_opts(c, opts, o, mode)) != DGS_OK) return st;
+    if ((st = check_scene(c, s, mode)) != DGS_OK) return st;
+    if (!out || !out->color) return fail(c, DGS_ERR_INVALID_ARG, "output color buffer is NULL");
+    hipSetDevice(c->device);
+    const int N = s->num_cells, K = s->gaussians_per_cell;
+    const int M = N * K;
+    const int tiles = k.TX * k.TY;
+    const int P = mode == DGS_MODE_DUPLEX ? N : M;
+    int64_t want_keys = c->cap_keys;
+    if (want_keys == 0) want_keys = (int64_t)P * 8 > (1 << 20) ? (int64_t)P * 8 : (1 << 20);
+    if ((st = ensure(c, P, M, want_keys, tiles)) != DGS_OK) return st;
+    const uint32_t cap = (uint32_t)c->cap_keys;
+    hipStream_t q = c->stream;
+
+    StageMarks sm(c);
+    if (o.stats) launch_fill_u32(q, (uint32_t*)c->counters, 0u, 4);
+    sm.mark(0);
+    if (mode == DGS_MODE_DUPLEX) {
+        launch_cell_preprocess(q, N, s->cell_pos, s->cell_scale, s->cell_rot, s->cell_v_sh, s->v_sh_degree, k, o,
+                               c->p_depth, c->p_rect, c->p_ntiles, c->cell_v);
+        sm.mark(1);
+        launch_gauss_project(q, M, K, s->means, s->scales, s->rots, s->opacities, s->sh, s->sh_degree, k, o,
+                             c->p_ntiles, c->recs, c->grect, nullptr, nullptr);
+    } else {
+        sm.mark(1);
+        launch_gauss_project(q, M, K, s->means, s->scales, s->rots, s->opacities, s->sh, s->sh_degree, k, o,
+                             nullptr, c->recs, c->grect, c->p_depth, c->p_ntiles);
+    }
+    sm.mark(2);
+    const uint64_t* prect = mode == DGS_MODE_DUPLEX ? c->p_rect : c->grect;
+    launch_exclusive_scan(q, c->p_ntiles, c->p_offsets, P, c->misc + 0, c->scan_status, c->misc + 1, c->dev_err);
+    launch_emit_keys(q, P, c->p_ntiles, c->p_offsets, prect, c->p_depth, k.TX, cap, c->keys0, c->vals0, c->dev_err);
+    sm.mark(3);
+    SortScratch ss{c->hist, c->sort_status, c->misc + 2};
+    const int bits = 32 + tile_bits(tiles);
+    const bool in1 = launch_radix_sort(q, c->keys0, c->vals0, c->keys1, c->vals1, c->misc + 0, cap, bits, ss,
+                                       c->dev_err);
+    const uint64_t* skeys = in1 ? c->keys1 : c->keys0;
+    const uint32_t* svals = in1 ? c->vals1 : c->vals0;
+    sm.mark(4);
+    launch_tile_ranges(q, skeys, c->misc + 0, cap, c->ranges, tiles);
+    sm.mark(5);
+    CompositeArgs a;
+    a.ranges = c->ranges;
+    a.vals = svals;
+    a.recs = c->recs;
+    a.cell_v = c->cell_v;
+    a.K = K;
+    a.k = k;
+    a.o = o;
+    a.color = out->color;
+    a.D = out->weight_sum;
+    a.T = out->final_T;
+    a.last = out->last;
+    a.counters = o.stats ? c->counters : nullptr;
+    if (mode == DGS_MODE_DUPLEX)
+        launch_composite_duplex(q, a);
+    else
+        launch_composite_alpha(q, a);
+    sm.mark(6);
+    c->last_mode = mode;
+    c->last_passes = sort_passes(bits);
+    c->last_prims = P;
+    c->last_gauss = M;
+    c->last_tiles = tiles;
+    c->last_in_1 = in1;
+    return launched(c);
+}
+
+dgs_status dgs_sync(dgs_ctx c) {
+    if (!c) return DGS_ERR_INVALID_ARG;
+    hipSetDevice(c->device);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, DGS_ERR_DEVICE, "stream synchronize failed");
+    int e = 0;
+    if (hipMemcpy(&e, c->dev_err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(c, DGS_ERR_DEVICE, "error flag readback failed");
+    if (e) {
+        hipMemset(c->dev_err, 0, sizeof(int));
+        if (e & (1 << kErrTimeout)) return fail(c, DGS_ERR_TIMEOUT, "device look-back wait timed out");
+        if (e & (1 << kErrCapacity)) return fail(c, DGS_ERR_CAPACITY, "key capacity exceeded; reserve more keys");
+        return fail(c, DGS_ERR_DEVICE, "device error flag set");
+    }
+    return DGS_OK;
+}
+
+dgs_status dgs_get_stats(dgs_ctx c, dgs_stats* out) {
+    if (!c || !out) return DGS_ERR_INVALID_ARG;
+    hipSetDevice(c->device);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, DGS_ERR_DEVICE, "stream synchronize failed");
+    uint32_t total = 0;
+    unsigned long long cnt[2] = {0, 0};
+    int e = 0;
+    hipMemcpy(&total, c->misc, sizeof(uint32_t), hipMemcpyDeviceToHost);
+    hipMemcpy(cnt, c->counters, sizeof(cnt), hipMemcpyDeviceToHost);
+    hipMemcpy(&e, c->dev_err, sizeof(int), hipMemcpyDeviceToHost);
+    out->num_keys = total;
+    out->key_capacity = c->cap_keys;
+    out->n_val = (int64_t)cnt[0];
+    out->n_rendered = (int64_t)cnt[1];
+    out->device_error = (e & (1 << kErrTimeout)) ? DGS_ERR_TIMEOUT : (e & (1 << kErrCapacity)) ? DGS_ERR_CAPACITY : 0;
+    out->sort_passes = c->last_passes;
+    return DGS_OK;
+}
+
+const char* dgs_last_error(dgs_ctx c) { return c ? c->err.c_str() : "invalid context"; }
+
+dgs_status dgs_read_lists(dgs_ctx c, uint64_t* keys, uint32_t* values, uint32_t* ranges) {
+    if (!c) return DGS_ERR_INVALID_ARG;
+    if (c->last_mode < 0) return fail(c, DGS_ERR_INVALID_ARG, "no frame rendered yet");
+    hipSetDevice(c->device);
+    hipStreamSynchronize(c->stream);
+    uint32_t total = 0;
+    hipMemcpy(&total, c->misc, sizeof(uint32_t), hipMemcpyDeviceToHost);
+    if ((int64_t)total > c->cap_keys) total = (uint32_t)c->cap_keys;
+    const uint64_t* sk = c->last_in_1 ? c->keys1 : c->keys0;
+    const uint32_t* sv = c->last_in_1 ? c->vals1 : c->vals0;
+    if (keys && total) hipMemcpyAsync(keys, sk, total * sizeof(uint64_t), hipMemcpyDeviceToDevice, c->stream);
+    if (values && total) hipMemcpyAsync(values, sv, total * sizeof(uint32_t), hipMemcpyDeviceToDevice, c->stream);
+    if (ranges)
+        hipMemcpyAsync(ranges, c->ranges, 2 * c->last_tiles * sizeof(uint32_t), hipMemcpyDeviceToDevice, c->stream);
+    return launched(c);
+}
+
+dgs_status dgs_read_prims(dgs_ctx c, int32_t* rect, uint32_t* depth_bits, uint32_t* ntiles) {
+    if (!c) return DGS_ERR_INVALID_ARG;
+    if (c->last_mode < 0) return fail(c, DGS_ERR_INVALID_ARG, "no frame rendered yet");
+    hipSetDevice(c->device);
+    const int64_t P = c->last_prims;
+    if (P == 0) return DGS_OK;
+    const uint64_t* pr = c->last_mode == DGS_MODE_DUPLEX ? c->p_rect : c->grect;
+    if (rect) hipLaunchKernelGGL(k_unpack_rects, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, c->stream, pr, P, rect);
+    if (depth_bits) hipMemcpyAsync(depth_bits, c->p_depth, P * sizeof(uint32_t), hipMemcpyDeviceToDevice, c->stream);
+    if (ntiles) hipMemcpyAsync(ntiles, c->p_ntiles, P * sizeof(uint32_t), hipMemcpyDeviceToDevice, c->stream);
+    return launched(c);
+}
+
+dgs_status dgs_read_gauss_rects(dgs_ctx c, int32_t* rect) {
+    if (!c || !rect) return DGS_ERR_INVALID_ARG;
+    if (c->last_mode < 0) return fail(c, DGS_ERR_INVALID_ARG, "no frame rendered yet");
+    hipSetDevice(c->device);
+    const int64_t M = c->last_gauss;
+    if (M == 0) return DGS_OK;
+    hipLaunchKernelGGL(k_unpack_rects, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, c->stream, c->grect, M, rect);
+    return launched(c);
+}
+
+dgs_status dgs_set_timing(dgs_ctx c, int32_t enable) {
+    if (!c) return DGS_ERR_INVALID_ARG;
+    c->timing = enable != 0;
+    return DGS_OK;
+}
+
+dgs_status dgs_get_timing(dgs_ctx c, float* ms, int32_t n_stages, int32_t* frames) {
+    if (!c || !ms || n_stages < 0 || n_stages > DGS_NUM_STAGES) return DGS_ERR_INVALID_ARG;
+    hipSetDevice(c->device);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, DGS_ERR_DEVICE, "stream synchronize failed");
+    for (int i = 0; i < n_stages; i++) ms[i] = 0.0f;
+    for (size_t f = 0; f < c->events_used; f++) {
+        auto& ev = c->events[f];
+        for (int i = 0; i < n_stages; i++) {
+            float t = 0.0f;
+            if (hipEventElapsedTime(&t, ev[i], ev[i + 1]) == hipSuccess) ms[i] += t;
+        }
+    }
+    if (frames) *frames = (int32_t)c->events_used;
+    c->events_used = 0;
+    return DGS_OK;
+}
+
+dgs_status dgs_sort_pairs(dgs_ctx c, uint64_t* keys, uint32_t* values, int64_t n, int32_t key_bits) {
+    if (!c) return DGS_ERR_INVALID_ARG;
+    if (n < 0 || key_bits < 1 || key_bits > 64) return fail(c, DGS_ERR_INVALID_ARG, "bad n or key_bits");
+    if (n == 0) return DGS_OK;
+    if (!keys || !values) return fail(c, DGS_ERR_INVALID_ARG, "NULL buffer");
+    hipSetDevice(c->device);
+    dgs_status st;
+    if ((st = ensure(c, 0, 0, n, 0)) != DGS_OK) return st;
+    launch_fill_u32(c->stream, c->misc + 10, (uint32_t)n, 1);
+    SortScratch ss{c->hist, c->sort_status, c->misc + 2};
+    const bool in1 = launch_radix_sort(c->stream, keys, values, c->keys1, c->vals1, c->misc + 10, (uint32_t)n,
+                                       key_bits, ss, c->dev_err);
+    if (in1) {
+        hipMemcpyAsync(keys, c->keys1, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, c->stream);
+        hipMemcpyAsync(values, c->vals1, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, c->stream);
+    }
+    return launched(c);
+}
+
+}  // extern "C"

@@ -1,0 +1,67 @@
+// Internal definitions shared by the HIP kernels and the C-ABI host code.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dgs {
+
+constexpr int kTile = 16;        // screen tile edge, pixels
+constexpr int kMaxK = 32;        // Gaussians per cell supported by the compositor
+constexpr int kBatchSlots = 256; // Gaussian records staged in LDS per batch
+constexpr int kXcds = 8;         // MI355X: 8 accelerator complex dies
+
+// Device-side error codes (mirror dgs_status values).
+constexpr int kErrCapacity = 3;
+constexpr int kErrTimeout = 6;
+
+// Per-frame camera constants, passed by value to kernels.
+struct CamK {
+    float R[9], t[3];     // world -> camera
+    float fx, fy, cx, cy;
+    float znear;
+    float o[3];           // camera centre, -R^T t
+    double Rd[9], td[3];  // the same rotation/translation in binary64
+    int W, H, TX, TY;
+};
+
+struct OptK {
+    float eps, alpha_max, log2_alpha_min, delta, kappa;
+    float bg[3];
+    int v_one, no_et, stats;
+};
+
+// Projected Gaussian as the compositor reads it (48 bytes).
+//   dx = (px - x0) + ox, dy = (py - y0) + oy      (pixel offset from the mean)
+//   log2(sigma G') = lo + ca dx^2 + cb dx dy + cc dy^2
+//   inside the box  <=>  (unsigned)(px - x0) <= wx  and  (unsigned)(py - y0) <= wy
+struct __align__(16) GRec {
+    float ox, oy;
+    float ca, cb, cc, lo;
+    float r, g, b;
+    int32_t x0, y0;
+    uint32_t wxy;  // wx | wy << 16 (each <= 32767); culled: x0 = y0 = 0x7fff0000, wxy = 0
+};
+static_assert(sizeof(GRec) == 48, "GRec layout");
+
+// Packed integer rectangle: x0 | x1 << 16 | y0 << 32 | y1 << 48 (each < 2^15).
+__host__ __device__ inline uint64_t pack_rect(int x0, int x1, int y0, int y1) {
+    return (uint64_t)(uint16_t)x0 | ((uint64_t)(uint16_t)x1 << 16) | ((uint64_t)(uint16_t)y0 << 32) |
+           ((uint64_t)(uint16_t)y1 << 48);
+}
+__host__ __device__ inline int rect_x0(uint64_t r) { return (int)(r & 0xffff); }
+__host__ __device__ inline int rect_x1(uint64_t r) { return (int)((r >> 16) & 0xffff); }
+__host__ __device__ inline int rect_y0(uint64_t r) { return (int)((r >> 32) & 0xffff); }
+__host__ __device__ inline int rect_y1(uint64_t r) { return (int)((r >> 48) & 0xffff); }
+constexpr uint64_t kEmptyRect = ~0ull;
+
+// Workgroups are dispatched round-robin over the XCDs (block b runs on XCD
+// b % 8).  Give each XCD one contiguous range of logical blocks so that
+// neighbouring tiles, which share cells, share that XCD's L2.
+__device__ inline int xcd_remap(int b, int nblocks) {
+    int x = b % kXcds, local = b / kXcds;
+    int per = nblocks / kXcds, rem = nblocks % kXcds;
+    int base = x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per;
+    return base + local;
+}
+
+}  // namespace dgs

@@ -1,0 +1,64 @@
+// Host-side launchers of the HIP kernels (internal to the library).
+#pragma once
+#include "common.h"
+
+namespace dgs {
+
+void launch_cell_preprocess(hipStream_t st, int N, const float* pos, const float* scale, const float* rot,
+                            const float* vsh, int vdeg, const CamK& k, const OptK& o, uint32_t* depth_bits,
+                            uint64_t* prect, uint32_t* ntiles, float* v);
+
+void launch_gauss_project(hipStream_t st, int M, int K, const float* means, const float* scales,
+                          const float* rots, const float* opac, const float* sh, int sh_deg, const CamK& k,
+                          const OptK& o, const uint32_t* cell_ntiles, GRec* recs, uint64_t* grect,
+                          uint32_t* gdepth, uint32_t* gntiles);
+
+// Exclusive scan of n u32 values; *total receives the sum.  status needs
+// scan_status_words(n) words, ticket one word; both are cleared here.
+size_t scan_status_words(int64_t n);
+void launch_exclusive_scan(hipStream_t st, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
+                           uint32_t* status, uint32_t* ticket, int* err);
+
+void launch_fill_u32(hipStream_t st, uint32_t* p, uint32_t v, size_t n);
+
+// One key per (primitive, touched tile): key = tile << 32 | depth bits,
+// value = primitive id, written at offsets[p] in row-major tile order.
+void launch_emit_keys(hipStream_t st, int P, const uint32_t* ntiles, const uint32_t* offsets,
+                      const uint64_t* prect, const uint32_t* depth, int TX, uint32_t cap, uint64_t* keys,
+                      uint32_t* vals, int* err);
+
+// [start, end) per tile of the sorted keys; ranges must hold 2*tiles words.
+void launch_tile_ranges(hipStream_t st, const uint64_t* keys, const uint32_t* n_ptr, uint32_t cap,
+                        uint32_t* ranges, int tiles);
+
+// Onesweep LSD radix sort of (u64 key, u32 value) pairs on the low `bits`
+// bits.  The count is read on the device from *n_ptr (clamped to cap).
+// Returns true when the sorted data ends in (k1, v1), false for (k0, v0).
+struct SortScratch {
+    uint32_t* hist;     // [8][256]
+    uint32_t* status;   // sort_status_words(cap)
+    uint32_t* tickets;  // [8]
+};
+int sort_passes(int bits);
+size_t sort_status_words(int64_t cap, int passes);
+bool launch_radix_sort(hipStream_t st, uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1,
+                       const uint32_t* n_ptr, uint32_t cap, int bits, const SortScratch& s, int* err);
+
+struct CompositeArgs {
+    const uint32_t* ranges;
+    const uint32_t* vals;
+    const GRec* recs;
+    const float* cell_v;  // Duplex only
+    int K;
+    CamK k;
+    OptK o;
+    float* color;
+    float* D;
+    float* T;
+    int32_t* last;
+    unsigned long long* counters;  // [2]: n_val, n_rendered (stats mode), nullable
+};
+void launch_composite_duplex(hipStream_t st, const CompositeArgs& a);
+void launch_composite_alpha(hipStream_t st, const CompositeArgs& a);
+
+}  // namespace dgs

@@ -1,0 +1,188 @@
+"""Torch-facing wrapper of the C ABI.
+
+PyTorch only provides device memory and streams here: scenes are uploaded
+once into planar device tensors, outputs are preallocated tensors, and every
+step of a frame runs in the HIP library.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _capi as capi
+
+
+def _planar(a, device):
+    """[P, ...] numpy -> planar [..., P] contiguous float32 device tensor."""
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    t = torch.as_tensor(a.reshape(a.shape[0], int(np.prod(a.shape[1:], dtype=np.int64))))
+    t = t.t().contiguous()
+    return t.to(device)
+
+
+class DeviceScene:
+    """A scene resident in device memory in the library's planar layout."""
+
+    def __init__(self, tensors, N, K, v_sh_degree, sh_degree):
+        self.t = tensors
+        self.N, self.K = int(N), int(K)
+        self.M = self.N * self.K
+        self.v_sh_degree, self.sh_degree = int(v_sh_degree), int(sh_degree)
+
+    @classmethod
+    def from_numpy(cls, scene, device="cuda"):
+        N = scene["cell_pos"].shape[0]
+        K = int(scene["K"])
+        sh = np.asarray(scene["sh"], np.float32)  # [M, C, 3] -> [C, 3, M]
+        t = dict(cell_pos=_planar(scene["cell_pos"], device), cell_scale=_planar(scene["cell_scale"], device),
+                 cell_rot=_planar(scene["cell_rot"], device), cell_v_sh=_planar(scene["cell_v_sh"], device),
+                 means=_planar(scene["means"], device), scales=_planar(scene["scales"], device),
+                 rots=_planar(scene["rots"], device),
+                 opacities=torch.as_tensor(np.ascontiguousarray(scene["opacities"], np.float32)).to(device),
+                 sh=torch.as_tensor(np.ascontiguousarray(sh.transpose(1, 2, 0))).to(device))
+        return cls(t, N, K, scene["v_sh_degree"], scene["sh_degree"])
+
+    def nbytes(self):
+        return sum(v.numel() * v.element_size() for v in self.t.values())
+
+    def struct(self):
+        s = capi.dgs_scene()
+        s.num_cells = self.N
+        s.gaussians_per_cell = self.K
+        for k in ("cell_pos", "cell_scale", "cell_rot", "cell_v_sh", "means", "scales", "rots", "opacities", "sh"):
+            setattr(s, k, self.t[k].data_ptr() if self.t[k].numel() else None)
+        s.v_sh_degree = self.v_sh_degree
+        s.sh_degree = self.sh_degree
+        return s
+
+
+def camera_struct(cam):
+    c = capi.dgs_camera()
+    V = np.asarray(cam["viewmat"], np.float32).reshape(-1)
+    for i in range(16):
+        c.viewmat[i] = float(V[i])
+    c.fx, c.fy, c.cx, c.cy = float(cam["fx"]), float(cam["fy"]), float(cam["cx"]), float(cam["cy"])
+    c.width, c.height = int(cam["width"]), int(cam["height"])
+    c.z_near = float(cam.get("z_near", 0.2))
+    return c
+
+
+def opts_struct(mode="duplex", v_one=False, no_et=False, stats=False, eps=None, alpha_min=None, alpha_max=None,
+                delta=None, kappa=None, bg=None):
+    o = capi.dgs_render_opts()
+    capi.dgs_default_opts(o)
+    o.mode = capi.DGS_MODE_DUPLEX if mode == "duplex" else capi.DGS_MODE_ALPHA
+    o.flags = (capi.DGS_FLAG_V_ONE if v_one else 0) | (capi.DGS_FLAG_NO_ET if no_et else 0) | \
+              (capi.DGS_FLAG_STATS if stats else 0)
+    if eps is not None:
+        o.eps_T = eps
+    if alpha_min is not None:
+        o.alpha_min = alpha_min
+    if alpha_max is not None:
+        o.alpha_max = alpha_max
+    if delta is not None:
+        o.cov2d_dilation = delta
+    if kappa is not None:
+        o.proxy_kappa = kappa
+    if bg is not None:
+        for i in range(3):
+            o.bg[i] = float(bg[i])
+    return o
+
+
+class Renderer:
+    """One library context bound to a device and a stream."""
+
+    def __init__(self, device=0, stream=None):
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = capi.dgs_create(self.device.index or 0, self.stream.cuda_stream)
+
+    def close(self):
+        if self.ctx:
+            capi.dgs_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reserve(self, max_keys, max_prims=0, max_tiles=0):
+        capi.dgs_reserve(self.ctx, max_keys, max_prims, max_tiles)
+
+    def alloc_image(self, cam, aux=True):
+        H, W = int(cam["height"]), int(cam["width"])
+        d = self.device
+        out = dict(color=torch.empty((3, H, W), device=d, dtype=torch.float32))
+        if aux:
+            out.update(D=torch.empty((H, W), device=d, dtype=torch.float32),
+                       T=torch.empty((H, W), device=d, dtype=torch.float32),
+                       last=torch.empty((H, W), device=d, dtype=torch.int32))
+        return out
+
+    def render_into(self, scene: DeviceScene, cam, out, opts):
+        """Enqueue one frame (no host synchronisation); returns the status."""
+        img = capi.dgs_image()
+        img.color = out["color"].data_ptr()
+        img.weight_sum = out["D"].data_ptr() if "D" in out else None
+        img.final_T = out["T"].data_ptr() if "T" in out else None
+        img.last = out["last"].data_ptr() if "last" in out else None
+        return capi.dgs_render(self.ctx, scene.struct(), camera_struct(cam), opts, img)
+
+    def render(self, scene: DeviceScene, cam, out=None, check=True, **kw):
+        """Render a frame.  With check=True the call synchronises, and on a
+        key-capacity overflow it reserves the reported count and renders
+        again."""
+        opts = opts_struct(**kw)
+        if out is None:
+            out = self.alloc_image(cam)
+        capi.check(self.render_into(scene, cam, out, opts), self.ctx)
+        if check:
+            st = capi.dgs_sync(self.ctx)
+            if st == capi.DGS_ERR_CAPACITY:
+                need = capi.dgs_get_stats(self.ctx).num_keys
+                self.reserve(int(need * 1.25) + 4096)
+                capi.check(self.render_into(scene, cam, out, opts), self.ctx)
+                st = capi.dgs_sync(self.ctx)
+            capi.check(st, self.ctx)
+        return out
+
+    def sync(self):
+        return capi.dgs_sync(self.ctx)
+
+    def stats(self):
+        s = capi.dgs_get_stats(self.ctx)
+        return dict(num_keys=s.num_keys, key_capacity=s.key_capacity, n_val=s.n_val, n_rendered=s.n_rendered,
+                    device_error=s.device_error, sort_passes=s.sort_passes)
+
+    def read_lists(self, tiles):
+        n = self.stats()["num_keys"]
+        keys = torch.empty(max(n, 1), dtype=torch.int64, device=self.device)
+        vals = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        ranges = torch.empty((tiles, 2), dtype=torch.int32, device=self.device)
+        capi.dgs_read_lists(self.ctx, keys.data_ptr(), vals.data_ptr(), ranges.data_ptr())
+        self.stream.synchronize()
+        return keys[:n], vals[:n], ranges
+
+    def read_prims(self, P):
+        rect = torch.empty((max(P, 1), 4), dtype=torch.int32, device=self.device)
+        depth = torch.empty(max(P, 1), dtype=torch.int32, device=self.device)
+        nt = torch.empty(max(P, 1), dtype=torch.int32, device=self.device)
+        capi.dgs_read_prims(self.ctx, rect.data_ptr(), depth.data_ptr(), nt.data_ptr())
+        self.stream.synchronize()
+        return rect[:P], depth[:P], nt[:P]
+
+    def read_gauss_rects(self, M):
+        rect = torch.empty((max(M, 1), 4), dtype=torch.int32, device=self.device)
+        capi.dgs_read_gauss_rects(self.ctx, rect.data_ptr())
+        self.stream.synchronize()
+        return rect[:M]
+
+    def sort_pairs(self, keys, vals, key_bits):
+        """In-place stable sort of int64 keys (as u64) and int32 values."""
+        assert keys.dtype == torch.int64 and vals.dtype == torch.int32 and keys.is_contiguous()
+        assert vals.is_contiguous() and keys.numel() == vals.numel()
+        capi.dgs_sort_pairs(self.ctx, keys.data_ptr(), vals.data_ptr(), keys.numel(), key_bits)
+        capi.check(capi.dgs_sync(self.ctx), self.ctx)
