@@ -6,7 +6,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/duplexgs.h"
+#include "duplexgs.h"
 #include "common.h"
 #include "launch.h"
 
@@ -26,12 +26,14 @@ struct dgs_ctx_s {
     uint64_t *keys0 = nullptr, *keys1 = nullptr;
     uint32_t *vals0 = nullptr, *vals1 = nullptr;
     uint32_t* ranges = nullptr;
+    uint32_t* tile_order = nullptr;
     uint32_t* scan_status = nullptr;
     size_t scan_status_cap = 0;
     uint32_t* sort_status = nullptr;
     size_t sort_status_cap = 0;
     uint32_t* hist = nullptr;     // [8][256]
-    uint32_t* misc = nullptr;     // [0] key total, [1] scan ticket, [2..9] sort tickets, [10] sort count
+    uint32_t* misc = nullptr;     // [0] key total, [1] scan ticket, [2..9] sort tickets, [10] sort count,
+                                  // [11..12] compositor work-queue head and item count
     int* dev_err = nullptr;
     unsigned long long* counters = nullptr;  // n_val, n_rendered
 
@@ -96,6 +98,7 @@ dgs_status ensure(dgs_ctx c, int64_t prims, int64_t gauss, int64_t keys, int64_t
     }
     if (tiles > c->cap_tiles) {
         if ((e = grow(c->ranges, 2 * tiles, c->stream)) != hipSuccess) goto oom;
+        if ((e = grow(c->tile_order, 4 * tiles, c->stream)) != hipSuccess) goto oom;
         c->cap_tiles = tiles;
     }
     return DGS_OK;
@@ -260,7 +263,7 @@ dgs_status dgs_destroy(dgs_ctx c) {
     for (auto& a : c->events)
         for (auto& e : a) hipEventDestroy(e);
     void* ptrs[] = {c->p_depth, c->p_ntiles, c->p_offsets, c->p_rect, c->cell_v, c->recs, c->grect,
-                    c->keys0, c->keys1, c->vals0, c->vals1, c->ranges, c->scan_status, c->sort_status,
+                    c->keys0, c->keys1, c->vals0, c->vals1, c->ranges, c->tile_order, c->scan_status, c->sort_status,
                     c->hist, c->misc, c->dev_err, c->counters};
     for (void* p : ptrs)
         if (p) hipFree(p);
@@ -344,6 +347,8 @@ dgs_status dgs_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* cam, cons
     a.T = out->final_T;
     a.last = out->last;
     a.counters = o.stats ? c->counters : nullptr;
+    a.order = c->tile_order;
+    a.queue = c->misc + 11;
     if (mode == DGS_MODE_DUPLEX)
         launch_composite_duplex(q, a);
     else

@@ -14,256 +14,427 @@
 // Alpha (eqs. alpha_blending, transmittance): the same walk over
 // depth-sorted Gaussians with C += T alpha c, T *= 1 - alpha, plus T bg.
 //
-// One workgroup (4 wavefronts) per 16x16 tile; wavefront w owns the 8x8
-// quadrant (w & 1, w >> 1), lane l the pixel (l & 7, l >> 3) in it.  Batches
-// of up to 256 Gaussian records are staged in LDS together with a per-record
-// and per-cell mask of the quadrants their boxes touch, so a wavefront skips
-// whole cells and Gaussians that miss its quadrant.
+// Mapping: a wavefront runs without workgroup barriers and owns either a
+// whole 16x16 tile or, for tiles with long lists, one 16x4 strip of it
+// (strip j = rows 4j..4j+3; lane l holds pixel (l & 15, 4j + (l >> 4)) of
+// every strip it owns).  Work items are taken from a queue that lists them
+// heaviest first.  The tile list is consumed in
+// chunks of up to 64 Gaussian records (whole cells): each lane loads one
+// record, the wave ballots which strips every record's box touches, and the
+// records go to the wave's private LDS slot, from which they are read as
+// broadcasts.  The next chunk is fetched into registers while the current
+// one is composited.  Cells and members that touch none of the tile's
+// strips are skipped with scalar bit tests on the ballots.
 #include "common.h"
 #include "launch.h"
 
 namespace dgs {
 
-struct PixelCoord {
-    int px, py;
-    bool valid;
+constexpr int kWaves = 4;  // tiles per workgroup
+
+struct Chunk {
+    float4 r0, r1, r2;  // this lane's record
+    float v;            // v of the cell whose first member is this lane
+    bool ok;
 };
 
-__device__ inline PixelCoord tile_pixel(int tile, int TX, int W, int H) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    PixelCoord c;
-    c.px = (tile % TX) * kTile + (wave & 1) * 8 + (lane & 7);
-    c.py = (tile / TX) * kTile + (wave >> 1) * 8 + (lane >> 3);
-    c.valid = c.px < W && c.py < H;
-    return c;
+__device__ inline void load_chunk(const CompositeArgs& a, uint32_t pos, int nrec, int K, int lane, bool cells,
+                                  Chunk& q) {
+    q.ok = lane < nrec;
+    if (!q.ok) return;
+    uint32_t g;
+    if (cells) {
+        const int c = lane / K, k = lane - c * K;
+        const uint32_t cell = a.vals[pos + c];
+        g = cell * K + k;
+        q.v = k == 0 ? a.cell_v[cell] : 0.0f;
+    } else {
+        g = a.vals[pos + lane];
+        q.v = 0.0f;
+    }
+    const float4* p = reinterpret_cast<const float4*>(a.recs + g);
+    q.r0 = p[0];
+    q.r1 = p[1];
+    q.r2 = p[2];
 }
 
-// Quadrant-overlap mask (bit w for wavefront w) of a record's box inside tile.
-__device__ inline uint32_t quad_mask(const GRec& e, int tx0, int ty0) {
-    const int wx = (int)(e.wxy & 0xffffu), wy = (int)(e.wxy >> 16);
-    const int x0 = e.x0 - tx0, x1 = x0 + wx, y0 = e.y0 - ty0, y1 = y0 + wy;
-    uint32_t m = 0;
-    const bool c0 = x0 <= 7 && x1 >= 0, c1 = x0 <= 15 && x1 >= 8;
-    const bool r0 = y0 <= 7 && y1 >= 0, r1 = y0 <= 15 && y1 >= 8;
-    if (r0 && c0) m |= 1u;
-    if (r0 && c1) m |= 2u;
-    if (r1 && c0) m |= 4u;
-    if (r1 && c1) m |= 8u;
-    return m;
+// Ballots of the strips (bit j: rows 4j..4j+3 of the tile) each lane's record touches.
+__device__ inline void strip_ballots(const Chunk& q, int tx0, int ty0, uint64_t* B) {
+    uint32_t sm = 0;
+    if (q.ok) {
+        const int x0 = __float_as_int(q.r2.y), y0 = __float_as_int(q.r2.z);
+        const uint32_t wxy = __float_as_uint(q.r2.w);
+        const int x1 = x0 + (int)(wxy & 0xffffu), y1 = y0 + (int)(wxy >> 16);
+        if (x0 <= tx0 + 15 && x1 >= tx0) {
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+                if (y0 <= ty0 + 4 * j + 3 && y1 >= ty0 + 4 * j) sm |= 1u << j;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j++) B[j] = __ballot((sm >> j) & 1u);
 }
 
-__device__ inline void load_rec(const GRec* __restrict__ recs, uint32_t g, GRec& e) {
-    const float4* p = reinterpret_cast<const float4*>(recs + g);
-    float4 a = p[0], b = p[1], c = p[2];
+__device__ inline void store_chunk(GRec* lds, int lane, const Chunk& q) {
+    if (!q.ok) return;
+    float4* d = reinterpret_cast<float4*>(lds + lane);
+    d[0] = q.r0;
+    d[1] = q.r1;
+    d[2] = q.r2;
+}
+
+struct RecView {
+    float ox, oy, ca, cb, cc, lo, r, g, b;
+    int x0, y0;
+    uint32_t wx, wy;
+};
+
+__device__ inline RecView read_rec(const GRec* lds, int i) {
+    const float4* p = reinterpret_cast<const float4*>(lds + i);
+    const float4 a = p[0], b = p[1], c = p[2];
+    RecView e;
     e.ox = a.x; e.oy = a.y; e.ca = a.z; e.cb = a.w;
     e.cc = b.x; e.lo = b.y; e.r = b.z; e.g = b.w;
-    e.b = c.x; e.x0 = __float_as_int(c.y); e.y0 = __float_as_int(c.z); e.wxy = __float_as_uint(c.w);
+    e.b = c.x;
+    e.x0 = __float_as_int(c.y);
+    e.y0 = __float_as_int(c.z);
+    const uint32_t wxy = __float_as_uint(c.w);
+    e.wx = wxy & 0xffffu;
+    e.wy = wxy >> 16;
+    return e;
 }
 
-// log2(sigma G') of record e at the pixel, or -inf outside its box.
-__device__ inline float rec_power(const GRec& e, int px, int py) {
-    const uint32_t rx = (uint32_t)(px - e.x0), ry = (uint32_t)(py - e.y0);
-    if (rx > (e.wxy & 0xffffu) || ry > (e.wxy >> 16)) return -INFINITY;
-    const float dx = (float)(int)rx + e.ox, dy = (float)(int)ry + e.oy;
-    return e.lo + dx * (e.ca * dx + e.cb * dy) + e.cc * dy * dy;
-}
 
-__global__ __launch_bounds__(256) void k_composite_duplex(CompositeArgs a) {
-    __shared__ GRec s_rec[kBatchSlots];
-    __shared__ uint8_t s_mmask[kBatchSlots];
-    __shared__ uint32_t s_cmask[kBatchSlots];
-    __shared__ float s_v[kBatchSlots];
+// Work item: tile << 3 | mode; mode 0 = all four strips, mode 4 + j = strip j.
+constexpr uint32_t kSplitLen = 64;  // tiles with at least this many entries are split into strips
 
-    const int ntiles = a.k.TX * a.k.TY;
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    if (tile >= ntiles) return;
-    const PixelCoord pc = tile_pixel(tile, a.k.TX, a.k.W, a.k.H);
-    const int wave = threadIdx.x >> 6;
-    const uint32_t mybit = 1u << wave;
+template <bool STATS, int NS>
+__device__ inline void duplex_tile(const CompositeArgs& a, int tile, int s0, int lane, GRec* lds,
+                                   unsigned long long* cnt_val, unsigned long long* cnt_rend) {
     const int tx0 = (tile % a.k.TX) * kTile, ty0 = (tile / a.k.TX) * kTile;
+    const int px = tx0 + (lane & 15), py0 = ty0 + 4 * s0 + (lane >> 4);
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
     const int K = a.K;
-    const int cells_per_batch = kBatchSlots / K < 64 ? kBatchSlots / K : 64;
+    const int cpc = 64 / K;  // cells per chunk
+    const uint32_t kmask = K == 32 ? 0xffffffffu : ((1u << K) - 1u);
     const float eps = a.o.no_et ? 0.0f : a.o.eps;
+    const float th = a.o.log2_alpha_min, amax = a.o.alpha_max;
 
-    float T = 1.0f, N0 = 0.0f, N1 = 0.0f, N2 = 0.0f, D = 0.0f;
-    int32_t last = 0;
-    bool done = !pc.valid;
-    uint32_t nrend = 0, nval = 0;
-    bool wave_done = __all(done);
+    float T[NS], N0[NS], N1[NS], N2[NS], D[NS];
+    int32_t last[NS];
+    bool act[NS];
+    uint32_t nval = 0, nrend = 0;
+#pragma unroll
+    for (int j = 0; j < NS; j++) {
+        T[j] = 1.0f; N0[j] = N1[j] = N2[j] = D[j] = 0.0f; last[j] = 0;
+        act[j] = px < a.k.W && py0 + 4 * j < a.k.H;
+    }
 
-    for (uint32_t b = start; b < end; b += cells_per_batch) {
-        const int nb = (int)min((uint32_t)cells_per_batch, end - b);
-        const int nslots = nb * K;
-        __syncthreads();  // the previous batch has been consumed
-        if (threadIdx.x < nb) s_cmask[threadIdx.x] = 0;
-        __syncthreads();
-        if (threadIdx.x < nslots) {
-            const int c = threadIdx.x / K;
-            const uint32_t cell = a.vals[b + c];
-            GRec e;
-            load_rec(a.recs, cell * K + (threadIdx.x - c * K), e);
-            s_rec[threadIdx.x] = e;
-            const uint32_t m = quad_mask(e, tx0, ty0);
-            s_mmask[threadIdx.x] = (uint8_t)m;
-            if (m) atomicOr(&s_cmask[c], m);
-            if (threadIdx.x - c * K == 0) s_v[c] = a.cell_v[cell];
-        }
-        __syncthreads();
-        if (!wave_done) {
-            for (int c = 0; c < nb; c++) {
-                if (!(s_cmask[c] & mybit)) continue;  // no member touches this quadrant
-                if (!done && T < eps) done = true;      // cell-level early termination
-                if (__all(done)) {
-                    wave_done = true;
-                    break;
-                }
-                const float v = s_v[c];
-                float A0 = 0.0f, A1 = 0.0f, A2 = 0.0f, B = 0.0f, P = 1.0f;
-                uint32_t cnt = 0;
-                for (int kk = 0; kk < K; kk++) {
-                    const int s = c * K + kk;
-                    if (!(s_mmask[s] & mybit)) continue;
-                    const GRec& e = s_rec[s];
-                    const float pw = rec_power(e, pc.px, pc.py);
-                    if (!done && pw >= a.o.log2_alpha_min) {
-                        const float al = fminf(a.o.alpha_max, exp2f(pw));
-                        A0 += al * e.r;
-                        A1 += al * e.g;
-                        A2 += al * e.b;
-                        B += al;
-                        P -= P * (v * al);
-                        cnt++;
+    Chunk q;
+    if (start < end) load_chunk(a, start, (int)min((uint32_t)cpc, end - start) * K, K, lane, true, q);
+    bool alive = true;
+    for (uint32_t pos = start; pos < end && (alive || STATS);) {
+        const int nch = (int)min((uint32_t)cpc, end - pos);
+        store_chunk(lds, lane, q);
+        uint64_t B4[4];
+        strip_ballots(q, tx0, ty0, B4);
+        uint64_t B[NS];
+#pragma unroll
+        for (int j = 0; j < NS; j++) B[j] = B4[s0 + j];
+        const float cv = q.v;
+        const uint32_t next = pos + nch;
+        if (next < end) load_chunk(a, next, (int)min((uint32_t)cpc, end - next) * K, K, lane, true, q);
+        for (int c = 0; c < nch; c++) {
+            const int base = c * K;
+            uint32_t mj[NS], any = 0;
+#pragma unroll
+            for (int j = 0; j < NS; j++) {
+                mj[j] = (uint32_t)(B[j] >> base) & kmask;
+                any |= mj[j];
+            }
+            if (!any) continue;  // no member of this cell touches the owned strips
+            bool anyact = false;
+#pragma unroll
+            for (int j = 0; j < NS; j++) {
+                act[j] = act[j] && !(T[j] < eps);  // cell-level termination
+                anyact = anyact || act[j];
+            }
+            if (!STATS && !__any(anyact)) {
+                alive = false;
+                break;
+            }
+            const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cv), base));
+            float A0[NS], A1[NS], A2[NS], Bs[NS], P[NS];
+#pragma unroll
+            for (int j = 0; j < NS; j++) { A0[j] = A1[j] = A2[j] = Bs[j] = 0.0f; P[j] = 1.0f; }
+            for (uint32_t rem = any; rem; rem &= rem - 1) {
+                const int k = __builtin_ctz(rem);
+                const RecView e = read_rec(lds, base + k);
+                const uint32_t rx = (uint32_t)(px - e.x0);
+                const bool inx = rx <= e.wx;
+                const float dx = (float)(int)rx + e.ox;
+                const float t0 = fmaf(e.ca * dx, dx, e.lo);
+                const float t1 = e.cb * dx;
+                const uint32_t ry0 = (uint32_t)(py0 - e.y0);
+#pragma unroll
+                for (int j = 0; j < NS; j++) {
+                    if (!((mj[j] >> k) & 1u)) continue;  // scalar: member misses strip j
+                    const uint32_t ry = ry0 + 4u * j;
+                    const float dy = (float)(int)ry + e.oy;
+                    const float pw = fmaf(dy, fmaf(e.cc, dy, t1), t0);
+                    const bool hit = inx && ry <= e.wy && pw >= th;
+                    if (STATS) {
+                        nval += hit;
+                        nrend += hit && act[j];
                     }
-                }
-                if (!done) {
-                    const float w = v * T;
-                    N0 += w * A0;
-                    N1 += w * A1;
-                    N2 += w * A2;
-                    D += w * B;
-                    T *= P;
-                    if (cnt) {
-                        last = (int32_t)(b + c - start + 1);
-                        nrend += cnt;
+                    if (hit && act[j]) {
+                        const float al = fminf(amax, __builtin_amdgcn_exp2f(pw));
+                        A0[j] = fmaf(al, e.r, A0[j]);
+                        A1[j] = fmaf(al, e.g, A1[j]);
+                        A2[j] = fmaf(al, e.b, A2[j]);
+                        Bs[j] += al;
+                        P[j] = fmaf(-P[j], v * al, P[j]);
                     }
                 }
             }
+#pragma unroll
+            for (int j = 0; j < NS; j++) {
+                if (!mj[j]) continue;  // scalar: nothing of this cell in strip j
+                if (act[j]) {
+                    const float w = v * T[j];
+                    N0[j] = fmaf(w, A0[j], N0[j]);
+                    N1[j] = fmaf(w, A1[j], N1[j]);
+                    N2[j] = fmaf(w, A2[j], N2[j]);
+                    D[j] = fmaf(w, Bs[j], D[j]);
+                    T[j] *= P[j];
+                    if (Bs[j] > 0.0f) last[j] = (int32_t)(pos + c - start + 1);
+                }
+            }
         }
-        if (a.counters) {
-            // N^val: gated members of every listed cell, ignoring termination
-            if (pc.valid)
-                for (int s = 0; s < nslots; s++)
-                    if (s_mmask[s] & mybit) nval += rec_power(s_rec[s], pc.px, pc.py) >= a.o.log2_alpha_min;
-        } else if (!__syncthreads_or(!wave_done)) {
-            break;
+        pos = next;
+    }
+    const size_t HW = (size_t)a.k.W * a.k.H;
+#pragma unroll
+    for (int j = 0; j < NS; j++) {
+        const int py = py0 + 4 * j;
+        if (px >= a.k.W || py >= a.k.H) continue;
+        const size_t p = (size_t)py * a.k.W + px;
+        if (D[j] > 0.0f) {
+            const float inv = 1.0f / D[j];
+            a.color[p] = N0[j] * inv;
+            a.color[HW + p] = N1[j] * inv;
+            a.color[2 * HW + p] = N2[j] * inv;
+        } else {
+            a.color[p] = a.o.bg[0];
+            a.color[HW + p] = a.o.bg[1];
+            a.color[2 * HW + p] = a.o.bg[2];
         }
+        if (a.D) a.D[p] = D[j];
+        if (a.T) a.T[p] = T[j];
+        if (a.last) a.last[p] = last[j];
     }
-    if (!pc.valid) return;
-    const size_t HW = (size_t)a.k.W * a.k.H, p = (size_t)pc.py * a.k.W + pc.px;
-    if (D > 0.0f) {
-        const float inv = 1.0f / D;
-        a.color[p] = N0 * inv;
-        a.color[HW + p] = N1 * inv;
-        a.color[2 * HW + p] = N2 * inv;
-    } else {
-        a.color[p] = a.o.bg[0];
-        a.color[HW + p] = a.o.bg[1];
-        a.color[2 * HW + p] = a.o.bg[2];
-    }
-    if (a.D) a.D[p] = D;
-    if (a.T) a.T[p] = T;
-    if (a.last) a.last[p] = last;
-    if (a.counters) {
-        atomicAdd(&a.counters[0], (unsigned long long)nval);
-        atomicAdd(&a.counters[1], (unsigned long long)nrend);
+    if (STATS) {
+        *cnt_val += nval;
+        *cnt_rend += nrend;
     }
 }
 
-__global__ __launch_bounds__(256) void k_composite_alpha(CompositeArgs a) {
-    __shared__ GRec s_rec[kBatchSlots];
-    __shared__ uint8_t s_mmask[kBatchSlots];
-
-    const int ntiles = a.k.TX * a.k.TY;
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    if (tile >= ntiles) return;
-    const PixelCoord pc = tile_pixel(tile, a.k.TX, a.k.W, a.k.H);
-    const int wave = threadIdx.x >> 6;
-    const uint32_t mybit = 1u << wave;
+template <bool STATS, int NS>
+__device__ inline void alpha_tile(const CompositeArgs& a, int tile, int s0, int lane, GRec* lds,
+                                  unsigned long long* cnt_val, unsigned long long* cnt_rend) {
     const int tx0 = (tile % a.k.TX) * kTile, ty0 = (tile / a.k.TX) * kTile;
+    const int px = tx0 + (lane & 15), py0 = ty0 + 4 * s0 + (lane >> 4);
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
     const float eps = a.o.no_et ? 0.0f : a.o.eps;
+    const float th = a.o.log2_alpha_min, amax = a.o.alpha_max;
 
-    float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-    int32_t last = 0;
-    bool done = !pc.valid;
-    uint32_t nrend = 0, nval = 0;
-    bool wave_done = __all(done);
-
-    for (uint32_t b = start; b < end; b += kBatchSlots) {
-        const int nb = (int)min((uint32_t)kBatchSlots, end - b);
-        __syncthreads();
-        if (threadIdx.x < nb) {
-            GRec e;
-            load_rec(a.recs, a.vals[b + threadIdx.x], e);
-            s_rec[threadIdx.x] = e;
-            s_mmask[threadIdx.x] = (uint8_t)quad_mask(e, tx0, ty0);
+    float T[NS], C0[NS], C1[NS], C2[NS];
+    int32_t last[NS];
+    bool act[NS];
+    uint32_t nval = 0, nrend = 0;
+#pragma unroll
+    for (int j = 0; j < NS; j++) {
+        T[j] = 1.0f; C0[j] = C1[j] = C2[j] = 0.0f; last[j] = 0;
+        act[j] = px < a.k.W && py0 + 4 * j < a.k.H;
+    }
+    Chunk q;
+    if (start < end) load_chunk(a, start, (int)min(64u, end - start), 1, lane, false, q);
+    bool alive = true;
+    for (uint32_t pos = start; pos < end && (alive || STATS);) {
+        const int n = (int)min(64u, end - pos);
+        store_chunk(lds, lane, q);
+        uint64_t B4[4];
+        strip_ballots(q, tx0, ty0, B4);
+        uint64_t B[NS], any = 0;
+#pragma unroll
+        for (int j = 0; j < NS; j++) {
+            B[j] = B4[s0 + j];
+            any |= B[j];
         }
-        __syncthreads();
-        if (!wave_done) {
-            for (int s = 0; s < nb; s++) {
-                if (!(s_mmask[s] & mybit)) continue;
-                if (!done && T < eps) done = true;
-                if (__all(done)) {
-                    wave_done = true;
+        const uint32_t next = pos + n;
+        if (next < end) load_chunk(a, next, (int)min(64u, end - next), 1, lane, false, q);
+        int since_check = 0;
+        for (; any; any &= any - 1) {
+            const int m = __builtin_ctzll(any);
+            if (!STATS && ++since_check == 8) {
+                since_check = 0;
+                bool anyact = false;
+#pragma unroll
+                for (int j = 0; j < NS; j++) anyact = anyact || act[j];
+                if (!__any(anyact)) {
+                    alive = false;
                     break;
                 }
-                const GRec& e = s_rec[s];
-                const float pw = rec_power(e, pc.px, pc.py);
-                if (!done && pw >= a.o.log2_alpha_min) {
-                    const float al = fminf(a.o.alpha_max, exp2f(pw));
-                    const float w = al * T;
-                    C0 += w * e.r;
-                    C1 += w * e.g;
-                    C2 += w * e.b;
-                    T -= w;
-                    last = (int32_t)(b + s - start + 1);
-                    nrend++;
+            }
+            const RecView e = read_rec(lds, m);
+            const uint32_t rx = (uint32_t)(px - e.x0);
+            const bool inx = rx <= e.wx;
+            const float dx = (float)(int)rx + e.ox;
+            const float t0 = fmaf(e.ca * dx, dx, e.lo);
+            const float t1 = e.cb * dx;
+            const uint32_t ry0 = (uint32_t)(py0 - e.y0);
+#pragma unroll
+            for (int j = 0; j < NS; j++) {
+                if (!((B[j] >> m) & 1ull)) continue;
+                act[j] = act[j] && !(T[j] < eps);  // termination before each Gaussian
+                const uint32_t ry = ry0 + 4u * j;
+                const float dy = (float)(int)ry + e.oy;
+                const float pw = fmaf(dy, fmaf(e.cc, dy, t1), t0);
+                const bool hit = inx && ry <= e.wy && pw >= th;
+                if (STATS) nval += hit;
+                if (hit && act[j]) {
+                    const float al = fminf(amax, __builtin_amdgcn_exp2f(pw));
+                    const float w = al * T[j];
+                    C0[j] = fmaf(w, e.r, C0[j]);
+                    C1[j] = fmaf(w, e.g, C1[j]);
+                    C2[j] = fmaf(w, e.b, C2[j]);
+                    T[j] -= w;
+                    last[j] = (int32_t)(pos + m - start + 1);
+                    if (STATS) nrend++;
                 }
             }
         }
-        if (a.counters) {
-            if (pc.valid)
-                for (int s = 0; s < nb; s++)
-                    if (s_mmask[s] & mybit) nval += rec_power(s_rec[s], pc.px, pc.py) >= a.o.log2_alpha_min;
-        } else if (!__syncthreads_or(!wave_done)) {
-            break;
+        pos = next;
+    }
+    const size_t HW = (size_t)a.k.W * a.k.H;
+#pragma unroll
+    for (int j = 0; j < NS; j++) {
+        const int py = py0 + 4 * j;
+        if (px >= a.k.W || py >= a.k.H) continue;
+        const size_t p = (size_t)py * a.k.W + px;
+        a.color[p] = fmaf(T[j], a.o.bg[0], C0[j]);
+        a.color[HW + p] = fmaf(T[j], a.o.bg[1], C1[j]);
+        a.color[2 * HW + p] = fmaf(T[j], a.o.bg[2], C2[j]);
+        if (a.D) a.D[p] = 1.0f - T[j];
+        if (a.T) a.T[p] = T[j];
+        if (a.last) a.last[p] = last[j];
+    }
+    if (STATS) {
+        *cnt_val += nval;
+        *cnt_rend += nrend;
+    }
+}
+
+// Persistent wavefronts: each takes the next work item of a queue that lists
+// them heaviest first, so long tiles start early and short ones fill in
+// behind them on every XCD.  Every wavefront leaves once the queue is empty.
+template <bool DUPLEX, bool STATS>
+__global__ __launch_bounds__(256) void k_composite(CompositeArgs a) {
+    __shared__ GRec s_rec[kWaves][64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    GRec* lds = s_rec[wave];
+    const uint32_t nitems = a.queue[1];
+    unsigned long long cv = 0, cr = 0;
+    for (;;) {
+        uint32_t t = 0;
+        if (lane == 0) t = atomicAdd(a.queue, 1u);
+        t = (uint32_t)__shfl((int)t, 0, 64);
+        if (t >= nitems) break;
+        const uint32_t item = a.order[t];
+        const int tile = (int)(item >> 3), mode = (int)(item & 7u);
+        if (DUPLEX) {
+            if (mode == 0)
+                duplex_tile<STATS, 4>(a, tile, 0, lane, lds, &cv, &cr);
+            else
+                duplex_tile<STATS, 1>(a, tile, mode - 4, lane, lds, &cv, &cr);
+        } else {
+            if (mode == 0)
+                alpha_tile<STATS, 4>(a, tile, 0, lane, lds, &cv, &cr);
+            else
+                alpha_tile<STATS, 1>(a, tile, mode - 4, lane, lds, &cv, &cr);
         }
     }
-    if (!pc.valid) return;
-    const size_t HW = (size_t)a.k.W * a.k.H, p = (size_t)pc.py * a.k.W + pc.px;
-    a.color[p] = C0 + T * a.o.bg[0];
-    a.color[HW + p] = C1 + T * a.o.bg[1];
-    a.color[2 * HW + p] = C2 + T * a.o.bg[2];
-    if (a.D) a.D[p] = 1.0f - T;
-    if (a.T) a.T[p] = T;
-    if (a.last) a.last[p] = last;
-    if (a.counters) {
-        atomicAdd(&a.counters[0], (unsigned long long)nval);
-        atomicAdd(&a.counters[1], (unsigned long long)nrend);
+    if (STATS) {
+        atomicAdd(&a.counters[0], cv);
+        atomicAdd(&a.counters[1], cr);
     }
 }
 
-void launch_composite_duplex(hipStream_t st, const CompositeArgs& a) {
-    const int tiles = a.k.TX * a.k.TY;
-    if (tiles <= 0) return;
-    hipLaunchKernelGGL(k_composite_duplex, dim3(tiles), dim3(256), 0, st, a);
+// Builds the work queue: one item per tile, or one per strip for tiles whose
+// list has at least kSplitLen entries; items are bucketed by
+// floor(log2(estimated cost)) and laid out from costly to cheap (order inside
+// a bucket is arbitrary: it only affects scheduling, never results).
+// queue[0] = head (reset), queue[1] = item count.  One workgroup.
+__global__ __launch_bounds__(1024) void k_tile_order(const uint32_t* __restrict__ ranges, int ntiles,
+                                                     uint32_t* __restrict__ order, uint32_t* __restrict__ queue) {
+    __shared__ uint32_t s_cnt[33], s_off[33];
+    const int tid = threadIdx.x;
+    if (tid < 33) s_cnt[tid] = 0;
+    __syncthreads();
+    for (int t = tid; t < ntiles; t += blockDim.x) {
+        const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+        if (len >= kSplitLen)
+            atomicAdd(&s_cnt[32 - __clz(len / 2)], 4u);  // four strips, each about half a tile's cost
+        else
+            atomicAdd(&s_cnt[32 - __clz(len)], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t run = 0;
+        for (int b = 32; b >= 0; b--) {
+            s_off[b] = run;
+            run += s_cnt[b];
+        }
+        queue[0] = 0;
+        queue[1] = run;
+    }
+    __syncthreads();
+    for (int t = tid; t < ntiles; t += blockDim.x) {
+        const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+        if (len >= kSplitLen) {
+            const uint32_t o = atomicAdd(&s_off[32 - __clz(len / 2)], 4u);
+            for (uint32_t j = 0; j < 4; j++) order[o + j] = ((uint32_t)t << 3) | (4u + j);
+        } else {
+            order[atomicAdd(&s_off[32 - __clz(len)], 1u)] = (uint32_t)t << 3;
+        }
+    }
 }
 
-void launch_composite_alpha(hipStream_t st, const CompositeArgs& a) {
+static unsigned persistent_grid(int tiles) {
+    // enough wavefronts to fill every SIMD of the 256 CUs a few times over
+    const int waves = 4 * tiles < 256 * 4 * 4 ? 4 * tiles : 256 * 4 * 4;
+    return (unsigned)((waves + kWaves - 1) / kWaves);
+}
+
+static void launch_composite(hipStream_t st, const CompositeArgs& a, bool duplex) {
     const int tiles = a.k.TX * a.k.TY;
     if (tiles <= 0) return;
-    hipLaunchKernelGGL(k_composite_alpha, dim3(tiles), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, st, a.ranges, tiles, a.order, a.queue);
+    const dim3 g(persistent_grid(tiles)), b(256);
+    if (duplex) {
+        if (a.counters)
+            hipLaunchKernelGGL((k_composite<true, true>), g, b, 0, st, a);
+        else
+            hipLaunchKernelGGL((k_composite<true, false>), g, b, 0, st, a);
+    } else {
+        if (a.counters)
+            hipLaunchKernelGGL((k_composite<false, true>), g, b, 0, st, a);
+        else
+            hipLaunchKernelGGL((k_composite<false, false>), g, b, 0, st, a);
+    }
 }
+
+void launch_composite_duplex(hipStream_t st, const CompositeArgs& a) { launch_composite(st, a, true); }
+void launch_composite_alpha(hipStream_t st, const CompositeArgs& a) { launch_composite(st, a, false); }
 
 }  // namespace dgs

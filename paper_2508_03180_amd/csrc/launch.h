@@ -57,6 +57,8 @@ struct CompositeArgs {
     float* T;
     int32_t* last;
     unsigned long long* counters;  // [2]: n_val, n_rendered (stats mode), nullable
+    uint32_t* order;               // [4 * tiles] scratch: heaviest-first work items
+    uint32_t* queue;               // [2] scratch: work-queue head, item count
 };
 void launch_composite_duplex(hipStream_t st, const CompositeArgs& a);
 void launch_composite_alpha(hipStream_t st, const CompositeArgs& a);
