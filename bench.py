@@ -3,12 +3,13 @@
 
 Workload: the clustered 1M-Gaussian scene (100,000 cells x 10 Gaussians, SH
 degree 3, seed 1) rendered at 1920x1080 along a 60-frame orbit, inputs
-resident in HBM.  A step is one whole frame: cell preprocess, Gaussian
-projection, scan + key emission, onesweep radix sort, tile ranges and the
-hybrid compositor.  The same frames are also rendered by the per-Gaussian-sort
-alpha-blending path of the same library.
+resident in HBM.  A step is one whole frame through the C ABI: cell
+preprocess, Gaussian projection, scan + key emission, onesweep radix sort,
+tile ranges and work queue, and the hybrid compositor.  The same frames are
+also rendered by the per-Gaussian-sort alpha-blending path of the same
+library (the comparison path).
 
-Prints one JSON line (rank 0, N = 1).
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -21,16 +22,26 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work of one compositor member evaluation:
-# per (pixel, Gaussian) pair inside the Gaussian's box in a processed cell,
-# 12 flops to form log2(sigma G') (2 offsets, 3 products, 3 fused
-# multiply-adds counted as 2) plus the gate; per pair that passes alpha_min,
-# 1 exp, 1 clamp and 10 flops of accumulation (A: 3 FMA, B: 1 add,
-# P: 1 mul + 1 FMA).
-FLOP_EVAL = 12
-FLOP_ACCUM = 12
 PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 vector peak
-PEAK_HBM_GBS = 8000.0
+PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
+
+# Algorithmic FP32 work of the compositors (FMA counts 2), per counted event:
+#   in-box evaluation: offsets (2), quadratic form (3 products, 3 multiply by
+#   the conic, 2 adds), exp (1), times sigma (1)                       = 12
+#   Duplex accumulated member: clamp (1), A (3 FMA = 6), B (1),
+#   1 - v alpha (2), P *= (1)                                         = 11
+#   Duplex blended cell per pixel: w = v T (1), N, D (4 FMA = 8), T *= P (1) = 10
+#   alpha blended Gaussian: clamp (1), w = alpha T (1), C (3 FMA = 6),
+#   T -= w (1)                                                         = 9
+FLOP_BOX = 12
+FLOP_DUPLEX_MEMBER = 11
+FLOP_DUPLEX_CELL = 10
+FLOP_ALPHA_HIT = 9
+
+# algorithmic bytes of the Gaussian projection, per projected Gaussian:
+# reads mean 12, scales 12, quaternion 16, opacity 4, SH (deg 3) 192,
+# writes the 48-byte record and the 8-byte packed rectangle
+BYTES_PROJECT_SH3 = 12 + 12 + 16 + 4 + 192 + 48 + 8
 
 
 def parse():
@@ -47,7 +58,7 @@ def parse():
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this renderer runs on one GPU; multi-GPU runs are not supported (--gpus 1)"}))
         sys.exit(2)
     import numpy as np
     import torch
@@ -62,28 +73,22 @@ def main():
     cams = scenes.orbit_cameras(NF, W, H)
     r = Renderer(0)
     ds = DeviceScene.from_numpy(scene, "cuda:0")
-    stream = r.stream
     out = r.alloc_image(cams[0])
     cam_structs = [camera_struct(c) for c in cams]
     sc = ds.struct()
-
-    def img_struct(o):
-        im = capi.dgs_image()
-        im.color, im.weight_sum = o["color"].data_ptr(), o["D"].data_ptr()
-        im.final_T, im.last = o["T"].data_ptr(), o["last"].data_ptr()
-        return im
-
-    im = img_struct(out)
+    im = capi.dgs_image()
+    im.color, im.weight_sum = out["color"].data_ptr(), out["D"].data_ptr()
+    im.final_T, im.last = out["T"].data_ptr(), out["last"].data_ptr()
     L = capi.lib()
 
-    def frames(mode, n, opts=None):
-        op = opts or opts_struct(mode=mode)
+    def frames(mode, n):
+        op = opts_struct(mode=mode)
         for i in range(n):
             st = L.dgs_render(r.ctx, sc, cam_structs[i % NF], op, im)
             if st:
                 capi.check(st, r.ctx)
 
-    def size_and_count(mode):
+    def size_all(mode):
         keys = []
         for i in range(NF):
             r.render(ds, cams[i], out=out, mode=mode)
@@ -100,45 +105,58 @@ def main():
         capi.check(capi.dgs_sync(r.ctx), r.ctx)
         return dt
 
-    def stage_times(mode, steps):
+    def stage_times(mode):
         capi.dgs_set_timing(r.ctx, 1)
-        frames(mode, steps)
+        frames(mode, NF)
         ms, nfr = capi.dgs_get_timing(r.ctx)
         capi.dgs_set_timing(r.ctx, 0)
         return {k: v / nfr for k, v in zip(capi.STAGE_NAMES, ms)}
 
     def counters(mode, idx):
-        tot = dict(n_val=0, n_rendered=0, keys=0)
+        tot = dict(n_val=0, n_rendered=0, n_box=0, n_cell_hits=0, keys=0, projected=0)
         for i in idx:
             r.render(ds, cams[i], out=out, mode=mode, stats=True)
             s = r.stats()
-            tot["n_val"] += s["n_val"]
-            tot["n_rendered"] += s["n_rendered"]
+            for k in ("n_val", "n_rendered", "n_box", "n_cell_hits"):
+                tot[k] += s[k]
             tot["keys"] += s["num_keys"]
+            if mode == "duplex":
+                _, _, nt = r.read_prims(ds.N)
+                tot["projected"] += int((nt > 0).sum().item()) * ds.K
+            else:
+                tot["projected"] += ds.M
         return {k: v / len(idx) for k, v in tot.items()}
 
-    keys_dup = size_and_count("duplex")
+    keys_dup = size_all("duplex")
     dt = timed("duplex", a.steps, a.warmup)
     fps = a.steps / dt
-    stages = stage_times("duplex", NF)
+    st_dup = stage_times("duplex")
     cnt = counters("duplex", range(0, NF, 6))
-    res = dict(fps_alpha=None)
-    if not a.no_alpha:
-        keys_alpha = size_and_count("alpha")
-        dta = timed("alpha", a.steps, a.warmup)
-        res["fps_alpha"] = a.steps / dta
-        res["stages_alpha_ms"] = stage_times("alpha", NF)
-        res["keys_alpha_mean"] = float(np.mean(keys_alpha))
 
-    # roofline of the dominant kernel (the compositor): algorithmic flops per
-    # launch from the counted member evaluations
-    comp_ms = stages["composite"]
-    evals = cnt["n_val"]  # gated pairs of all listed cells (upper bound on evaluated work)
-    flops = cnt["n_rendered"] * (FLOP_EVAL + FLOP_ACCUM)
+    alpha = None
+    if not a.no_alpha:
+        keys_alpha = size_all("alpha")
+        dta = timed("alpha", a.steps, a.warmup)
+        st_alpha = stage_times("alpha")
+        cnt_a = counters("alpha", range(0, NF, 6))
+        comp_a = st_alpha["composite"]
+        flops_a = FLOP_BOX * cnt_a["n_box"] + FLOP_ALPHA_HIT * cnt_a["n_rendered"]
+        alpha = {"fps": round(a.steps / dta, 2), "ms_per_step": round(1e3 * dta / a.steps, 4),
+                 "stages_ms": {k: round(v, 4) for k, v in st_alpha.items()},
+                 "keys_mean": float(np.mean(keys_alpha)),
+                 "composite_tflops": round(flops_a / (comp_a * 1e-3) / 1e12, 3),
+                 "sort_keys_per_s": round(cnt_a["keys"] / (st_alpha["radix_sort"] * 1e-3), 1)}
+
+    # roofline of the dominant kernel, the Duplex compositor (plain FP32 ALU)
+    comp_ms = st_dup["composite"]
+    flops = (FLOP_BOX * cnt["n_box"] + FLOP_DUPLEX_MEMBER * cnt["n_rendered"]
+             + FLOP_DUPLEX_CELL * cnt["n_cell_hits"])
     achieved = flops / (comp_ms * 1e-3) / 1e12
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
-            "kernel": "k_composite_duplex", "kernel_ms": round(comp_ms, 4)}
+            "kernel": "k_composite<true, false>", "kernel_ms": round(comp_ms, 4),
+            "algorithmic_gflop_per_launch": round(flops / 1e9, 4)}
+    proj_gbs = cnt["projected"] * BYTES_PROJECT_SH3 / (st_dup["gauss_project"] * 1e-3) / 1e9
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -150,26 +168,28 @@ def main():
         cdt = time.perf_counter() - t0
         cpu = {"value": round(len(idx) / cdt, 4), "unit": "frames/s", "cores": oracle.num_threads(),
                "kind": "oracle",
-               "sample": f"{len(idx)} full 1920x1080 frames (orbit {idx}) of the same scene, binary64 oracle"}
+               "sample": f"{len(idx)} full 1920x1080 frames (orbit frames {idx}) of the same scene"}
 
     line = {
         "metric": "FPS @1080p, 1M Gaussians vs per-Gaussian-sort baseline; serve p50/p99 ms",
         "value": round(fps, 2), "unit": "frames/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": round(1e3 * dt / a.steps, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "clustered 1M-Gaussian scene (100k cells x 10, SH3), 1920x1080, 60-frame orbit",
-                   "cells": ds.N, "gaussians": ds.M, "width": W, "height": H, "frames": NF},
-        "fps_alpha_baseline": None if res["fps_alpha"] is None else round(res["fps_alpha"], 2),
-        "speedup_vs_alpha": None if res["fps_alpha"] is None else round(fps / res["fps_alpha"], 3),
-        "stages_ms": {k: round(v, 4) for k, v in stages.items()},
+        "config": {"workload": "clustered scene, 100k cells x 10 Gaussians (1M), SH degree 3, "
+                               "1920x1080, 60-frame orbit", "cells": ds.N, "gaussians": ds.M,
+                   "width": W, "height": H, "frames": NF},
+        "alpha_baseline": alpha,
+        "speedup_vs_alpha": None if alpha is None else round(fps / alpha["fps"], 3),
+        "stages_ms": {k: round(v, 4) for k, v in st_dup.items()},
         "keys_mean": float(np.mean(keys_dup)),
+        "key_reduction_vs_alpha": None if alpha is None else round(1 - np.mean(keys_dup) / alpha["keys_mean"], 4),
+        "sort_keys_per_s": round(cnt["keys"] / (st_dup["radix_sort"] * 1e-3), 1),
+        "projection_hbm_gbs": round(proj_gbs, 1),
+        "projection_hbm_frac": round(proj_gbs / PEAK_HBM_GBS, 4),
         "termination_ratio": round(1 - cnt["n_rendered"] / max(cnt["n_val"], 1), 4),
         "roofline": roof,
         "cpu_baseline": cpu,
     }
-    if "stages_alpha_ms" in res:
-        line["stages_alpha_ms"] = {k: round(v, 4) for k, v in res["stages_alpha_ms"].items()}
-        line["keys_alpha_mean"] = res["keys_alpha_mean"]
     print(json.dumps(line), flush=True)
     r.close()
 

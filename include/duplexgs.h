@@ -115,6 +115,8 @@ typedef struct {
     int64_t key_capacity;  /* reserved key capacity */
     int64_t n_val;         /* sum over pixels of N^val (DGS_FLAG_STATS renders only) */
     int64_t n_rendered;    /* sum over pixels of N^rendered (DGS_FLAG_STATS renders only) */
+    int64_t n_box;         /* (pixel, Gaussian) pairs evaluated inside the Gaussian's box before termination */
+    int64_t n_cell_hits;   /* (pixel, list entry) pairs that contributed (Duplex: cells; alpha: Gaussians) */
     int32_t device_error;  /* dgs_status of the last device-side error, 0 if none */
     int32_t sort_passes;   /* radix passes of the last sort */
 } dgs_stats;
@@ -176,7 +178,8 @@ dgs_status dgs_read_gauss_rects(dgs_ctx ctx, int32_t* rect);
 /* Stage timing.  While enabled, every render records HIP events on the
  * context stream at the boundaries of its stages:
  *   0 cell preprocess (or nothing in alpha mode), 1 Gaussian projection,
- *   2 scan + key emission, 3 radix sort, 4 tile ranges, 5 compositor. */
+ *   2 scan + key emission, 3 radix sort, 4 tile ranges + compositor work
+ *   queue, 5 the compositor kernel alone. */
 #define DGS_NUM_STAGES 6
 dgs_status dgs_set_timing(dgs_ctx ctx, int32_t enable);
 

@@ -53,7 +53,8 @@ class dgs_image(C.Structure):
 
 class dgs_stats(C.Structure):
     _fields_ = [("num_keys", C.c_int64), ("key_capacity", C.c_int64), ("n_val", C.c_int64),
-                ("n_rendered", C.c_int64), ("device_error", C.c_int32), ("sort_passes", C.c_int32)]
+                ("n_rendered", C.c_int64), ("n_box", C.c_int64), ("n_cell_hits", C.c_int64),
+                ("device_error", C.c_int32), ("sort_passes", C.c_int32)]
 
 
 dgs_ctx = C.c_void_p
@@ -79,7 +80,7 @@ _SIGS = {
 }
 
 DGS_NUM_STAGES = 6
-STAGE_NAMES = ["cell_preprocess", "gauss_project", "scan_emit", "radix_sort", "tile_ranges", "composite"]
+STAGE_NAMES = ["cell_preprocess", "gauss_project", "scan_emit", "radix_sort", "tile_ranges_queue", "composite"]
 
 _lib = None
 

@@ -27,15 +27,16 @@ struct dgs_ctx_s {
     uint32_t *vals0 = nullptr, *vals1 = nullptr;
     uint32_t* ranges = nullptr;
     uint32_t* tile_order = nullptr;
-    uint32_t* scan_status = nullptr;
+    uint64_t* scan_status = nullptr;
     size_t scan_status_cap = 0;
-    uint32_t* sort_status = nullptr;
+    uint64_t* sort_status = nullptr;
     size_t sort_status_cap = 0;
+    uint32_t epoch = 0;  // look-back epoch counter
     uint32_t* hist = nullptr;     // [8][256]
     uint32_t* misc = nullptr;     // [0] key total, [1] scan ticket, [2..9] sort tickets, [10] sort count,
                                   // [11..12] compositor work-queue head and item count
     int* dev_err = nullptr;
-    unsigned long long* counters = nullptr;  // n_val, n_rendered
+    unsigned long long* counters = nullptr;  // n_val, n_rendered, n_box, n_cell_hits
 
     // last frame
     int last_mode = -1, last_passes = 0;
@@ -65,6 +66,13 @@ hipError_t grow(T*& p, int64_t want, hipStream_t st) {
     return hipMalloc((void**)&p, sizeof(T) * (size_t)(want > 0 ? want : 1));
 }
 
+// Look-back status buffers start zeroed (epoch 0 is never used).
+hipError_t grow_zeroed(uint64_t*& p, int64_t want, hipStream_t st) {
+    hipError_t e = grow(p, want, st);
+    if (e == hipSuccess) e = hipMemset(p, 0, sizeof(uint64_t) * (size_t)(want > 0 ? want : 1));
+    return e;
+}
+
 dgs_status ensure(dgs_ctx c, int64_t prims, int64_t gauss, int64_t keys, int64_t tiles) {
     hipError_t e = hipSuccess;
     if (prims > c->cap_prims) {
@@ -75,7 +83,7 @@ dgs_status ensure(dgs_ctx c, int64_t prims, int64_t gauss, int64_t keys, int64_t
         if ((e = grow(c->p_rect, prims, c->stream)) != hipSuccess) goto oom;
         if ((e = grow(c->cell_v, prims, c->stream)) != hipSuccess) goto oom;
         size_t sw = scan_status_words(prims);
-        if ((e = grow(c->scan_status, (int64_t)sw, c->stream)) != hipSuccess) goto oom;
+        if ((e = grow_zeroed(c->scan_status, (int64_t)sw, c->stream)) != hipSuccess) goto oom;
         c->scan_status_cap = sw;
         c->cap_prims = prims;
     }
@@ -91,8 +99,8 @@ dgs_status ensure(dgs_ctx c, int64_t prims, int64_t gauss, int64_t keys, int64_t
         if ((e = grow(c->keys1, keys, c->stream)) != hipSuccess) goto oom;
         if ((e = grow(c->vals0, keys, c->stream)) != hipSuccess) goto oom;
         if ((e = grow(c->vals1, keys, c->stream)) != hipSuccess) goto oom;
-        size_t sw = sort_status_words(keys, 8);
-        if ((e = grow(c->sort_status, (int64_t)sw, c->stream)) != hipSuccess) goto oom;
+        size_t sw = sort_status_words(keys);
+        if ((e = grow_zeroed(c->sort_status, (int64_t)sw, c->stream)) != hipSuccess) goto oom;
         c->sort_status_cap = sw;
         c->cap_keys = keys;
     }
@@ -244,13 +252,13 @@ dgs_status dgs_create(int device, void* hip_stream, dgs_ctx* out) {
     if (hipMalloc((void**)&c->hist, 8 * 256 * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc((void**)&c->misc, 16 * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc((void**)&c->dev_err, sizeof(int)) != hipSuccess ||
-        hipMalloc((void**)&c->counters, 2 * sizeof(unsigned long long)) != hipSuccess) {
+        hipMalloc((void**)&c->counters, 4 * sizeof(unsigned long long)) != hipSuccess) {
         dgs_destroy(c);
         return DGS_ERR_OOM;
     }
     hipMemsetAsync(c->misc, 0, 16 * sizeof(uint32_t), c->stream);
     hipMemsetAsync(c->dev_err, 0, sizeof(int), c->stream);
-    hipMemsetAsync(c->counters, 0, 2 * sizeof(unsigned long long), c->stream);
+    hipMemsetAsync(c->counters, 0, 4 * sizeof(unsigned long long), c->stream);
     hipStreamSynchronize(c->stream);
     *out = c;
     return DGS_OK;
@@ -307,7 +315,16 @@ dgs_status dgs_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* cam, cons
     hipStream_t q = c->stream;
 
     StageMarks sm(c);
-    if (o.stats) launch_fill_u32(q, (uint32_t*)c->counters, 0u, 4);
+    {
+        // per-frame zeroing: digit histograms, scan/sort tickets and the
+        // compositor queue (misc[1..12]), tile ranges, statistics counters
+        ClearList cl;
+        cl.add(c->hist, 8 * 256);
+        cl.add(c->misc + 1, 12);
+        cl.add(c->ranges, 2 * (size_t)tiles);
+        if (o.stats) cl.add((uint32_t*)c->counters, 8);
+        launch_clear(q, cl);
+    }
     sm.mark(0);
     if (mode == DGS_MODE_DUPLEX) {
         launch_cell_preprocess(q, N, s->cell_pos, s->cell_scale, s->cell_rot, s->cell_v_sh, s->v_sh_degree, k, o,
@@ -322,18 +339,18 @@ dgs_status dgs_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* cam, cons
     }
     sm.mark(2);
     const uint64_t* prect = mode == DGS_MODE_DUPLEX ? c->p_rect : c->grect;
-    launch_exclusive_scan(q, c->p_ntiles, c->p_offsets, P, c->misc + 0, c->scan_status, c->misc + 1, c->dev_err);
+    launch_exclusive_scan(q, c->p_ntiles, c->p_offsets, P, c->misc + 0, c->scan_status, &c->epoch, c->misc + 1,
+                          c->dev_err);
     launch_emit_keys(q, P, c->p_ntiles, c->p_offsets, prect, c->p_depth, k.TX, cap, c->keys0, c->vals0, c->dev_err);
     sm.mark(3);
     SortScratch ss{c->hist, c->sort_status, c->misc + 2};
     const int bits = 32 + tile_bits(tiles);
     const bool in1 = launch_radix_sort(q, c->keys0, c->vals0, c->keys1, c->vals1, c->misc + 0, cap, bits, ss,
-                                       c->dev_err);
+                                       &c->epoch, c->dev_err);
     const uint64_t* skeys = in1 ? c->keys1 : c->keys0;
     const uint32_t* svals = in1 ? c->vals1 : c->vals0;
     sm.mark(4);
-    launch_tile_ranges(q, skeys, c->misc + 0, cap, c->ranges, tiles);
-    sm.mark(5);
+    launch_tile_ranges(q, skeys, c->misc + 0, cap, c->ranges);
     CompositeArgs a;
     a.ranges = c->ranges;
     a.vals = svals;
@@ -349,6 +366,8 @@ dgs_status dgs_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* cam, cons
     a.counters = o.stats ? c->counters : nullptr;
     a.order = c->tile_order;
     a.queue = c->misc + 11;
+    launch_tile_order(q, a);
+    sm.mark(5);
     if (mode == DGS_MODE_DUPLEX)
         launch_composite_duplex(q, a);
     else
@@ -384,7 +403,7 @@ dgs_status dgs_get_stats(dgs_ctx c, dgs_stats* out) {
     hipSetDevice(c->device);
     if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, DGS_ERR_DEVICE, "stream synchronize failed");
     uint32_t total = 0;
-    unsigned long long cnt[2] = {0, 0};
+    unsigned long long cnt[4] = {0, 0, 0, 0};
     int e = 0;
     hipMemcpy(&total, c->misc, sizeof(uint32_t), hipMemcpyDeviceToHost);
     hipMemcpy(cnt, c->counters, sizeof(cnt), hipMemcpyDeviceToHost);
@@ -393,6 +412,8 @@ dgs_status dgs_get_stats(dgs_ctx c, dgs_stats* out) {
     out->key_capacity = c->cap_keys;
     out->n_val = (int64_t)cnt[0];
     out->n_rendered = (int64_t)cnt[1];
+    out->n_box = (int64_t)cnt[2];
+    out->n_cell_hits = (int64_t)cnt[3];
     out->device_error = (e & (1 << kErrTimeout)) ? DGS_ERR_TIMEOUT : (e & (1 << kErrCapacity)) ? DGS_ERR_CAPACITY : 0;
     out->sort_passes = c->last_passes;
     return DGS_OK;
@@ -471,10 +492,14 @@ dgs_status dgs_sort_pairs(dgs_ctx c, uint64_t* keys, uint32_t* values, int64_t n
     hipSetDevice(c->device);
     dgs_status st;
     if ((st = ensure(c, 0, 0, n, 0)) != DGS_OK) return st;
+    ClearList cl;
+    cl.add(c->hist, 8 * 256);
+    cl.add(c->misc + 2, 8);
+    launch_clear(c->stream, cl);
     launch_fill_u32(c->stream, c->misc + 10, (uint32_t)n, 1);
     SortScratch ss{c->hist, c->sort_status, c->misc + 2};
     const bool in1 = launch_radix_sort(c->stream, keys, values, c->keys1, c->vals1, c->misc + 10, (uint32_t)n,
-                                       key_bits, ss, c->dev_err);
+                                       key_bits, ss, &c->epoch, c->dev_err);
     if (in1) {
         hipMemcpyAsync(keys, c->keys1, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, c->stream);
         hipMemcpyAsync(values, c->vals1, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, c->stream);

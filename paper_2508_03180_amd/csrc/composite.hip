@@ -108,9 +108,15 @@ __device__ inline RecView read_rec(const GRec* lds, int i) {
 // Work item: tile << 3 | mode; mode 0 = all four strips, mode 4 + j = strip j.
 constexpr uint32_t kSplitLen = 64;  // tiles with at least this many entries are split into strips
 
+// Statistics counters (STATS only): n_val, n_rendered (the termination ratio
+// 1 - n_rendered / n_val), in-box member evaluations and (pixel, entry) pairs
+// that contributed, for the algorithmic work count.
+struct Counters {
+    uint32_t val = 0, rend = 0, box = 0, cellhit = 0;
+};
+
 template <bool STATS, int NS>
-__device__ inline void duplex_tile(const CompositeArgs& a, int tile, int s0, int lane, GRec* lds,
-                                   unsigned long long* cnt_val, unsigned long long* cnt_rend) {
+__device__ inline void duplex_tile(const CompositeArgs& a, int tile, int s0, int lane, GRec* lds, Counters& cn) {
     const int tx0 = (tile % a.k.TX) * kTile, ty0 = (tile / a.k.TX) * kTile;
     const int px = tx0 + (lane & 15), py0 = ty0 + 4 * s0 + (lane >> 4);
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
@@ -123,7 +129,6 @@ __device__ inline void duplex_tile(const CompositeArgs& a, int tile, int s0, int
     float T[NS], N0[NS], N1[NS], N2[NS], D[NS];
     int32_t last[NS];
     bool act[NS];
-    uint32_t nval = 0, nrend = 0;
 #pragma unroll
     for (int j = 0; j < NS; j++) {
         T[j] = 1.0f; N0[j] = N1[j] = N2[j] = D[j] = 0.0f; last[j] = 0;
@@ -182,10 +187,12 @@ __device__ inline void duplex_tile(const CompositeArgs& a, int tile, int s0, int
                     const uint32_t ry = ry0 + 4u * j;
                     const float dy = (float)(int)ry + e.oy;
                     const float pw = fmaf(dy, fmaf(e.cc, dy, t1), t0);
-                    const bool hit = inx && ry <= e.wy && pw >= th;
+                    const bool inbox = inx && ry <= e.wy;
+                    const bool hit = inbox && pw >= th;
                     if (STATS) {
-                        nval += hit;
-                        nrend += hit && act[j];
+                        cn.val += hit;
+                        cn.rend += hit && act[j];
+                        cn.box += inbox && act[j];
                     }
                     if (hit && act[j]) {
                         const float al = fminf(amax, __builtin_amdgcn_exp2f(pw));
@@ -208,6 +215,7 @@ __device__ inline void duplex_tile(const CompositeArgs& a, int tile, int s0, int
                     D[j] = fmaf(w, Bs[j], D[j]);
                     T[j] *= P[j];
                     if (Bs[j] > 0.0f) last[j] = (int32_t)(pos + c - start + 1);
+                    if (STATS) cn.cellhit += Bs[j] > 0.0f;
                 }
             }
         }
@@ -233,15 +241,10 @@ __device__ inline void duplex_tile(const CompositeArgs& a, int tile, int s0, int
         if (a.T) a.T[p] = T[j];
         if (a.last) a.last[p] = last[j];
     }
-    if (STATS) {
-        *cnt_val += nval;
-        *cnt_rend += nrend;
-    }
 }
 
 template <bool STATS, int NS>
-__device__ inline void alpha_tile(const CompositeArgs& a, int tile, int s0, int lane, GRec* lds,
-                                  unsigned long long* cnt_val, unsigned long long* cnt_rend) {
+__device__ inline void alpha_tile(const CompositeArgs& a, int tile, int s0, int lane, GRec* lds, Counters& cn) {
     const int tx0 = (tile % a.k.TX) * kTile, ty0 = (tile / a.k.TX) * kTile;
     const int px = tx0 + (lane & 15), py0 = ty0 + 4 * s0 + (lane >> 4);
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
@@ -251,7 +254,6 @@ __device__ inline void alpha_tile(const CompositeArgs& a, int tile, int s0, int 
     float T[NS], C0[NS], C1[NS], C2[NS];
     int32_t last[NS];
     bool act[NS];
-    uint32_t nval = 0, nrend = 0;
 #pragma unroll
     for (int j = 0; j < NS; j++) {
         T[j] = 1.0f; C0[j] = C1[j] = C2[j] = 0.0f; last[j] = 0;
@@ -300,8 +302,12 @@ __device__ inline void alpha_tile(const CompositeArgs& a, int tile, int s0, int 
                 const uint32_t ry = ry0 + 4u * j;
                 const float dy = (float)(int)ry + e.oy;
                 const float pw = fmaf(dy, fmaf(e.cc, dy, t1), t0);
-                const bool hit = inx && ry <= e.wy && pw >= th;
-                if (STATS) nval += hit;
+                const bool inbox = inx && ry <= e.wy;
+                const bool hit = inbox && pw >= th;
+                if (STATS) {
+                    cn.val += hit;
+                    cn.box += inbox && act[j];
+                }
                 if (hit && act[j]) {
                     const float al = fminf(amax, __builtin_amdgcn_exp2f(pw));
                     const float w = al * T[j];
@@ -310,7 +316,10 @@ __device__ inline void alpha_tile(const CompositeArgs& a, int tile, int s0, int 
                     C2[j] = fmaf(w, e.b, C2[j]);
                     T[j] -= w;
                     last[j] = (int32_t)(pos + m - start + 1);
-                    if (STATS) nrend++;
+                    if (STATS) {
+                        cn.rend++;
+                        cn.cellhit++;
+                    }
                 }
             }
         }
@@ -329,10 +338,6 @@ __device__ inline void alpha_tile(const CompositeArgs& a, int tile, int s0, int 
         if (a.T) a.T[p] = T[j];
         if (a.last) a.last[p] = last[j];
     }
-    if (STATS) {
-        *cnt_val += nval;
-        *cnt_rend += nrend;
-    }
 }
 
 // Persistent wavefronts: each takes the next work item of a queue that lists
@@ -344,7 +349,7 @@ __global__ __launch_bounds__(256) void k_composite(CompositeArgs a) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     GRec* lds = s_rec[wave];
     const uint32_t nitems = a.queue[1];
-    unsigned long long cv = 0, cr = 0;
+    Counters cn;
     for (;;) {
         uint32_t t = 0;
         if (lane == 0) t = atomicAdd(a.queue, 1u);
@@ -354,19 +359,21 @@ __global__ __launch_bounds__(256) void k_composite(CompositeArgs a) {
         const int tile = (int)(item >> 3), mode = (int)(item & 7u);
         if (DUPLEX) {
             if (mode == 0)
-                duplex_tile<STATS, 4>(a, tile, 0, lane, lds, &cv, &cr);
+                duplex_tile<STATS, 4>(a, tile, 0, lane, lds, cn);
             else
-                duplex_tile<STATS, 1>(a, tile, mode - 4, lane, lds, &cv, &cr);
+                duplex_tile<STATS, 1>(a, tile, mode - 4, lane, lds, cn);
         } else {
             if (mode == 0)
-                alpha_tile<STATS, 4>(a, tile, 0, lane, lds, &cv, &cr);
+                alpha_tile<STATS, 4>(a, tile, 0, lane, lds, cn);
             else
-                alpha_tile<STATS, 1>(a, tile, mode - 4, lane, lds, &cv, &cr);
+                alpha_tile<STATS, 1>(a, tile, mode - 4, lane, lds, cn);
         }
     }
     if (STATS) {
-        atomicAdd(&a.counters[0], cv);
-        atomicAdd(&a.counters[1], cr);
+        atomicAdd(&a.counters[0], (unsigned long long)cn.val);
+        atomicAdd(&a.counters[1], (unsigned long long)cn.rend);
+        atomicAdd(&a.counters[2], (unsigned long long)cn.box);
+        atomicAdd(&a.counters[3], (unsigned long long)cn.cellhit);
     }
 }
 
@@ -416,10 +423,15 @@ static unsigned persistent_grid(int tiles) {
     return (unsigned)((waves + kWaves - 1) / kWaves);
 }
 
-static void launch_composite(hipStream_t st, const CompositeArgs& a, bool duplex) {
+void launch_tile_order(hipStream_t st, const CompositeArgs& a) {
     const int tiles = a.k.TX * a.k.TY;
     if (tiles <= 0) return;
     hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, st, a.ranges, tiles, a.order, a.queue);
+}
+
+static void launch_composite(hipStream_t st, const CompositeArgs& a, bool duplex) {
+    const int tiles = a.k.TX * a.k.TY;
+    if (tiles <= 0) return;
     const dim3 g(persistent_grid(tiles)), b(256);
     if (duplex) {
         if (a.counters)

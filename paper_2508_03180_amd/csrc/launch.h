@@ -13,13 +13,31 @@ void launch_gauss_project(hipStream_t st, int M, int K, const float* means, cons
                           const OptK& o, const uint32_t* cell_ntiles, GRec* recs, uint64_t* grect,
                           uint32_t* gdepth, uint32_t* gntiles);
 
+// Look-back status words carry a 30-bit epoch (never 0) that changes with
+// every scan or sort pass, so status buffers are zeroed once at allocation
+// and never cleared again.
+inline uint32_t next_epoch(uint32_t* counter) { return 1u + (++*counter % ((1u << 30) - 1u)); }
+
 // Exclusive scan of n u32 values; *total receives the sum.  status needs
-// scan_status_words(n) words, ticket one word; both are cleared here.
+// scan_status_words(n) 64-bit words; *ticket must be zero.
 size_t scan_status_words(int64_t n);
 void launch_exclusive_scan(hipStream_t st, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
-                           uint32_t* status, uint32_t* ticket, int* err);
+                           uint64_t* status, uint32_t* epoch, uint32_t* ticket, int* err);
 
 void launch_fill_u32(hipStream_t st, uint32_t* p, uint32_t v, size_t n);
+
+// Zeroes up to 8 small u32 buffers in one launch (graph-safe: no memset nodes).
+struct ClearList {
+    uint32_t* p[8];
+    size_t n[8];
+    int count = 0;
+    void add(uint32_t* ptr, size_t words) {
+        p[count] = ptr;
+        n[count] = words;
+        count++;
+    }
+};
+void launch_clear(hipStream_t st, const ClearList& l);
 
 // One key per (primitive, touched tile): key = tile << 32 | depth bits,
 // value = primitive id, written at offsets[p] in row-major tile order.
@@ -27,22 +45,25 @@ void launch_emit_keys(hipStream_t st, int P, const uint32_t* ntiles, const uint3
                       const uint64_t* prect, const uint32_t* depth, int TX, uint32_t cap, uint64_t* keys,
                       uint32_t* vals, int* err);
 
-// [start, end) per tile of the sorted keys; ranges must hold 2*tiles words.
+// [start, end) per tile of the sorted keys; ranges (2 words per tile) must
+// be zero beforehand (tiles without keys keep [0, 0)).
 void launch_tile_ranges(hipStream_t st, const uint64_t* keys, const uint32_t* n_ptr, uint32_t cap,
-                        uint32_t* ranges, int tiles);
+                        uint32_t* ranges);
 
 // Onesweep LSD radix sort of (u64 key, u32 value) pairs on the low `bits`
 // bits.  The count is read on the device from *n_ptr (clamped to cap).
 // Returns true when the sorted data ends in (k1, v1), false for (k0, v0).
+// hist (8 x 256 words) and tickets (8 words) must be zero beforehand.
 struct SortScratch {
     uint32_t* hist;     // [8][256]
-    uint32_t* status;   // sort_status_words(cap)
+    uint64_t* status;   // sort_status_words(cap) look-back words
     uint32_t* tickets;  // [8]
 };
 int sort_passes(int bits);
-size_t sort_status_words(int64_t cap, int passes);
+size_t sort_status_words(int64_t cap);
 bool launch_radix_sort(hipStream_t st, uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1,
-                       const uint32_t* n_ptr, uint32_t cap, int bits, const SortScratch& s, int* err);
+                       const uint32_t* n_ptr, uint32_t cap, int bits, const SortScratch& s, uint32_t* epoch,
+                       int* err);
 
 struct CompositeArgs {
     const uint32_t* ranges;
@@ -56,10 +77,13 @@ struct CompositeArgs {
     float* D;
     float* T;
     int32_t* last;
-    unsigned long long* counters;  // [2]: n_val, n_rendered (stats mode), nullable
+    unsigned long long* counters;  // [4]: n_val, n_rendered, n_box, n_cell_hits (stats mode), nullable
     uint32_t* order;               // [4 * tiles] scratch: heaviest-first work items
     uint32_t* queue;               // [2] scratch: work-queue head, item count
 };
+// Work queue of the compositor (heaviest-first tile / strip items); must
+// precede launch_composite_*.
+void launch_tile_order(hipStream_t st, const CompositeArgs& a);
 void launch_composite_duplex(hipStream_t st, const CompositeArgs& a);
 void launch_composite_alpha(hipStream_t st, const CompositeArgs& a);
 

@@ -11,13 +11,14 @@ namespace dgs {
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanPart = kScanThreads * kScanItems;
-constexpr uint32_t kFlagAgg = 1u << 30, kFlagInc = 2u << 30, kValMask = (1u << 30) - 1;
 constexpr int kSpinLimit = 1 << 22;
 
-__device__ inline uint32_t ld_status(const uint32_t* p) {
+// status word: epoch << 34 | flag << 32 | value; flag 1 = partition total,
+// 2 = inclusive prefix.  Words from an older epoch read as unpublished.
+__device__ inline uint64_t ld_status(const uint64_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ inline void st_status(uint32_t* p, uint32_t v) {
+__device__ inline void st_status(uint64_t* p, uint64_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -36,8 +37,8 @@ __device__ inline uint32_t wave_incl_scan(uint32_t v) {
 // a partition only ever waits for partitions that are already running.
 __global__ __launch_bounds__(kScanThreads) void k_scan_excl(const uint32_t* __restrict__ in,
                                                              uint32_t* __restrict__ out, int64_t n,
-                                                             uint32_t* __restrict__ total, uint32_t* status,
-                                                             uint32_t* ticket, int* err) {
+                                                             uint32_t* __restrict__ total, uint64_t* status,
+                                                             uint32_t epoch, uint32_t* ticket, int* err) {
     __shared__ uint32_t s_part, s_wsum[kScanThreads / 64], s_excl;
     const int nparts = (int)((n + kScanPart - 1) / kScanPart);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -63,24 +64,26 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_excl(const uint32_t* __re
             btotal += s;
         }
         if (tid == 0) {
+            const uint64_t tag = (uint64_t)epoch << 34;
             uint32_t excl = 0;
             if (part == 0) {
-                st_status(&status[0], kFlagInc | (btotal & kValMask));
+                st_status(&status[0], tag | (2ull << 32) | btotal);
             } else {
-                st_status(&status[part], kFlagAgg | (btotal & kValMask));
+                st_status(&status[part], tag | (1ull << 32) | btotal);
                 int j = part - 1, spins = 0;
                 while (j >= 0) {
-                    uint32_t s = ld_status(&status[j]);
-                    if ((s & ~kValMask) == 0) {
+                    const uint64_t s = ld_status(&status[j]);
+                    const uint32_t flag = (uint32_t)(s >> 32) & 3u;
+                    if ((uint32_t)(s >> 34) != epoch || flag == 0) {
                         if (++spins > kSpinLimit) { atomicOr(err, 1 << kErrTimeout); break; }
                         __builtin_amdgcn_s_sleep(1);
                         continue;
                     }
-                    excl += s & kValMask;
-                    if (s & kFlagInc) break;
+                    excl += (uint32_t)s;
+                    if (flag == 2) break;
                     j--;
                 }
-                st_status(&status[part], kFlagInc | ((excl + btotal) & kValMask));
+                st_status(&status[part], tag | (2ull << 32) | (excl + btotal));
             }
             s_excl = excl;
             if (part == nparts - 1) *total = excl + btotal;
@@ -111,16 +114,30 @@ void launch_fill_u32(hipStream_t st, uint32_t* p, uint32_t v, size_t n) {
 size_t scan_status_words(int64_t n) { return (size_t)((n + kScanPart - 1) / kScanPart) + 1; }
 
 void launch_exclusive_scan(hipStream_t st, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
-                           uint32_t* status, uint32_t* ticket, int* err) {
+                           uint64_t* status, uint32_t* epoch, uint32_t* ticket, int* err) {
     if (n <= 0) {
         launch_fill_u32(st, total, 0u, 1);
         return;
     }
-    size_t nparts = (size_t)((n + kScanPart - 1) / kScanPart);
-    launch_fill_u32(st, status, 0u, nparts);
-    launch_fill_u32(st, ticket, 0u, 1);
-    unsigned grid = (unsigned)(nparts < 1024 ? nparts : 1024);
-    hipLaunchKernelGGL(k_scan_excl, dim3(grid), dim3(kScanThreads), 0, st, in, out, n, total, status, ticket, err);
+    const size_t nparts = (size_t)((n + kScanPart - 1) / kScanPart);
+    const unsigned grid = (unsigned)(nparts < 1024 ? nparts : 1024);
+    hipLaunchKernelGGL(k_scan_excl, dim3(grid), dim3(kScanThreads), 0, st, in, out, n, total, status,
+                       next_epoch(epoch), ticket, err);
+}
+
+__global__ void k_clear(ClearList l) {
+    const size_t gid = blockIdx.x * (size_t)blockDim.x + threadIdx.x, stride = (size_t)gridDim.x * blockDim.x;
+    for (int b = 0; b < l.count; b++)
+        for (size_t i = gid; i < l.n[b]; i += stride) l.p[b][i] = 0u;
+}
+
+void launch_clear(hipStream_t st, const ClearList& l) {
+    size_t most = 0;
+    for (int b = 0; b < l.count; b++) most = l.n[b] > most ? l.n[b] : most;
+    if (most == 0) return;
+    unsigned grid = (unsigned)((most + 255) / 256);
+    if (grid > 256) grid = 256;
+    hipLaunchKernelGGL(k_clear, dim3(grid), dim3(256), 0, st, l);
 }
 
 // ---------------------------------------------------------------- keys
@@ -171,8 +188,7 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t* __restrict_
 }
 
 void launch_tile_ranges(hipStream_t st, const uint64_t* keys, const uint32_t* n_ptr, uint32_t cap,
-                        uint32_t* ranges, int tiles) {
-    launch_fill_u32(st, ranges, 0u, 2 * (size_t)tiles);
+                        uint32_t* ranges) {
     unsigned grid = (unsigned)((cap + 255) / 256);
     if (grid > 2048) grid = 2048;
     if (grid == 0) grid = 1;

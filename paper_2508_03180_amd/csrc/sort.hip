@@ -1,12 +1,15 @@
 // Onesweep LSD radix sort of (u64 key, u32 value) pairs, 8-bit digits.
 //
 // One histogram sweep counts the digits of every pass; each pass is then a
-// single read and a single scatter of the data.  Within a pass, persistent
-// workgroups take fixed-size partitions from a ticket counter; each
-// partition ranks its keys stably in LDS (wavefront ballots match equal
-// digits), publishes its per-digit counts and resolves its global offsets by
-// decoupled look-back over the partitions before it.  The key count is read
-// on the device, so a frame needs no host round trip.
+// single read and a single write of the data.  Within a pass, persistent
+// workgroups take fixed-size partitions from a ticket counter in launch
+// order; a partition ranks its keys stably (wavefront ballots match equal
+// digits), publishes its per-digit counts and resolves its global offsets
+// by decoupled look-back over the partitions before it, then writes its
+// keys digit-grouped from LDS so that every store covers a contiguous run.
+// Look-back status words carry an epoch, so no clearing is needed between
+// passes or sorts.  The key count is read on the device: a frame needs no
+// host round trip.
 #include "common.h"
 #include "launch.h"
 
@@ -14,16 +17,16 @@ namespace dgs {
 
 constexpr int kSortThreads = 256;
 constexpr int kSortWaves = kSortThreads / 64;
-constexpr int kSortItems = 12;
-constexpr int kSortPart = kSortThreads * kSortItems;
-constexpr uint32_t kSFlagAgg = 1u << 30, kSFlagInc = 2u << 30, kSValMask = (1u << 30) - 1;
+constexpr int kSortItems = 16;
+constexpr int kSortPart = kSortThreads * kSortItems;  // 4096 keys per partition
+constexpr int kHistBlocks = 128;
 constexpr int kSortSpinLimit = 1 << 22;
 
 int sort_passes(int bits) { return (bits + 7) / 8; }
 
 static size_t max_parts(int64_t cap) { return (size_t)((cap + kSortPart - 1) / kSortPart); }
 
-size_t sort_status_words(int64_t cap, int passes) { return max_parts(cap) * 256 * (size_t)passes; }
+size_t sort_status_words(int64_t cap) { return max_parts(cap) * 256; }
 
 __global__ __launch_bounds__(256) void k_radix_hist(const uint64_t* __restrict__ keys,
                                                     const uint32_t* __restrict__ n_ptr, uint32_t cap, int passes,
@@ -35,7 +38,7 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint64_t* __restrict__
     uint32_t n = *n_ptr;
     if (n > cap) n = cap;
     for (uint32_t i = blockIdx.x * kSortThreads + tid; i < n; i += gridDim.x * kSortThreads) {
-        uint64_t k = keys[i];
+        const uint64_t k = keys[i];
         for (int p = 0; p < passes; p++) atomicAdd(&sh[wave][p][(uint32_t)(k >> (8 * p)) & 255u], 1u);
     }
     __syncthreads();
@@ -46,15 +49,16 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint64_t* __restrict__
     }
 }
 
-// In place: per pass, counts -> exclusive digit offsets.
+// In place: per pass, digit counts -> exclusive digit offsets.
 __global__ __launch_bounds__(256) void k_radix_hist_scan(uint32_t* hist, int passes) {
     __shared__ uint32_t s_w[kSortWaves];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int p = 0; p < passes; p++) {
-        uint32_t v = hist[p * 256 + tid], x = v;
+        const uint32_t v = hist[p * 256 + tid];
+        uint32_t x = v;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
-            uint32_t u = __shfl_up(x, d, 64);
+            const uint32_t u = __shfl_up(x, d, 64);
             if (lane >= d) x += u;
         }
         if (lane == 63) s_w[wave] = x;
@@ -66,16 +70,46 @@ __global__ __launch_bounds__(256) void k_radix_hist_scan(uint32_t* hist, int pas
     }
 }
 
-__device__ inline uint32_t lds_status(const uint32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline void sts_status(uint32_t* p, uint32_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Number of set bits of `mask` at lanes below this one.
 __device__ inline uint32_t lanes_below(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// status word: epoch << 34 | flag << 32 | count; flag 1 = partition total,
+// 2 = inclusive prefix over this and every earlier partition
+__device__ inline uint64_t ld_st64(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_st64(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Exclusive prefix of `col` over partitions [0, part) by decoupled look-back
+// with up to four status words in flight.  Returns false on a timeout.
+__device__ inline bool look_back(const uint64_t* status, size_t stride, int part, uint32_t epoch, uint32_t* excl) {
+    uint32_t sum = 0;
+    int j = part - 1, spins = 0;
+    while (j >= 0) {
+        uint64_t s[4];
+#pragma unroll
+        for (int i = 0; i < 4; i++) s[i] = j - i >= 0 ? ld_st64(status + (size_t)(j - i) * stride) : 0;
+        int i = 0;
+        bool done = false;
+        for (; i < 4; i++) {
+            if (j - i < 0) { done = true; break; }
+            if ((uint32_t)(s[i] >> 34) != epoch || ((s[i] >> 32) & 3u) == 0) break;  // not published yet
+            sum += (uint32_t)s[i];
+            if (((s[i] >> 32) & 3u) == 2u) { done = true; break; }
+        }
+        if (done) break;
+        if (i == 0) {
+            if (++spins > kSortSpinLimit) { *excl = sum; return false; }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        j -= i;
+    }
+    *excl = sum;
+    return true;
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __restrict__ kin,
@@ -83,10 +117,15 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
                                                            uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                            const uint32_t* __restrict__ n_ptr, uint32_t cap,
                                                            int shift, const uint32_t* __restrict__ goff,
-                                                           uint32_t* status, uint32_t* ticket, int* err) {
-    __shared__ uint32_t s_part;
+                                                           uint64_t* status, uint32_t epoch, uint32_t* ticket,
+                                                           int* err) {
+    __shared__ uint64_t s_key[kSortPart];
+    __shared__ uint32_t s_val[kSortPart];
     __shared__ uint32_t s_cnt[kSortWaves][256];  // per-wave digit counts, then per-wave offsets
-    __shared__ uint32_t s_base[256];              // global start of each digit for this partition
+    __shared__ uint32_t s_lstart[256];            // start of each digit in the partition-local order
+    __shared__ uint32_t s_gbase[256];             // global start of each digit minus its local start
+    __shared__ uint32_t s_wsum[kSortWaves];
+    __shared__ uint32_t s_part;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     uint32_t n = *n_ptr;
     if (n > cap) n = cap;
@@ -97,12 +136,13 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
         __syncthreads();
         const uint32_t part = s_part;
         if (part >= nparts) break;
-        const uint32_t wbase = part * kSortPart + wave * (kSortItems * 64);
+        const uint32_t pbase = part * kSortPart;
+        const uint32_t wbase = pbase + wave * (kSortItems * 64);
         uint64_t k[kSortItems];
         uint32_t v[kSortItems], rank[kSortItems];
 #pragma unroll
         for (int i = 0; i < kSortItems; i++) {
-            uint32_t idx = wbase + i * 64 + lane;
+            const uint32_t idx = wbase + i * 64 + lane;
             if (idx < n) {
                 k[i] = kin[idx];
                 v[i] = vin[idx];
@@ -127,82 +167,78 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
             __builtin_amdgcn_wave_barrier();
         }
         __syncthreads();
-        // thread d: partition total of digit d, per-wave exclusive offsets
-        {
-            const int d = tid;
-            uint32_t tot = 0;
+        // thread d: partition total of digit d, per-wave offsets, local start
+        const int d = tid;
+        uint32_t tot = 0;
 #pragma unroll
-            for (int w = 0; w < kSortWaves; w++) {
-                uint32_t c = s_cnt[w][d];
-                s_cnt[w][d] = tot;
-                tot += c;
-            }
-            uint32_t* my = status + (size_t)part * 256 + d;
-            uint32_t excl = 0;
-            if (part == 0) {
-                sts_status(my, kSFlagInc | tot);
-            } else {
-                sts_status(my, kSFlagAgg | tot);
-                int j = (int)part - 1, spins = 0;
-                while (j >= 0) {
-                    uint32_t s = lds_status(status + (size_t)j * 256 + d);
-                    if ((s & ~kSValMask) == 0) {
-                        if (++spins > kSortSpinLimit) { atomicOr(err, 1 << kErrTimeout); break; }
-                        __builtin_amdgcn_s_sleep(1);
-                        continue;
-                    }
-                    excl += s & kSValMask;
-                    if (s & kSFlagInc) break;
-                    j--;
-                }
-                sts_status(my, kSFlagInc | ((excl + tot) & kSValMask));
-            }
-            s_base[d] = goff[d] + excl;
+        for (int w = 0; w < kSortWaves; w++) {
+            const uint32_t c = s_cnt[w][d];
+            s_cnt[w][d] = tot;
+            tot += c;
+        }
+        uint32_t x = tot;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t u = __shfl_up(x, o, 64);
+            if (lane >= o) x += u;
+        }
+        if (lane == 63) s_wsum[wave] = x;
+        // publish this partition's totals, then look back for the prefix
+        uint64_t* my = status + (size_t)part * 256 + d;
+        const uint64_t tag = (uint64_t)epoch << 34;
+        uint32_t excl = 0;
+        if (part == 0) {
+            st_st64(my, tag | (2ull << 32) | tot);
+        } else {
+            st_st64(my, tag | (1ull << 32) | tot);
+            if (!look_back(status + d, 256, (int)part, epoch, &excl)) atomicOr(err, 1 << kErrTimeout);
+            st_st64(my, tag | (2ull << 32) | (excl + tot));
         }
         __syncthreads();
+        uint32_t lstart = x - tot;
+        for (int w = 0; w < wave; w++) lstart += s_wsum[w];
+        s_lstart[d] = lstart;
+        s_gbase[d] = goff[d] + excl - lstart;
+        __syncthreads();
+        // partition-local digit-grouped order in LDS
 #pragma unroll
         for (int i = 0; i < kSortItems; i++) {
             if (wbase + i * 64 + lane < n) {
-                const uint32_t d = (uint32_t)(k[i] >> shift) & 255u;
-                const uint32_t pos = s_base[d] + s_cnt[wave][d] + rank[i];
-                kout[pos] = k[i];
-                vout[pos] = v[i];
+                const uint32_t dd = (uint32_t)(k[i] >> shift) & 255u;
+                const uint32_t lp = s_lstart[dd] + s_cnt[wave][dd] + rank[i];
+                s_key[lp] = k[i];
+                s_val[lp] = v[i];
+            }
+        }
+        __syncthreads();
+        const uint32_t cnt = n - pbase < (uint32_t)kSortPart ? n - pbase : (uint32_t)kSortPart;
+        for (uint32_t i = tid; i < cnt; i += kSortThreads) {
+            const uint64_t kk = s_key[i];
+            const uint32_t pos = s_gbase[(uint32_t)(kk >> shift) & 255u] + i;
+            if (pos < n) {  // always true unless a look-back wait timed out
+                kout[pos] = kk;
+                vout[pos] = s_val[i];
             }
         }
         __syncthreads();  // LDS is reused by the next partition
     }
 }
 
-__global__ void k_clear_sort(uint32_t* status, size_t words, const uint32_t* n_ptr, uint32_t cap, int passes,
-                             size_t pass_stride, uint32_t* hist, uint32_t* tickets) {
-    uint32_t n = *n_ptr;
-    if (n > cap) n = cap;
-    const size_t used = (size_t)((n + kSortPart - 1) / kSortPart) * 256;
-    const size_t gid = blockIdx.x * (size_t)blockDim.x + threadIdx.x, stride = (size_t)gridDim.x * blockDim.x;
-    for (int p = 0; p < passes; p++)
-        for (size_t i = gid; i < used; i += stride) status[p * pass_stride + i] = 0;
-    for (size_t i = gid; i < (size_t)passes * 256; i += stride) hist[i] = 0;
-    if (gid < 8) tickets[gid] = 0;
-}
-
 bool launch_radix_sort(hipStream_t st, uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1,
-                       const uint32_t* n_ptr, uint32_t cap, int bits, const SortScratch& s, int* err) {
+                       const uint32_t* n_ptr, uint32_t cap, int bits, const SortScratch& s, uint32_t* epoch,
+                       int* err) {
     const int passes = sort_passes(bits);
     if (passes <= 0 || cap == 0) return false;
-    const size_t pass_stride = max_parts(cap) * 256;
-    hipLaunchKernelGGL(k_clear_sort, dim3(512), dim3(256), 0, st, s.status, pass_stride * passes, n_ptr, cap,
-                       passes, pass_stride, s.hist, s.tickets);
-    unsigned hgrid = (unsigned)((cap + kSortThreads * 16 - 1) / (kSortThreads * 16));
-    if (hgrid > 1024) hgrid = 1024;
-    hipLaunchKernelGGL(k_radix_hist, dim3(hgrid), dim3(kSortThreads), 0, st, k0, n_ptr, cap, passes, s.hist);
+    hipLaunchKernelGGL(k_radix_hist, dim3(kHistBlocks), dim3(kSortThreads), 0, st, k0, n_ptr, cap, passes, s.hist);
     hipLaunchKernelGGL(k_radix_hist_scan, dim3(1), dim3(256), 0, st, s.hist, passes);
-    size_t parts = max_parts(cap);
-    unsigned grid = (unsigned)(parts < 2048 ? parts : 2048);
+    const size_t parts = max_parts(cap);
+    const unsigned grid = (unsigned)(parts < 1024 ? parts : 1024);
     uint64_t *ki = k0, *ko = k1;
     uint32_t *vi = v0, *vo = v1;
     for (int p = 0; p < passes; p++) {
+        const uint32_t ep = next_epoch(epoch);
         hipLaunchKernelGGL(k_onesweep, dim3(grid), dim3(kSortThreads), 0, st, ki, vi, ko, vo, n_ptr, cap, 8 * p,
-                           s.hist + p * 256, s.status + p * pass_stride, s.tickets + p, err);
+                           s.hist + p * 256, s.status, ep, s.tickets + p, err);
         uint64_t* tk = ki; ki = ko; ko = tk;
         uint32_t* tv = vi; vi = vo; vo = tv;
     }

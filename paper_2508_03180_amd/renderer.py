@@ -155,7 +155,8 @@ class Renderer:
     def stats(self):
         s = capi.dgs_get_stats(self.ctx)
         return dict(num_keys=s.num_keys, key_capacity=s.key_capacity, n_val=s.n_val, n_rendered=s.n_rendered,
-                    device_error=s.device_error, sort_passes=s.sort_passes)
+                    n_box=s.n_box, n_cell_hits=s.n_cell_hits, device_error=s.device_error,
+                    sort_passes=s.sort_passes)
 
     def read_lists(self, tiles):
         n = self.stats()["num_keys"]
