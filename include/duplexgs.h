@@ -110,6 +110,22 @@ typedef struct {
     int32_t* last;     /* [H][W] 1 + tile-list position of the last contributing entry (0 = none), nullable */
 } dgs_image;
 
+/* Gradients: caller-owned device buffers in the scene's planar layout.  The
+ * library ADDS into them, so zero them first.  Cell scales and rotations only
+ * decide which tiles a cell is listed in (a discrete choice), so they get no
+ * gradient; cell positions get the gradient through the view direction of
+ * v_n only. */
+typedef struct {
+    float* d_means;     /* [3][M] */
+    float* d_scales;    /* [3][M] */
+    float* d_rots;      /* [4][M] (w, x, y, z) */
+    float* d_opacities; /* [M] */
+    float* d_sh;        /* [C][3][M] */
+    float* d_cell_v_sh; /* [Cv][N] */
+    float* d_cell_pos;  /* [3][N] */
+    float* d_mean2d;    /* [2][M] gradient of the projected means (densification statistics), nullable */
+} dgs_grads;
+
 typedef struct {
     int64_t num_keys;      /* (tile, primitive) keys of the last render */
     int64_t key_capacity;  /* reserved key capacity */
@@ -147,6 +163,20 @@ dgs_status dgs_reserve(dgs_ctx ctx, int64_t max_keys, int64_t max_prims, int64_t
  * dgs_render_backward and the dgs_read_* calls). */
 dgs_status dgs_render(dgs_ctx ctx, const dgs_scene* scene, const dgs_camera* cam, const dgs_render_opts* opts,
                       const dgs_image* out);
+
+/* Backward of the hybrid renderer (Sec. V-A eqs. hybrid_renderer and
+ * dulpex_T, with w_n = v_n T_n): given dL/dC (grad_color, [3][H][W]) and
+ * optionally dL/dD (grad_weight_sum, [H][W], nullable), adds dL/d(parameters)
+ * into *grads.  It replays the per-tile cell lists, projected Gaussians and
+ * v_n kept by the context from its most recent dgs_render, which must have
+ * rendered the same scene, camera and options in DGS_MODE_DUPLEX into `fwd`
+ * with weight_sum, final_T and last all non-NULL (they are read here).
+ * Returns DGS_ERR_UNSUPPORTED for DGS_MODE_ALPHA and DGS_ERR_INVALID_ARG when
+ * the sizes do not match the last render.  Gradients are summed with float
+ * atomics, so their last bits may differ between runs. */
+dgs_status dgs_render_backward(dgs_ctx ctx, const dgs_scene* scene, const dgs_camera* cam,
+                               const dgs_render_opts* opts, const dgs_image* fwd, const float* grad_color,
+                               const float* grad_weight_sum, const dgs_grads* grads);
 
 /* Waits for the context's stream; returns the first device-side error since
  * the previous dgs_sync (DGS_ERR_CAPACITY, DGS_ERR_TIMEOUT) or DGS_OK. */

@@ -51,6 +51,12 @@ class dgs_image(C.Structure):
     _fields_ = [("color", C.c_void_p), ("weight_sum", C.c_void_p), ("final_T", C.c_void_p), ("last", C.c_void_p)]
 
 
+class dgs_grads(C.Structure):
+    _fields_ = [("d_means", C.c_void_p), ("d_scales", C.c_void_p), ("d_rots", C.c_void_p),
+                ("d_opacities", C.c_void_p), ("d_sh", C.c_void_p), ("d_cell_v_sh", C.c_void_p),
+                ("d_cell_pos", C.c_void_p), ("d_mean2d", C.c_void_p)]
+
+
 class dgs_stats(C.Structure):
     _fields_ = [("num_keys", C.c_int64), ("key_capacity", C.c_int64), ("n_val", C.c_int64),
                 ("n_rendered", C.c_int64), ("n_box", C.c_int64), ("n_cell_hits", C.c_int64),
@@ -68,6 +74,9 @@ _SIGS = {
     "dgs_reserve": (C.c_int, [dgs_ctx, C.c_int64, C.c_int64, C.c_int64]),
     "dgs_render": (C.c_int, [dgs_ctx, C.POINTER(dgs_scene), C.POINTER(dgs_camera), C.POINTER(dgs_render_opts),
                              C.POINTER(dgs_image)]),
+    "dgs_render_backward": (C.c_int, [dgs_ctx, C.POINTER(dgs_scene), C.POINTER(dgs_camera),
+                                      C.POINTER(dgs_render_opts), C.POINTER(dgs_image), C.c_void_p, C.c_void_p,
+                                      C.POINTER(dgs_grads)]),
     "dgs_sync": (C.c_int, [dgs_ctx]),
     "dgs_get_stats": (C.c_int, [dgs_ctx, C.POINTER(dgs_stats)]),
     "dgs_last_error": (C.c_char_p, [dgs_ctx]),
@@ -143,6 +152,11 @@ def dgs_reserve(ctx, max_keys, max_prims, max_tiles):
 
 def dgs_render(ctx, scene, cam, opts, image):
     return lib().dgs_render(ctx, C.byref(scene), C.byref(cam), C.byref(opts), C.byref(image))
+
+
+def dgs_render_backward(ctx, scene, cam, opts, image, grad_color_ptr, grad_weight_sum_ptr, grads):
+    return lib().dgs_render_backward(ctx, C.byref(scene), C.byref(cam), C.byref(opts), C.byref(image),
+                                     C.c_void_p(grad_color_ptr), C.c_void_p(grad_weight_sum_ptr), C.byref(grads))
 
 
 def dgs_sync(ctx):

@@ -1,0 +1,465 @@
+// Backward pass of the hybrid renderer (Duplex mode).
+//
+// Forward per pixel (Sec. V-A, eq. hybrid_renderer, w_n = v_n T_n,
+// eq. dulpex_T): for processed cells n,
+//     A_n = sum_k a_k c_k,  B_n = sum_k a_k,  P_n = prod_k (1 - v_n a_k),
+//     N = sum_n v_n T_n A_n,  D = sum_n v_n T_n B_n,  T_{n+1} = T_n P_n,
+//     C = N / D.
+// With g_N = dL/dC / D and g_D = -(dL/dC . C) / D + dL/dD:
+//     dL/dA_n = v_n T_n g_N,  dL/dB_n = v_n T_n g_D,
+//     dL/dT_n = v_n (g_N . A_n + g_D B_n) + P_n dL/dT_{n+1},
+//     dL/dP_n = T_n dL/dT_{n+1},   dP_n/da_k = -v_n P_n / (1 - v_n a_k),
+//     dL/dv_n = T_n (g_N . A_n + g_D B_n) - dL/dP_n sum_k a_k P_n / (1 - v_n a_k).
+// The walk replays the forward's per-tile cell lists back to front from the
+// last contributing cell, recovering T_n = T_{n+1} / P_n (every factor
+// 1 - v a >= 1 - alpha_max > 0).  Per-Gaussian screen-space gradients
+// (mean, conic, sigma, colour) and per-cell dL/dv are reduced over each
+// wavefront and added atomically; a second kernel carries them through the
+// projection (EWA covariance, quaternion, scales, SH colour and its view
+// direction) and a third through v_n = sigmoid(SH(d_n)).
+#include "common.h"
+#include "launch.h"
+
+namespace dgs {
+
+constexpr int kBwdWaves = 4;
+constexpr float kLog2e = 1.4426950408889634f;
+
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+struct BRec {
+    float ox, oy, ca, cb, cc, lo;  // as stored: log2(sigma G') = lo + ca dx^2 + cb dx dy + cc dy^2
+    float A, B, C, sigma, r, g, b;  // natural-domain conic and sigma, for the gradients
+    int x0, y0;
+    uint32_t wx, wy;
+};
+
+// log2(sigma G') with exactly the forward's operations, so every gate
+// decision (box, alpha_min) and every alpha is reproduced bit for bit.
+__device__ inline float brec_power(const BRec& e, float dx, float dy) {
+    const float t0 = fmaf(e.ca * dx, dx, e.lo);
+    const float t1 = e.cb * dx;
+    return fmaf(dy, fmaf(e.cc, dy, t1), t0);
+}
+
+__device__ inline BRec read_brec(const GRec* lds, int i) {
+    const float4* p = reinterpret_cast<const float4*>(lds + i);
+    const float4 a = p[0], b = p[1], c = p[2];
+    BRec e;
+    e.ox = a.x; e.oy = a.y;
+    e.ca = a.z; e.cb = a.w; e.cc = b.x;
+    // stored log2-domain coefficients -> conic of the dilated covariance
+    e.A = a.z * (-2.0f / kLog2e);
+    e.B = a.w * (-1.0f / kLog2e);
+    e.C = b.x * (-2.0f / kLog2e);
+    e.lo = b.y;
+    e.sigma = __builtin_amdgcn_exp2f(b.y);
+    e.r = b.z; e.g = b.w; e.b = c.x;
+    e.x0 = __float_as_int(c.y);
+    e.y0 = __float_as_int(c.z);
+    const uint32_t wxy = __float_as_uint(c.w);
+    e.wx = wxy & 0xffffu;
+    e.wy = wxy >> 16;
+    return e;
+}
+
+// Backward of one 16x4 strip (one pixel per lane).
+__device__ inline void duplex_strip_bwd(const BwdArgs& a, int tile, int s0, int lane, GRec* lds) {
+    const CamK& k = a.k;
+    const int tx0 = (tile % k.TX) * kTile, ty0 = (tile / k.TX) * kTile;
+    const int px = tx0 + (lane & 15), py = ty0 + 4 * s0 + (lane >> 4);
+    const bool valid = px < k.W && py < k.H;
+    const uint32_t start = a.ranges[2 * tile], len = a.ranges[2 * tile + 1] - start;
+    const int K = a.K;
+    const int cpc = 64 / K;
+    const uint32_t kmask = K == 32 ? 0xffffffffu : ((1u << K) - 1u);
+    const float th = a.o.log2_alpha_min, amax = a.o.alpha_max;
+
+    const size_t HW = (size_t)k.W * k.H, pi = valid ? (size_t)py * k.W + px : 0;
+    int32_t last = 0;
+    float gN0 = 0.f, gN1 = 0.f, gN2 = 0.f, gD = 0.f, T = 1.0f;
+    if (valid) {
+        last = min(a.last[pi], (int32_t)len);  // never walk past this tile's list
+        const float D = a.D[pi];
+        if (D > 0.0f && last > 0) {
+            const float invD = 1.0f / D;
+            const float g0 = a.grad_color[pi], g1 = a.grad_color[HW + pi], g2 = a.grad_color[2 * HW + pi];
+            gN0 = g0 * invD; gN1 = g1 * invD; gN2 = g2 * invD;
+            gD = -(g0 * a.color[pi] + g1 * a.color[HW + pi] + g2 * a.color[2 * HW + pi]) * invD;
+            if (a.grad_D) gD += a.grad_D[pi];
+            T = a.T[pi];
+        } else {
+            last = 0;
+        }
+    }
+    // the wave walks from its largest `last` down to the first cell
+    int maxlast = last;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) maxlast = max(maxlast, __shfl_xor(maxlast, o, 64));
+    float R = 0.0f;  // dL/dT after the current cell
+    for (int hi = maxlast; hi > 0;) {
+        // chunk of cells [lo_c, hi) (list positions relative to start)
+        const int nch = hi < cpc ? hi : cpc;
+        const int lo_c = hi - nch;
+        const int nrec = nch * K;
+        float v_lane = 0.0f;
+        uint32_t sm = 0;
+        if (lane < nrec) {
+            const int c = lane / K, kk = lane - c * K;
+            const uint32_t cell = a.vals[start + lo_c + c];
+            const float4* p = reinterpret_cast<const float4*>(a.recs + (size_t)cell * K + kk);
+            float4* d = reinterpret_cast<float4*>(lds + lane);
+            const float4 r0 = p[0], r1 = p[1], r2 = p[2];
+            d[0] = r0; d[1] = r1; d[2] = r2;
+            if (kk == 0) v_lane = a.cell_v[cell];
+            const int x0 = __float_as_int(r2.y), y0 = __float_as_int(r2.z);
+            const uint32_t wxy = __float_as_uint(r2.w);
+            const int x1 = x0 + (int)(wxy & 0xffffu), y1 = y0 + (int)(wxy >> 16);
+            const int sy0 = ty0 + 4 * s0;
+            sm = (x0 <= tx0 + 15 && x1 >= tx0 && y0 <= sy0 + 3 && y1 >= sy0) ? 1u : 0u;
+        }
+        const uint64_t Bm = __ballot(sm);
+        for (int c = nch - 1; c >= 0; c--) {
+            const int base = c * K;
+            const int p = lo_c + c;  // list position (0-based) of this cell
+            const uint32_t mm = (uint32_t)(Bm >> base) & kmask;
+            const bool act = p < last;
+            if (!mm || !__any(act)) continue;  // no member touches the strip / no lane reaches it
+            const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v_lane), base));
+            const uint32_t cell = a.vals[start + p];
+            // pass 1: cell totals at this pixel (same decisions as the forward)
+            float A0 = 0.f, A1 = 0.f, A2 = 0.f, Bs = 0.f, P = 1.0f;
+            for (uint32_t rem = mm; rem; rem &= rem - 1) {
+                const BRec e = read_brec(lds, base + __builtin_ctz(rem));
+                const uint32_t rx = (uint32_t)(px - e.x0), ry = (uint32_t)(py - e.y0);
+                const float dx = (float)(int)rx + e.ox, dy = (float)(int)ry + e.oy;
+                const float pw = brec_power(e, dx, dy);
+                if (act && rx <= e.wx && ry <= e.wy && pw >= th) {
+                    const float al = fminf(amax, __builtin_amdgcn_exp2f(pw));
+                    A0 = fmaf(al, e.r, A0); A1 = fmaf(al, e.g, A1); A2 = fmaf(al, e.b, A2);
+                    Bs += al;
+                    P = fmaf(-P, v * al, P);
+                }
+            }
+            float dLdA0 = 0.f, dLdA1 = 0.f, dLdA2 = 0.f, dLdB = 0.f, dLdP = 0.f, dv = 0.f;
+            if (act) {
+                const float Tn = T / P;  // transmittance in front of this cell
+                const float w = v * Tn;
+                dLdA0 = w * gN0; dLdA1 = w * gN1; dLdA2 = w * gN2;
+                dLdB = w * gD;
+                const float dLdw = gN0 * A0 + gN1 * A1 + gN2 * A2 + gD * Bs;
+                dLdP = Tn * R;
+                dv = Tn * dLdw;
+                R = v * dLdw + P * R;
+                T = Tn;
+            }
+            // pass 2: per-member gradients, reduced over the wave
+            for (uint32_t rem = mm; rem; rem &= rem - 1) {
+                const int kk = __builtin_ctz(rem);
+                const BRec e = read_brec(lds, base + kk);
+                const uint32_t rx = (uint32_t)(px - e.x0), ry = (uint32_t)(py - e.y0);
+                const float dx = (float)(int)rx + e.ox, dy = (float)(int)ry + e.oy;
+                const float pw = brec_power(e, dx, dy);
+                const bool hit = act && rx <= e.wx && ry <= e.wy && pw >= th;
+                float gu0 = 0.f, gu1 = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, gs = 0.f, gr = 0.f, gg = 0.f, gb = 0.f;
+                if (hit) {
+                    const float sg = __builtin_amdgcn_exp2f(pw);  // sigma G'
+                    const float al = fminf(amax, sg);
+                    const float om = 1.0f - v * al;
+                    dv -= dLdP * al * P / om;
+                    const float dLda = dLdA0 * e.r + dLdA1 * e.g + dLdA2 * e.b + dLdB - dLdP * v * P / om;
+                    gr = dLdA0 * al; gg = dLdA1 * al; gb = dLdA2 * al;
+                    if (sg < amax) {
+                        // alpha = sigma exp(p): dalpha/dp = alpha, dalpha/dsigma = alpha / sigma
+                        const float gp = dLda * al;
+                        gs = dLda * al / e.sigma;
+                        const float y0 = e.A * dx + e.B * dy, y1 = e.B * dx + e.C * dy;
+                        gu0 = gp * y0;  // p depends on the mean through dx = px + 0.5 - u
+                        gu1 = gp * y1;
+                        gA = -0.5f * gp * dx * dx;
+                        gB = -gp * dx * dy;
+                        gC = -0.5f * gp * dy * dy;
+                    }
+                }
+                if (__any(hit)) {
+                    const float s[9] = {gu0, gu1, gA, gB, gC, gs, gr, gg, gb};
+                    const size_t gidx = (size_t)cell * K + kk;
+#pragma unroll
+                    for (int i = 0; i < 9; i++) {
+                        const float t = wave_sum(s[i]);
+                        if (lane == 0 && t != 0.0f) atomicAdd(&a.g2d[(size_t)i * a.M + gidx], t);
+                    }
+                }
+            }
+            const float dvs = wave_sum(dv);
+            if (lane == 0 && dvs != 0.0f) atomicAdd(&a.gv[cell], dvs);
+        }
+        hi = lo_c;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_composite_bwd(BwdArgs a) {
+    __shared__ GRec s_rec[kBwdWaves][64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    GRec* lds = s_rec[wave];
+    const uint32_t nitems = a.queue[1];
+    for (;;) {
+        uint32_t t = 0;
+        if (lane == 0) t = atomicAdd(a.queue, 1u);
+        t = (uint32_t)__shfl((int)t, 0, 64);
+        if (t >= nitems) break;
+        const uint32_t item = a.order[t];
+        duplex_strip_bwd(a, (int)(item >> 3), (int)(item & 3u), lane, lds);
+    }
+}
+
+// ---------------------------------------------------------------- projection
+
+// Real SH basis (as in the forward) and its gradient in the direction.
+__device__ inline void sh_basis_grad(int deg, float x, float y, float z, float* Y, float* gx, float* gy,
+                                     float* gz) {
+    const float c0 = 0.28209479177387814f, c1 = 0.4886025119029199f;
+    Y[0] = c0; gx[0] = gy[0] = gz[0] = 0.f;
+    if (deg < 1) return;
+    Y[1] = -c1 * y; gx[1] = 0.f; gy[1] = -c1; gz[1] = 0.f;
+    Y[2] = c1 * z;  gx[2] = 0.f; gy[2] = 0.f; gz[2] = c1;
+    Y[3] = -c1 * x; gx[3] = -c1; gy[3] = 0.f; gz[3] = 0.f;
+    if (deg < 2) return;
+    const float k4 = 1.0925484305920792f, k6 = 0.31539156525252005f, k8 = 0.5462742152960396f;
+    const float xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = k4 * x * y;                gx[4] = k4 * y;          gy[4] = k4 * x;           gz[4] = 0.f;
+    Y[5] = -k4 * y * z;               gx[5] = 0.f;             gy[5] = -k4 * z;          gz[5] = -k4 * y;
+    Y[6] = k6 * (2.f * zz - xx - yy); gx[6] = -2.f * k6 * x;   gy[6] = -2.f * k6 * y;    gz[6] = 4.f * k6 * z;
+    Y[7] = -k4 * x * z;               gx[7] = -k4 * z;         gy[7] = 0.f;              gz[7] = -k4 * x;
+    Y[8] = k8 * (xx - yy);            gx[8] = 2.f * k8 * x;    gy[8] = -2.f * k8 * y;    gz[8] = 0.f;
+    if (deg < 3) return;
+    const float k9 = 0.5900435899266435f, k10 = 2.890611442640554f, k11 = 0.4570457994644658f;
+    const float k12 = 0.3731763325901154f, k14 = 1.445305721320277f;
+    Y[9] = -k9 * y * (3.f * xx - yy);
+    gx[9] = -6.f * k9 * x * y; gy[9] = -k9 * (3.f * xx - 3.f * yy); gz[9] = 0.f;
+    Y[10] = k10 * x * y * z;
+    gx[10] = k10 * y * z; gy[10] = k10 * x * z; gz[10] = k10 * x * y;
+    Y[11] = -k11 * y * (4.f * zz - xx - yy);
+    gx[11] = 2.f * k11 * x * y; gy[11] = -k11 * (4.f * zz - xx - 3.f * yy); gz[11] = -8.f * k11 * y * z;
+    Y[12] = k12 * z * (2.f * zz - 3.f * xx - 3.f * yy);
+    gx[12] = -6.f * k12 * x * z; gy[12] = -6.f * k12 * y * z; gz[12] = k12 * (6.f * zz - 3.f * xx - 3.f * yy);
+    Y[13] = -k11 * x * (4.f * zz - xx - yy);
+    gx[13] = -k11 * (4.f * zz - 3.f * xx - yy); gy[13] = 2.f * k11 * x * y; gz[13] = -8.f * k11 * x * z;
+    Y[14] = k14 * z * (xx - yy);
+    gx[14] = 2.f * k14 * x * z; gy[14] = -2.f * k14 * y * z; gz[14] = k14 * (xx - yy);
+    Y[15] = -k9 * x * (xx - 3.f * yy);
+    gx[15] = -k9 * (3.f * xx - 3.f * yy); gy[15] = 6.f * k9 * x * y; gz[15] = 0.f;
+}
+
+// Adds the gradient g (w.r.t. the unit direction d = (p - o)/|p - o|) to the
+// gradient of p: (I - d d^T) g / |p - o|.
+__device__ inline void dir_to_pos(const float* d, float len, const float* g, float* gp) {
+    const float dg = d[0] * g[0] + d[1] * g[1] + d[2] * g[2];
+    for (int i = 0; i < 3; i++) gp[i] += (g[i] - d[i] * dg) / len;
+}
+
+__global__ __launch_bounds__(256) void k_gauss_project_bwd(BwdArgs a, ProjBwdArgs b) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.M) return;
+    const int M = a.M;
+    float s9[9];
+    bool any = false;
+#pragma unroll
+    for (int i = 0; i < 9; i++) {
+        s9[i] = a.g2d[(size_t)i * M + g];
+        any = any || s9[i] != 0.0f;
+    }
+    if (!any) return;
+    const CamK& k = a.k;
+    const float m0 = b.means[g], m1 = b.means[M + g], m2 = b.means[2 * M + g];
+    float t[3];
+    for (int i = 0; i < 3; i++) t[i] = k.R[3 * i] * m0 + k.R[3 * i + 1] * m1 + k.R[3 * i + 2] * m2 + k.t[i];
+    const float tz = t[2], itz = 1.0f / tz;
+    // rotation from the normalised quaternion
+    const float q0 = b.rots[g], q1 = b.rots[M + g], q2 = b.rots[2 * M + g], q3 = b.rots[3 * M + g];
+    const float qn = sqrtf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+    const float w = q0 / qn, x = q1 / qn, y = q2 / qn, z = q3 / qn;
+    float R[9];
+    R[0] = 1.f - 2.f * (y * y + z * z); R[1] = 2.f * (x * y - w * z);       R[2] = 2.f * (x * z + w * y);
+    R[3] = 2.f * (x * y + w * z);       R[4] = 1.f - 2.f * (x * x + z * z); R[5] = 2.f * (y * z - w * x);
+    R[6] = 2.f * (x * z - w * y);       R[7] = 2.f * (y * z + w * x);       R[8] = 1.f - 2.f * (x * x + y * y);
+    const float s[3] = {b.scales[g], b.scales[M + g], b.scales[2 * M + g]};
+    float Mq[9], Sig[9];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) Mq[3 * i + j] = R[3 * i + j] * s[j];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++)
+            Sig[3 * i + j] = Mq[3 * i] * Mq[3 * j] + Mq[3 * i + 1] * Mq[3 * j + 1] + Mq[3 * i + 2] * Mq[3 * j + 2];
+    // Jacobian of the perspective map, with the frustum clamp
+    const float limx = 1.3f * (0.5f * k.W / k.fx), limy = 1.3f * (0.5f * k.H / k.fy);
+    const float rx = t[0] * itz, ry = t[1] * itz;
+    const bool cx_in = rx > -limx && rx < limx, cy_in = ry > -limy && ry < limy;
+    const float xr = fminf(limx, fmaxf(-limx, rx)), yr = fminf(limy, fmaxf(-limy, ry));
+    const float J00 = k.fx * itz, J02 = -k.fx * xr * itz, J11 = k.fy * itz, J12 = -k.fy * yr * itz;
+    float Mx[6];  // J W, 2 x 3
+    for (int j = 0; j < 3; j++) {
+        Mx[j] = J00 * k.R[j] + J02 * k.R[6 + j];
+        Mx[3 + j] = J11 * k.R[3 + j] + J12 * k.R[6 + j];
+    }
+    float cov[3];  // xx, xy, yy of M Sigma M^T (plus dilation below)
+    {
+        float MS[6];
+        for (int r = 0; r < 2; r++)
+            for (int j = 0; j < 3; j++)
+                MS[3 * r + j] = Mx[3 * r] * Sig[j] + Mx[3 * r + 1] * Sig[3 + j] + Mx[3 * r + 2] * Sig[6 + j];
+        cov[0] = MS[0] * Mx[0] + MS[1] * Mx[1] + MS[2] * Mx[2];
+        cov[1] = MS[0] * Mx[3] + MS[1] * Mx[4] + MS[2] * Mx[5];
+        cov[2] = MS[3] * Mx[3] + MS[4] * Mx[4] + MS[5] * Mx[5];
+    }
+    const float a_ = cov[0] + a.o.delta, b_ = cov[1], c_ = cov[2] + a.o.delta;
+    const float det = a_ * c_ - b_ * b_;
+    const float QA = c_ / det, QB = -b_ / det, QC = a_ / det;
+    // conic gradient -> covariance gradient: dL/dS = -Q Gq Q (Gq symmetric, off-diagonal gB/2)
+    const float gA = s9[2], gBh = 0.5f * s9[3], gC = s9[4];
+    const float t00 = QA * gA + QB * gBh, t01 = QA * gBh + QB * gC;
+    const float t10 = QB * gA + QC * gBh, t11 = QB * gBh + QC * gC;
+    const float dS00 = -(t00 * QA + t01 * QB), dS01 = -(t00 * QB + t01 * QC), dS11 = -(t10 * QB + t11 * QC);
+    // Sigma' = Mx Sigma Mx^T: dL/dMx = 2 G Mx Sigma, dL/dSigma = Mx^T G Mx (G per-entry symmetric)
+    const float G2[4] = {dS00, dS01, dS01, dS11};
+    float MSig[6];
+    for (int r = 0; r < 2; r++)
+        for (int j = 0; j < 3; j++)
+            MSig[3 * r + j] = Mx[3 * r] * Sig[j] + Mx[3 * r + 1] * Sig[3 + j] + Mx[3 * r + 2] * Sig[6 + j];
+    float gMx[6];
+    for (int r = 0; r < 2; r++)
+        for (int j = 0; j < 3; j++) gMx[3 * r + j] = 2.f * (G2[2 * r] * MSig[j] + G2[2 * r + 1] * MSig[3 + j]);
+    float gSig[9];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++)
+            gSig[3 * i + j] = Mx[i] * (G2[0] * Mx[j] + G2[1] * Mx[3 + j]) + Mx[3 + i] * (G2[2] * Mx[j] + G2[3] * Mx[3 + j]);
+    // Sigma = Mq Mq^T: dL/dMq = 2 gSig Mq
+    float gMq[9];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++)
+            gMq[3 * i + j] = 2.f * (gSig[3 * i] * Mq[j] + gSig[3 * i + 1] * Mq[3 + j] + gSig[3 * i + 2] * Mq[6 + j]);
+    float gs[3] = {0.f, 0.f, 0.f}, gR[9];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            gs[j] += gMq[3 * i + j] * R[3 * i + j];
+            gR[3 * i + j] = gMq[3 * i + j] * s[j];
+        }
+    // rotation -> normalised quaternion -> quaternion
+    const float gw = 2.f * (-z * gR[1] + y * gR[2] + z * gR[3] - x * gR[5] - y * gR[6] + x * gR[7]);
+    const float gx = 2.f * (y * gR[1] + z * gR[2] + y * gR[3] - 2.f * x * gR[4] - w * gR[5] + z * gR[6] +
+                            w * gR[7] - 2.f * x * gR[8]);
+    const float gy = 2.f * (-2.f * y * gR[0] + x * gR[1] + w * gR[2] + x * gR[3] + z * gR[5] - w * gR[6] +
+                            z * gR[7] - 2.f * y * gR[8]);
+    const float gz = 2.f * (-2.f * z * gR[0] - w * gR[1] + x * gR[2] + w * gR[3] - 2.f * z * gR[4] + y * gR[5] +
+                            x * gR[6] + y * gR[7]);
+    const float qd = w * gw + x * gx + y * gy + z * gz;
+    b.d_rots[g] += (gw - w * qd) / qn;
+    b.d_rots[M + g] += (gx - x * qd) / qn;
+    b.d_rots[2 * M + g] += (gy - y * qd) / qn;
+    b.d_rots[3 * M + g] += (gz - z * qd) / qn;
+    for (int j = 0; j < 3; j++) b.d_scales[(size_t)j * M + g] += gs[j];
+    // Mx = J W: dL/dJ = dL/dMx W^T, then J (and the mean u) -> camera-space position
+    const float gJ00 = gMx[0] * k.R[0] + gMx[1] * k.R[1] + gMx[2] * k.R[2];
+    const float gJ02 = gMx[0] * k.R[6] + gMx[1] * k.R[7] + gMx[2] * k.R[8];
+    const float gJ11 = gMx[3] * k.R[3] + gMx[4] * k.R[4] + gMx[5] * k.R[5];
+    const float gJ12 = gMx[3] * k.R[6] + gMx[4] * k.R[7] + gMx[5] * k.R[8];
+    const float itz2 = itz * itz;
+    float gt[3];
+    const float gu0 = s9[0], gu1 = s9[1];
+    // u = f t_xy / t_z + c
+    gt[0] = gu0 * k.fx * itz;
+    gt[1] = gu1 * k.fy * itz;
+    gt[2] = -(gu0 * k.fx * t[0] + gu1 * k.fy * t[1]) * itz2;
+    // J00 = fx / tz, J11 = fy / tz
+    gt[2] += -(gJ00 * k.fx + gJ11 * k.fy) * itz2;
+    // J02 = -fx xr / tz with xr = t_x / t_z inside the clamp
+    gt[2] += gJ02 * k.fx * xr * itz2 + gJ12 * k.fy * yr * itz2;
+    if (cx_in) {
+        gt[0] += gJ02 * (-k.fx * itz) * itz;
+        gt[2] += gJ02 * (-k.fx * itz) * (-t[0] * itz2);
+    }
+    if (cy_in) {
+        gt[1] += gJ12 * (-k.fy * itz) * itz;
+        gt[2] += gJ12 * (-k.fy * itz) * (-t[1] * itz2);
+    }
+    float gm[3];
+    for (int j = 0; j < 3; j++) gm[j] = k.R[j] * gt[0] + k.R[3 + j] * gt[1] + k.R[6 + j] * gt[2];
+    // colour: c = max(0, 0.5 + sum sh Y(d)), d = (mu - o) / |mu - o|
+    float dd[3] = {m0 - k.o[0], m1 - k.o[1], m2 - k.o[2]};
+    const float len = sqrtf(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
+    for (int i = 0; i < 3; i++) dd[i] /= len;
+    float Y[16], Yx[16], Yy[16], Yz[16];
+    const int deg = b.sh_degree, Cn = (deg + 1) * (deg + 1);
+    sh_basis_grad(deg, dd[0], dd[1], dd[2], Y, Yx, Yy, Yz);
+    float gdir[3] = {0.f, 0.f, 0.f};
+    for (int ch = 0; ch < 3; ch++) {
+        const float gc = s9[6 + ch];
+        if (gc == 0.0f) continue;
+        float cval = 0.5f;
+        for (int j = 0; j < Cn; j++) cval += Y[j] * b.sh[((size_t)j * 3 + ch) * M + g];
+        if (cval < 0.0f) continue;  // clamped colour channel
+        for (int j = 0; j < Cn; j++) {
+            const float c = b.sh[((size_t)j * 3 + ch) * M + g];
+            b.d_sh[((size_t)j * 3 + ch) * M + g] += gc * Y[j];
+            gdir[0] += gc * c * Yx[j];
+            gdir[1] += gc * c * Yy[j];
+            gdir[2] += gc * c * Yz[j];
+        }
+    }
+    dir_to_pos(dd, len, gdir, gm);
+    for (int j = 0; j < 3; j++) b.d_means[(size_t)j * M + g] += gm[j];
+    b.d_opac[g] += s9[5];
+    if (b.d_mean2d) {
+        b.d_mean2d[g] += gu0;
+        b.d_mean2d[M + g] += gu1;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cell_bwd(BwdArgs a, ProjBwdArgs b) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= b.N || a.o.v_one) return;
+    const float gv = a.gv[n];
+    if (gv == 0.0f) return;
+    const CamK& k = a.k;
+    const int N = b.N;
+    const float p0 = b.cell_pos[n], p1 = b.cell_pos[N + n], p2 = b.cell_pos[2 * N + n];
+    float dd[3] = {p0 - k.o[0], p1 - k.o[1], p2 - k.o[2]};
+    const float len = sqrtf(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
+    for (int i = 0; i < 3; i++) dd[i] /= len;
+    float Y[16], Yx[16], Yy[16], Yz[16];
+    const int deg = b.v_sh_degree, Cn = (deg + 1) * (deg + 1);
+    sh_basis_grad(deg, dd[0], dd[1], dd[2], Y, Yx, Yy, Yz);
+    float sv = 0.f;
+    for (int j = 0; j < Cn; j++) sv += Y[j] * b.cell_v_sh[(size_t)j * N + n];
+    const float v = 1.0f / (1.0f + __expf(-sv));
+    const float gs = gv * v * (1.0f - v);
+    float gdir[3] = {0.f, 0.f, 0.f};
+    for (int j = 0; j < Cn; j++) {
+        const float c = b.cell_v_sh[(size_t)j * N + n];
+        b.d_cell_v_sh[(size_t)j * N + n] += gs * Y[j];
+        gdir[0] += gs * c * Yx[j];
+        gdir[1] += gs * c * Yy[j];
+        gdir[2] += gs * c * Yz[j];
+    }
+    float gp[3] = {0.f, 0.f, 0.f};
+    dir_to_pos(dd, len, gdir, gp);
+    for (int j = 0; j < 3; j++) b.d_cell_pos[(size_t)j * N + n] += gp[j];
+}
+
+void launch_composite_bwd(hipStream_t st, const BwdArgs& a) {
+    const int tiles = a.k.TX * a.k.TY;
+    if (tiles <= 0) return;
+    const int waves = 4 * tiles < 256 * 4 * 4 ? 4 * tiles : 256 * 4 * 4;
+    hipLaunchKernelGGL(k_composite_bwd, dim3((waves + kBwdWaves - 1) / kBwdWaves), dim3(256), 0, st, a);
+}
+
+void launch_project_bwd(hipStream_t st, const BwdArgs& a, const ProjBwdArgs& b) {
+    if (a.M > 0)
+        hipLaunchKernelGGL(k_gauss_project_bwd, dim3((a.M + 255) / 256), dim3(256), 0, st, a, b);
+    if (b.N > 0) hipLaunchKernelGGL(k_cell_bwd, dim3((b.N + 255) / 256), dim3(256), 0, st, a, b);
+}
+
+}  // namespace dgs

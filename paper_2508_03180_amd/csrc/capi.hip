@@ -32,6 +32,9 @@ struct dgs_ctx_s {
     uint64_t* sort_status = nullptr;
     size_t sort_status_cap = 0;
     uint32_t epoch = 0;  // look-back epoch counter
+    float* g2d = nullptr;  // [9][M] backward screen-space gradients
+    float* gv = nullptr;   // [N] backward dL/dv
+    int64_t cap_g2d = 0, cap_gv = 0;
     uint32_t* hist = nullptr;     // [8][256]
     uint32_t* misc = nullptr;     // [0] key total, [1] scan ticket, [2..9] sort tickets, [10] sort count,
                                   // [11..12] compositor work-queue head and item count
@@ -271,7 +274,7 @@ dgs_status dgs_destroy(dgs_ctx c) {
     for (auto& a : c->events)
         for (auto& e : a) hipEventDestroy(e);
     void* ptrs[] = {c->p_depth, c->p_ntiles, c->p_offsets, c->p_rect, c->cell_v, c->recs, c->grect,
-                    c->keys0, c->keys1, c->vals0, c->vals1, c->ranges, c->tile_order, c->scan_status, c->sort_status,
+                    c->keys0, c->keys1, c->vals0, c->vals1, c->ranges, c->tile_order, c->scan_status, c->sort_status, c->g2d, c->gv,
                     c->hist, c->misc, c->dev_err, c->counters};
     for (void* p : ptrs)
         if (p) hipFree(p);
@@ -366,7 +369,7 @@ dgs_status dgs_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* cam, cons
     a.counters = o.stats ? c->counters : nullptr;
     a.order = c->tile_order;
     a.queue = c->misc + 11;
-    launch_tile_order(q, a);
+    launch_tile_order(q, c->ranges, tiles, kSplitLen, c->tile_order, c->misc + 11);
     sm.mark(5);
     if (mode == DGS_MODE_DUPLEX)
         launch_composite_duplex(q, a);
@@ -380,6 +383,88 @@ dgs_status dgs_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* cam, cons
     c->last_tiles = tiles;
     c->last_in_1 = in1;
     return launched(c);
+}
+
+dgs_status dgs_render_backward(dgs_ctx c, const dgs_scene* s, const dgs_camera* cam, const dgs_render_opts* opts,
+                               const dgs_image* fwd, const float* grad_color, const float* grad_weight_sum,
+                               const dgs_grads* gr) {
+    if (!c) return DGS_ERR_INVALID_ARG;
+    CamK k;
+    OptK o;
+    int mode = 0;
+    dgs_status st;
+    if ((st = make_cam(c, cam, k)) != DGS_OK) return st;
+    if ((st = make_opts(c, opts, o, mode)) != DGS_OK) return st;
+    if ((st = check_scene(c, s, mode)) != DGS_OK) return st;
+    if (mode != DGS_MODE_DUPLEX) return fail(c, DGS_ERR_UNSUPPORTED, "backward is implemented for DGS_MODE_DUPLEX");
+    if (!fwd || !fwd->color || !fwd->weight_sum || !fwd->final_T || !fwd->last || !grad_color || !gr)
+        return fail(c, DGS_ERR_INVALID_ARG, "backward needs the forward color, weight_sum, final_T, last and grad_color");
+    if (!gr->d_means || !gr->d_scales || !gr->d_rots || !gr->d_opacities || !gr->d_sh || !gr->d_cell_v_sh ||
+        !gr->d_cell_pos)
+        return fail(c, DGS_ERR_INVALID_ARG, "gradient buffers must not be NULL (only d_mean2d is optional)");
+    const int N = s->num_cells, K = s->gaussians_per_cell, M = N * K, tiles = k.TX * k.TY;
+    if (c->last_mode != DGS_MODE_DUPLEX || c->last_prims != N || c->last_gauss != M || c->last_tiles != tiles)
+        return fail(c, DGS_ERR_INVALID_ARG, "backward must follow a Duplex render of the same scene and camera");
+    if (M == 0) return DGS_OK;
+    hipSetDevice(c->device);
+    hipError_t e = hipSuccess;
+    if (9 * (int64_t)M > c->cap_g2d) {
+        if ((e = grow(c->g2d, 9 * (int64_t)M, c->stream)) != hipSuccess) goto oom;
+        c->cap_g2d = 9 * (int64_t)M;
+    }
+    if (N > c->cap_gv) {
+        if ((e = grow(c->gv, (int64_t)N, c->stream)) != hipSuccess) goto oom;
+        c->cap_gv = N;
+    }
+    {
+        hipStream_t q = c->stream;
+        launch_fill_u32(q, (uint32_t*)c->g2d, 0u, 9 * (size_t)M);
+        launch_fill_u32(q, (uint32_t*)c->gv, 0u, (size_t)N);
+        launch_fill_u32(q, c->misc + 11, 0u, 2);
+        launch_tile_order(q, c->ranges, tiles, 0u, c->tile_order, c->misc + 11);
+        BwdArgs a;
+        a.ranges = c->ranges;
+        a.vals = c->last_in_1 ? c->vals1 : c->vals0;
+        a.recs = c->recs;
+        a.cell_v = c->cell_v;
+        a.K = K;
+        a.M = M;
+        a.k = k;
+        a.o = o;
+        a.color = fwd->color;
+        a.D = fwd->weight_sum;
+        a.T = fwd->final_T;
+        a.last = fwd->last;
+        a.grad_color = grad_color;
+        a.grad_D = grad_weight_sum;
+        a.g2d = c->g2d;
+        a.gv = c->gv;
+        a.order = c->tile_order;
+        a.queue = c->misc + 11;
+        launch_composite_bwd(q, a);
+        ProjBwdArgs b;
+        b.N = N;
+        b.means = s->means;
+        b.scales = s->scales;
+        b.rots = s->rots;
+        b.sh = s->sh;
+        b.sh_degree = s->sh_degree;
+        b.cell_pos = s->cell_pos;
+        b.cell_v_sh = s->cell_v_sh;
+        b.v_sh_degree = s->v_sh_degree;
+        b.d_means = gr->d_means;
+        b.d_scales = gr->d_scales;
+        b.d_rots = gr->d_rots;
+        b.d_opac = gr->d_opacities;
+        b.d_sh = gr->d_sh;
+        b.d_cell_v_sh = gr->d_cell_v_sh;
+        b.d_cell_pos = gr->d_cell_pos;
+        b.d_mean2d = gr->d_mean2d;
+        launch_project_bwd(q, a, b);
+    }
+    return launched(c);
+oom:
+    return fail(c, DGS_ERR_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
 }
 
 dgs_status dgs_sync(dgs_ctx c) {

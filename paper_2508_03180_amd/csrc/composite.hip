@@ -106,7 +106,6 @@ __device__ inline RecView read_rec(const GRec* lds, int i) {
 
 
 // Work item: tile << 3 | mode; mode 0 = all four strips, mode 4 + j = strip j.
-constexpr uint32_t kSplitLen = 64;  // tiles with at least this many entries are split into strips
 
 // Statistics counters (STATS only): n_val, n_rendered (the termination ratio
 // 1 - n_rendered / n_val), in-box member evaluations and (pixel, entry) pairs
@@ -378,19 +377,20 @@ __global__ __launch_bounds__(256) void k_composite(CompositeArgs a) {
 }
 
 // Builds the work queue: one item per tile, or one per strip for tiles whose
-// list has at least kSplitLen entries; items are bucketed by
+// list has at least split_len entries; items are bucketed by
 // floor(log2(estimated cost)) and laid out from costly to cheap (order inside
 // a bucket is arbitrary: it only affects scheduling, never results).
 // queue[0] = head (reset), queue[1] = item count.  One workgroup.
 __global__ __launch_bounds__(1024) void k_tile_order(const uint32_t* __restrict__ ranges, int ntiles,
-                                                     uint32_t* __restrict__ order, uint32_t* __restrict__ queue) {
+                                                     uint32_t split_len, uint32_t* __restrict__ order,
+                                                     uint32_t* __restrict__ queue) {
     __shared__ uint32_t s_cnt[33], s_off[33];
     const int tid = threadIdx.x;
     if (tid < 33) s_cnt[tid] = 0;
     __syncthreads();
     for (int t = tid; t < ntiles; t += blockDim.x) {
         const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
-        if (len >= kSplitLen)
+        if (len >= split_len)
             atomicAdd(&s_cnt[32 - __clz(len / 2)], 4u);  // four strips, each about half a tile's cost
         else
             atomicAdd(&s_cnt[32 - __clz(len)], 1u);
@@ -408,7 +408,7 @@ __global__ __launch_bounds__(1024) void k_tile_order(const uint32_t* __restrict_
     __syncthreads();
     for (int t = tid; t < ntiles; t += blockDim.x) {
         const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
-        if (len >= kSplitLen) {
+        if (len >= split_len) {
             const uint32_t o = atomicAdd(&s_off[32 - __clz(len / 2)], 4u);
             for (uint32_t j = 0; j < 4; j++) order[o + j] = ((uint32_t)t << 3) | (4u + j);
         } else {
@@ -423,10 +423,10 @@ static unsigned persistent_grid(int tiles) {
     return (unsigned)((waves + kWaves - 1) / kWaves);
 }
 
-void launch_tile_order(hipStream_t st, const CompositeArgs& a) {
-    const int tiles = a.k.TX * a.k.TY;
+void launch_tile_order(hipStream_t st, const uint32_t* ranges, int tiles, uint32_t split_len, uint32_t* order,
+                       uint32_t* queue) {
     if (tiles <= 0) return;
-    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, st, a.ranges, tiles, a.order, a.queue);
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, st, ranges, tiles, split_len, order, queue);
 }
 
 static void launch_composite(hipStream_t st, const CompositeArgs& a, bool duplex) {

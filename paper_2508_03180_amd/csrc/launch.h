@@ -82,9 +82,45 @@ struct CompositeArgs {
     uint32_t* queue;               // [2] scratch: work-queue head, item count
 };
 // Work queue of the compositor (heaviest-first tile / strip items); must
-// precede launch_composite_*.
-void launch_tile_order(hipStream_t st, const CompositeArgs& a);
+// precede launch_composite_*.  Tiles with at least split_len entries become
+// four strip items (split_len 0: every tile is split).
+void launch_tile_order(hipStream_t st, const uint32_t* ranges, int tiles, uint32_t split_len, uint32_t* order,
+                       uint32_t* queue);
+constexpr uint32_t kSplitLen = 64;
 void launch_composite_duplex(hipStream_t st, const CompositeArgs& a);
 void launch_composite_alpha(hipStream_t st, const CompositeArgs& a);
+
+// Backward of the Duplex compositor: per-Gaussian screen-space gradients
+// g2d[9][M] (mean x, y, conic A, B, C, sigma, r, g, b) and per-cell dL/dv,
+// both accumulated atomically (zero them first).
+struct BwdArgs {
+    const uint32_t* ranges;
+    const uint32_t* vals;
+    const GRec* recs;
+    const float* cell_v;
+    int K, M;
+    CamK k;
+    OptK o;
+    const float* color;
+    const float* D;
+    const float* T;
+    const int32_t* last;
+    const float* grad_color;
+    const float* grad_D;  // nullable
+    float* g2d;
+    float* gv;
+    uint32_t* order;
+    uint32_t* queue;
+};
+struct ProjBwdArgs {
+    int N;
+    const float *means, *scales, *rots, *sh;
+    int sh_degree;
+    const float *cell_pos, *cell_v_sh;
+    int v_sh_degree;
+    float *d_means, *d_scales, *d_rots, *d_opac, *d_sh, *d_cell_v_sh, *d_cell_pos, *d_mean2d;
+};
+void launch_composite_bwd(hipStream_t st, const BwdArgs& a);
+void launch_project_bwd(hipStream_t st, const BwdArgs& a, const ProjBwdArgs& b);
 
 }  // namespace dgs

@@ -20,6 +20,11 @@ def _planar(a, device):
     return t.to(device)
 
 
+def _planar_t(t):
+    """[P, ...] torch tensor -> planar [..., P] contiguous float32."""
+    return t.detach().reshape(t.shape[0], -1).t().contiguous().float()
+
+
 class DeviceScene:
     """A scene resident in device memory in the library's planar layout."""
 
@@ -41,6 +46,17 @@ class DeviceScene:
                  opacities=torch.as_tensor(np.ascontiguousarray(scene["opacities"], np.float32)).to(device),
                  sh=torch.as_tensor(np.ascontiguousarray(sh.transpose(1, 2, 0))).to(device))
         return cls(t, N, K, scene["v_sh_degree"], scene["sh_degree"])
+
+    @classmethod
+    def from_tensors(cls, cell_pos, cell_scale, cell_rot, cell_v_sh, means, scales, rots, opacities, sh, K):
+        """From natural-layout device tensors ([N,3], [N,3], [N,4], [N,Cv],
+        [M,3], [M,3], [M,4], [M], [M,C,3]); planar copies are made."""
+        Cv, C = cell_v_sh.shape[1], sh.shape[1]
+        t = dict(cell_pos=_planar_t(cell_pos), cell_scale=_planar_t(cell_scale), cell_rot=_planar_t(cell_rot),
+                 cell_v_sh=_planar_t(cell_v_sh), means=_planar_t(means), scales=_planar_t(scales),
+                 rots=_planar_t(rots), opacities=opacities.detach().contiguous().float(),
+                 sh=sh.detach().permute(1, 2, 0).contiguous().float())
+        return cls(t, cell_pos.shape[0], K, round(Cv ** 0.5) - 1, round(C ** 0.5) - 1)
 
     def nbytes(self):
         return sum(v.numel() * v.element_size() for v in self.t.values())
@@ -97,6 +113,7 @@ class Renderer:
         self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.ctx = capi.dgs_create(self.device.index or 0, self.stream.cuda_stream)
+        self.frame_id = 0  # incremented by every render; backward needs the latest
 
     def close(self):
         if self.ctx:
@@ -129,7 +146,34 @@ class Renderer:
         img.weight_sum = out["D"].data_ptr() if "D" in out else None
         img.final_T = out["T"].data_ptr() if "T" in out else None
         img.last = out["last"].data_ptr() if "last" in out else None
+        self.frame_id += 1
         return capi.dgs_render(self.ctx, scene.struct(), camera_struct(cam), opts, img)
+
+    def render_backward(self, scene: DeviceScene, cam, out, grad_color, grad_D=None, mean2d=False, **kw):
+        """Gradients (planar, float32) of a loss whose gradient w.r.t. the
+        last render's colour is grad_color [3,H,W] (and w.r.t. D, grad_D)."""
+        d = self.device
+        M, N = scene.M, scene.N
+        g = dict(means=torch.zeros((3, M), device=d), scales=torch.zeros((3, M), device=d),
+                 rots=torch.zeros((4, M), device=d), opacities=torch.zeros((M,), device=d),
+                 sh=torch.zeros_like(scene.t["sh"]), cell_v_sh=torch.zeros_like(scene.t["cell_v_sh"]),
+                 cell_pos=torch.zeros((3, N), device=d))
+        if mean2d:
+            g["mean2d"] = torch.zeros((2, M), device=d)
+        gr = capi.dgs_grads()
+        gr.d_means, gr.d_scales, gr.d_rots = g["means"].data_ptr(), g["scales"].data_ptr(), g["rots"].data_ptr()
+        gr.d_opacities, gr.d_sh = g["opacities"].data_ptr(), g["sh"].data_ptr()
+        gr.d_cell_v_sh, gr.d_cell_pos = g["cell_v_sh"].data_ptr(), g["cell_pos"].data_ptr()
+        gr.d_mean2d = g["mean2d"].data_ptr() if mean2d else None
+        img = capi.dgs_image()
+        img.color, img.weight_sum = out["color"].data_ptr(), out["D"].data_ptr()
+        img.final_T, img.last = out["T"].data_ptr(), out["last"].data_ptr()
+        gc = grad_color.contiguous().float()
+        gd = grad_D.contiguous().float() if grad_D is not None else None
+        st = capi.dgs_render_backward(self.ctx, scene.struct(), camera_struct(cam), opts_struct(**kw), img,
+                                      gc.data_ptr(), gd.data_ptr() if gd is not None else None, gr)
+        capi.check(st, self.ctx)
+        return g
 
     def render(self, scene: DeviceScene, cam, out=None, check=True, **kw):
         """Render a frame.  With check=True the call synchronises, and on a
@@ -187,3 +231,40 @@ class Renderer:
         assert vals.is_contiguous() and keys.numel() == vals.numel()
         capi.dgs_sort_pairs(self.ctx, keys.data_ptr(), vals.data_ptr(), keys.numel(), key_bits)
         capi.check(capi.dgs_sync(self.ctx), self.ctx)
+
+
+class DuplexRender(torch.autograd.Function):
+    """Differentiable Duplex render through the C ABI.
+
+    Inputs (natural layout, device): cell_pos [N,3], cell_scale [N,3],
+    cell_rot [N,4], cell_v_sh [N,Cv], means [M,3], scales [M,3], rots [M,4],
+    opacities [M], sh [M,C,3].  Returns (color [3,H,W], D [H,W]).  Cell
+    scales and rotations only choose tiles, so their gradient is None.  The
+    backward replays the renderer context's most recent frame: call it before
+    rendering again on the same Renderer.
+    """
+
+    @staticmethod
+    def forward(ctx, renderer, cam, opts, cell_pos, cell_scale, cell_rot, cell_v_sh, means, scales, rots,
+                opacities, sh):
+        K = means.shape[0] // max(cell_pos.shape[0], 1)
+        ds = DeviceScene.from_tensors(cell_pos, cell_scale, cell_rot, cell_v_sh, means, scales, rots, opacities,
+                                      sh, K)
+        out = renderer.render(ds, cam, mode="duplex", **opts)
+        ctx.renderer, ctx.ds, ctx.cam, ctx.opts, ctx.out = renderer, ds, cam, opts, out
+        ctx.frame = renderer.frame_id
+        ctx.shapes = (cell_v_sh.shape, sh.shape)
+        return out["color"], out["D"]
+
+    @staticmethod
+    def backward(ctx, g_color, g_D):
+        r = ctx.renderer
+        if r.frame_id != ctx.frame:
+            raise RuntimeError("the renderer rendered another frame before this backward; "
+                               "use one Renderer per pending backward")
+        if g_color is None:
+            g_color = torch.zeros_like(ctx.out["color"])
+        g = r.render_backward(ctx.ds, ctx.cam, ctx.out, g_color, g_D, **ctx.opts)
+        cv_shape, sh_shape = ctx.shapes
+        return (None, None, None, g["cell_pos"].t(), None, None, g["cell_v_sh"].t().reshape(cv_shape),
+                g["means"].t(), g["scales"].t(), g["rots"].t(), g["opacities"], g["sh"].permute(2, 0, 1).reshape(sh_shape))
