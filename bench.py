@@ -52,7 +52,76 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-alpha", action="store_true")
     p.add_argument("--cpu-frames", type=int, default=4)
+    p.add_argument("--bwd-steps", type=int, default=10)
     return p.parse_args()
+
+
+def ssim_loss(C, T):
+    """1 - SSIM with an 11x11 Gaussian window (sigma 1.5), per channel."""
+    import torch
+    import torch.nn.functional as F
+    g = torch.exp(-0.5 * ((torch.arange(11, device=C.device, dtype=C.dtype) - 5) / 1.5) ** 2)
+    g = g / g.sum()
+    w = (g[:, None] * g[None, :]).expand(3, 1, 11, 11).contiguous()
+    x, y = C[None], T[None]
+    mu_x = F.conv2d(x, w, padding=5, groups=3)
+    mu_y = F.conv2d(y, w, padding=5, groups=3)
+    sxx = F.conv2d(x * x, w, padding=5, groups=3) - mu_x ** 2
+    syy = F.conv2d(y * y, w, padding=5, groups=3) - mu_y ** 2
+    sxy = F.conv2d(x * y, w, padding=5, groups=3) - mu_x * mu_y
+    c1, c2 = 0.01 ** 2, 0.03 ** 2
+    ssim = ((2 * mu_x * mu_y + c1) * (2 * sxy + c2)) / ((mu_x ** 2 + mu_y ** 2 + c1) * (sxx + syy + c2))
+    return 1 - ssim.mean()
+
+
+def differentiation(r, scene, cam, steps):
+    """Forward + loss + backward time through the autograd Function."""
+    import numpy as np
+    import torch
+
+    from paper_2508_03180_amd.renderer import DeviceScene, DuplexRender
+
+    rng = np.random.default_rng(3)
+    pert = dict(scene)
+    pert["means"] = (scene["means"] + rng.normal(0, 0.01, scene["means"].shape)).astype(np.float32)
+    logit = np.log(scene["opacities"] / (1 - scene["opacities"]))
+    pert["opacities"] = (1 / (1 + np.exp(-(logit + rng.normal(0, 0.3, logit.shape))))).astype(np.float32)
+    target = r.render(DeviceScene.from_numpy(pert, "cuda:0"), cam)["color"].clone()
+    keys = ("cell_pos", "cell_scale", "cell_rot", "cell_v_sh", "means", "scales", "rots", "opacities", "sh")
+    t = {k: torch.tensor(scene[k], device="cuda", requires_grad=k not in ("cell_scale", "cell_rot")) for k in keys}
+
+    def step():
+        for v in t.values():
+            v.grad = None
+        C, _ = DuplexRender.apply(r, cam, {}, *[t[k] for k in keys])
+        loss = 0.8 * (C - target).abs().mean() + 0.2 * ssim_loss(C, target)
+        loss.backward()
+        return loss
+
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        loss = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    # the backward kernels alone
+    from paper_2508_03180_amd import _capi as capi
+    ds = DeviceScene.from_numpy(scene, "cuda:0")
+    out = r.render(ds, cam)
+    gC = torch.randn_like(out["color"])
+    r.render_backward(ds, cam, out, gC)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        r.render_backward(ds, cam, out, gC)
+    torch.cuda.synchronize()
+    bt = (time.perf_counter() - t1) / steps
+    capi.check(capi.dgs_sync(r.ctx), r.ctx)
+    return {"loss": "0.8 L1 + 0.2 (1 - SSIM 11x11) vs perturbed-scene target", "width": 1920, "height": 1080,
+            "fwd_loss_bwd_ms": round(dt * 1e3, 3), "backward_ms": round(bt * 1e3, 3),
+            "final_loss": round(float(loss), 5)}
 
 
 def main():
@@ -158,6 +227,10 @@ def main():
             "algorithmic_gflop_per_launch": round(flops / 1e9, 4)}
     proj_gbs = cnt["projected"] * BYTES_PROJECT_SH3 / (st_dup["gauss_project"] * 1e-3) / 1e9
 
+    # differentiation: forward + 0.8 L1 + 0.2 (1 - SSIM) + backward at 1080p
+    # against a target rendered from a perturbed copy of the scene
+    bwd = differentiation(r, scene, cams[0], a.bwd_steps)
+
     cpu = None
     if not a.no_cpu_baseline:
         import oracle
@@ -188,6 +261,7 @@ def main():
         "projection_hbm_frac": round(proj_gbs / PEAK_HBM_GBS, 4),
         "termination_ratio": round(1 - cnt["n_rendered"] / max(cnt["n_val"], 1), 4),
         "roofline": roof,
+        "differentiation": bwd,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -204,6 +204,8 @@ __device__ inline void duplex_strip_bwd(const BwdArgs& a, int tile, int s0, int 
 
 __global__ __launch_bounds__(256) void k_composite_bwd(BwdArgs a) {
     __shared__ GRec s_rec[kBwdWaves][64];
+    a.k = a.fr->k;
+    a.o = a.fr->o;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     GRec* lds = s_rec[wave];
     const uint32_t nitems = a.queue[1];
@@ -265,6 +267,8 @@ __device__ inline void dir_to_pos(const float* d, float len, const float* g, flo
 __global__ __launch_bounds__(256) void k_gauss_project_bwd(BwdArgs a, ProjBwdArgs b) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= a.M) return;
+    a.k = a.fr->k;
+    a.o = a.fr->o;
     const int M = a.M;
     float s9[9];
     bool any = false;
@@ -420,7 +424,10 @@ __global__ __launch_bounds__(256) void k_gauss_project_bwd(BwdArgs a, ProjBwdArg
 
 __global__ __launch_bounds__(256) void k_cell_bwd(BwdArgs a, ProjBwdArgs b) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= b.N || a.o.v_one) return;
+    if (n >= b.N) return;
+    a.k = a.fr->k;
+    a.o = a.fr->o;
+    if (a.o.v_one) return;
     const float gv = a.gv[n];
     if (gv == 0.0f) return;
     const CamK& k = a.k;

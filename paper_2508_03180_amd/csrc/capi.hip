@@ -6,51 +6,11 @@
 #include <string>
 #include <vector>
 
-#include "duplexgs.h"
-#include "common.h"
-#include "launch.h"
+#include "ctx.h"
 
 using namespace dgs;
 
-struct dgs_ctx_s {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    std::string err;
 
-    int64_t cap_prims = 0, cap_gauss = 0, cap_keys = 0, cap_tiles = 0;
-    uint32_t *p_depth = nullptr, *p_ntiles = nullptr, *p_offsets = nullptr;
-    uint64_t* p_rect = nullptr;
-    float* cell_v = nullptr;
-    GRec* recs = nullptr;
-    uint64_t* grect = nullptr;
-    uint64_t *keys0 = nullptr, *keys1 = nullptr;
-    uint32_t *vals0 = nullptr, *vals1 = nullptr;
-    uint32_t* ranges = nullptr;
-    uint32_t* tile_order = nullptr;
-    uint64_t* scan_status = nullptr;
-    size_t scan_status_cap = 0;
-    uint64_t* sort_status = nullptr;
-    size_t sort_status_cap = 0;
-    uint32_t epoch = 0;  // look-back epoch counter
-    float* g2d = nullptr;  // [9][M] backward screen-space gradients
-    float* gv = nullptr;   // [N] backward dL/dv
-    int64_t cap_g2d = 0, cap_gv = 0;
-    uint32_t* hist = nullptr;     // [8][256]
-    uint32_t* misc = nullptr;     // [0] key total, [1] scan ticket, [2..9] sort tickets, [10] sort count,
-                                  // [11..12] compositor work-queue head and item count
-    int* dev_err = nullptr;
-    unsigned long long* counters = nullptr;  // n_val, n_rendered, n_box, n_cell_hits
-
-    // last frame
-    int last_mode = -1, last_passes = 0;
-    int64_t last_prims = 0, last_gauss = 0, last_tiles = 0;
-    bool last_in_1 = false;
-
-    // stage timing
-    bool timing = false;
-    std::vector<std::array<hipEvent_t, DGS_NUM_STAGES + 1>> events;
-    size_t events_used = 0;
-};
 
 namespace {
 
@@ -255,7 +215,8 @@ dgs_status dgs_create(int device, void* hip_stream, dgs_ctx* out) {
     if (hipMalloc((void**)&c->hist, 8 * 256 * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc((void**)&c->misc, 16 * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc((void**)&c->dev_err, sizeof(int)) != hipSuccess ||
-        hipMalloc((void**)&c->counters, 4 * sizeof(unsigned long long)) != hipSuccess) {
+        hipMalloc((void**)&c->counters, 4 * sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc((void**)&c->frame, sizeof(FrameK)) != hipSuccess) {
         dgs_destroy(c);
         return DGS_ERR_OOM;
     }
@@ -275,7 +236,7 @@ dgs_status dgs_destroy(dgs_ctx c) {
         for (auto& e : a) hipEventDestroy(e);
     void* ptrs[] = {c->p_depth, c->p_ntiles, c->p_offsets, c->p_rect, c->cell_v, c->recs, c->grect,
                     c->keys0, c->keys1, c->vals0, c->vals1, c->ranges, c->tile_order, c->scan_status, c->sort_status, c->g2d, c->gv,
-                    c->hist, c->misc, c->dev_err, c->counters};
+                    c->hist, c->misc, c->dev_err, c->counters, c->frame};
     for (void* p : ptrs)
         if (p) hipFree(p);
     delete c;
@@ -297,6 +258,16 @@ dgs_status dgs_reserve(dgs_ctx c, int64_t max_keys, int64_t max_prims, int64_t m
 
 dgs_status dgs_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* cam, const dgs_render_opts* opts,
                       const dgs_image* out) {
+    return dgs_internal_render(c, s, cam, opts, out, true);
+}
+
+}  // extern "C"
+
+// The frame pipeline.  With write_frame the frame's camera and options are
+// written to the context's device FrameK by the first kernel; without it the
+// caller has put them there (a captured graph replayed for a new camera).
+dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* cam, const dgs_render_opts* opts,
+                               const dgs_image* out, bool write_frame) {
     if (!c) return DGS_ERR_INVALID_ARG;
     CamK k;
     OptK o;
@@ -318,6 +289,7 @@ dgs_status dgs_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* cam, cons
     hipStream_t q = c->stream;
 
     StageMarks sm(c);
+    if (write_frame) launch_set_frame(q, FrameK{k, o, out->color, out->weight_sum, out->final_T, out->last}, c->frame);
     {
         // per-frame zeroing: digit histograms, scan/sort tickets and the
         // compositor queue (misc[1..12]), tile ranges, statistics counters
@@ -326,30 +298,31 @@ dgs_status dgs_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* cam, cons
         cl.add(c->misc + 1, 12);
         cl.add(c->ranges, 2 * (size_t)tiles);
         if (o.stats) cl.add((uint32_t*)c->counters, 8);
+        cl.bump = c->misc + 13;
         launch_clear(q, cl);
     }
     sm.mark(0);
     if (mode == DGS_MODE_DUPLEX) {
-        launch_cell_preprocess(q, N, s->cell_pos, s->cell_scale, s->cell_rot, s->cell_v_sh, s->v_sh_degree, k, o,
-                               c->p_depth, c->p_rect, c->p_ntiles, c->cell_v);
+        launch_cell_preprocess(q, N, s->cell_pos, s->cell_scale, s->cell_rot, s->cell_v_sh, s->v_sh_degree,
+                               c->frame, c->p_depth, c->p_rect, c->p_ntiles, c->cell_v);
         sm.mark(1);
-        launch_gauss_project(q, M, K, s->means, s->scales, s->rots, s->opacities, s->sh, s->sh_degree, k, o,
+        launch_gauss_project(q, M, K, s->means, s->scales, s->rots, s->opacities, s->sh, s->sh_degree, c->frame,
                              c->p_ntiles, c->recs, c->grect, nullptr, nullptr);
     } else {
         sm.mark(1);
-        launch_gauss_project(q, M, K, s->means, s->scales, s->rots, s->opacities, s->sh, s->sh_degree, k, o,
+        launch_gauss_project(q, M, K, s->means, s->scales, s->rots, s->opacities, s->sh, s->sh_degree, c->frame,
                              nullptr, c->recs, c->grect, c->p_depth, c->p_ntiles);
     }
     sm.mark(2);
     const uint64_t* prect = mode == DGS_MODE_DUPLEX ? c->p_rect : c->grect;
-    launch_exclusive_scan(q, c->p_ntiles, c->p_offsets, P, c->misc + 0, c->scan_status, &c->epoch, c->misc + 1,
+    launch_exclusive_scan(q, c->p_ntiles, c->p_offsets, P, c->misc + 0, c->scan_status, c->misc + 13, c->misc + 1,
                           c->dev_err);
     launch_emit_keys(q, P, c->p_ntiles, c->p_offsets, prect, c->p_depth, k.TX, cap, c->keys0, c->vals0, c->dev_err);
     sm.mark(3);
     SortScratch ss{c->hist, c->sort_status, c->misc + 2};
     const int bits = 32 + tile_bits(tiles);
     const bool in1 = launch_radix_sort(q, c->keys0, c->vals0, c->keys1, c->vals1, c->misc + 0, cap, bits, ss,
-                                       &c->epoch, c->dev_err);
+                                       c->misc + 13, c->dev_err);
     const uint64_t* skeys = in1 ? c->keys1 : c->keys0;
     const uint32_t* svals = in1 ? c->vals1 : c->vals0;
     sm.mark(4);
@@ -360,7 +333,8 @@ dgs_status dgs_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* cam, cons
     a.recs = c->recs;
     a.cell_v = c->cell_v;
     a.K = K;
-    a.k = k;
+    a.fr = c->frame;
+    a.k = k;  // host copy: grid sizes only
     a.o = o;
     a.color = out->color;
     a.D = out->weight_sum;
@@ -384,6 +358,8 @@ dgs_status dgs_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* cam, cons
     c->last_in_1 = in1;
     return launched(c);
 }
+
+extern "C" {
 
 dgs_status dgs_render_backward(dgs_ctx c, const dgs_scene* s, const dgs_camera* cam, const dgs_render_opts* opts,
                                const dgs_image* fwd, const float* grad_color, const float* grad_weight_sum,
@@ -422,6 +398,7 @@ dgs_status dgs_render_backward(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
         launch_fill_u32(q, (uint32_t*)c->gv, 0u, (size_t)N);
         launch_fill_u32(q, c->misc + 11, 0u, 2);
         launch_tile_order(q, c->ranges, tiles, 0u, c->tile_order, c->misc + 11);
+        launch_set_frame(q, FrameK{k, o, fwd->color, fwd->weight_sum, fwd->final_T, fwd->last}, c->frame);
         BwdArgs a;
         a.ranges = c->ranges;
         a.vals = c->last_in_1 ? c->vals1 : c->vals0;
@@ -429,6 +406,7 @@ dgs_status dgs_render_backward(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
         a.cell_v = c->cell_v;
         a.K = K;
         a.M = M;
+        a.fr = c->frame;
         a.k = k;
         a.o = o;
         a.color = fwd->color;
@@ -580,11 +558,12 @@ dgs_status dgs_sort_pairs(dgs_ctx c, uint64_t* keys, uint32_t* values, int64_t n
     ClearList cl;
     cl.add(c->hist, 8 * 256);
     cl.add(c->misc + 2, 8);
+    cl.bump = c->misc + 13;
     launch_clear(c->stream, cl);
     launch_fill_u32(c->stream, c->misc + 10, (uint32_t)n, 1);
     SortScratch ss{c->hist, c->sort_status, c->misc + 2};
     const bool in1 = launch_radix_sort(c->stream, keys, values, c->keys1, c->vals1, c->misc + 10, (uint32_t)n,
-                                       key_bits, ss, &c->epoch, c->dev_err);
+                                       key_bits, ss, c->misc + 13, c->dev_err);
     if (in1) {
         hipMemcpyAsync(keys, c->keys1, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, c->stream);
         hipMemcpyAsync(values, c->vals1, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, c->stream);

@@ -30,6 +30,18 @@ struct OptK {
     int v_one, no_et, stats;
 };
 
+// Camera and options of one frame.  Kernels read them from device memory
+// (written once per frame, or copied in before a captured graph is replayed)
+// so that a captured frame can be replayed with a different camera.
+struct FrameK {
+    CamK k;
+    OptK o;
+    float* color;  // outputs of the frame ([3][H][W], [H][W] x 3; D, T, last nullable)
+    float* D;
+    float* T;
+    int32_t* last;
+};
+
 // Projected Gaussian as the compositor reads it (48 bytes).
 //   dx = (px - x0) + ox, dy = (py - y0) + oy      (pixel offset from the mean)
 //   log2(sigma G') = lo + ca dx^2 + cb dx dy + cc dy^2
@@ -42,6 +54,14 @@ struct __align__(16) GRec {
     uint32_t wxy;  // wx | wy << 16 (each <= 32767); culled: x0 = y0 = 0x7fff0000, wxy = 0
 };
 static_assert(sizeof(GRec) == 48, "GRec layout");
+
+// Look-back status words carry a 30-bit epoch (never 0) derived from a
+// device-side frame counter (bumped by the per-frame clear kernel) and the
+// pass index j < 16, so status buffers are zeroed once at allocation and
+// never again, also when a captured frame is replayed.
+__device__ inline uint32_t epoch_tag(uint32_t frame, uint32_t j) {
+    return 1u + (uint32_t)(((uint64_t)frame * 16u + j) % ((1u << 30) - 1u));
+}
 
 // Packed integer rectangle: x0 | x1 << 16 | y0 << 32 | y1 << 48 (each < 2^15).
 __host__ __device__ inline uint64_t pack_rect(int x0, int x1, int y0, int y1) {

@@ -345,6 +345,12 @@ __device__ inline void alpha_tile(const CompositeArgs& a, int tile, int s0, int 
 template <bool DUPLEX, bool STATS>
 __global__ __launch_bounds__(256) void k_composite(CompositeArgs a) {
     __shared__ GRec s_rec[kWaves][64];
+    a.k = a.fr->k;
+    a.o = a.fr->o;
+    a.color = a.fr->color;
+    a.D = a.fr->D;
+    a.T = a.fr->T;
+    a.last = a.fr->last;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     GRec* lds = s_rec[wave];
     const uint32_t nitems = a.queue[1];
@@ -430,7 +436,7 @@ void launch_tile_order(hipStream_t st, const uint32_t* ranges, int tiles, uint32
 }
 
 static void launch_composite(hipStream_t st, const CompositeArgs& a, bool duplex) {
-    const int tiles = a.k.TX * a.k.TY;
+    const int tiles = a.k.TX * a.k.TY;  // host copy of the frame's tile grid
     if (tiles <= 0) return;
     const dim3 g(persistent_grid(tiles)), b(256);
     if (duplex) {

@@ -1,0 +1,62 @@
+// Internal: the renderer context and entry points shared by the C ABI and
+// the serving runtime.
+#pragma once
+#include <array>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "duplexgs.h"
+#include "launch.h"
+
+struct dgs_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    int64_t cap_prims = 0, cap_gauss = 0, cap_keys = 0, cap_tiles = 0;
+    uint32_t *p_depth = nullptr, *p_ntiles = nullptr, *p_offsets = nullptr;
+    uint64_t* p_rect = nullptr;
+    float* cell_v = nullptr;
+    dgs::GRec* recs = nullptr;
+    uint64_t* grect = nullptr;
+    uint64_t *keys0 = nullptr, *keys1 = nullptr;
+    uint32_t *vals0 = nullptr, *vals1 = nullptr;
+    uint32_t* ranges = nullptr;
+    uint32_t* tile_order = nullptr;
+    uint64_t* scan_status = nullptr;
+    size_t scan_status_cap = 0;
+    uint64_t* sort_status = nullptr;
+    size_t sort_status_cap = 0;
+    dgs::FrameK* frame = nullptr;  // device copy of the current frame's camera and options
+    float* g2d = nullptr;  // [9][M] backward screen-space gradients
+    float* gv = nullptr;   // [N] backward dL/dv
+    int64_t cap_g2d = 0, cap_gv = 0;
+    uint32_t* hist = nullptr;     // [8][256]
+    uint32_t* misc = nullptr;     // [0] key total, [1] scan ticket, [2..9] sort tickets, [10] sort count,
+                                  // [11..12] compositor work-queue head and item count,
+                                  // [13] look-back frame counter
+    int* dev_err = nullptr;
+    unsigned long long* counters = nullptr;  // n_val, n_rendered, n_box, n_cell_hits
+
+    // last frame
+    int last_mode = -1, last_passes = 0;
+    int64_t last_prims = 0, last_gauss = 0, last_tiles = 0;
+    bool last_in_1 = false;
+
+    // stage timing
+    bool timing = false;
+    std::vector<std::array<hipEvent_t, DGS_NUM_STAGES + 1>> events;
+    size_t events_used = 0;
+};
+
+// The frame pipeline behind dgs_render.  With write_frame the camera,
+// options and output pointers are written to ctx->frame by the first kernel;
+// without it the caller has put them there (a captured frame replayed for a
+// new camera).  Host-side validation is the same in both cases.
+dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* cam, const dgs_render_opts* opts,
+                               const dgs_image* out, bool write_frame);
+
+// Validates camera and options and builds the device frame record.
+dgs_status dgs_internal_frame(dgs_ctx c, const dgs_camera* cam, const dgs_render_opts* opts, const dgs_image* out,
+                              dgs::FrameK* f);

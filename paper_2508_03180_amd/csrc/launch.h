@@ -4,33 +4,34 @@
 
 namespace dgs {
 
+// Writes the frame's camera and options to device memory (graph-safe kernel).
+void launch_set_frame(hipStream_t st, const FrameK& f, FrameK* dst);
+
 void launch_cell_preprocess(hipStream_t st, int N, const float* pos, const float* scale, const float* rot,
-                            const float* vsh, int vdeg, const CamK& k, const OptK& o, uint32_t* depth_bits,
+                            const float* vsh, int vdeg, const FrameK* fr, uint32_t* depth_bits,
                             uint64_t* prect, uint32_t* ntiles, float* v);
 
 void launch_gauss_project(hipStream_t st, int M, int K, const float* means, const float* scales,
-                          const float* rots, const float* opac, const float* sh, int sh_deg, const CamK& k,
-                          const OptK& o, const uint32_t* cell_ntiles, GRec* recs, uint64_t* grect,
-                          uint32_t* gdepth, uint32_t* gntiles);
-
-// Look-back status words carry a 30-bit epoch (never 0) that changes with
-// every scan or sort pass, so status buffers are zeroed once at allocation
-// and never cleared again.
-inline uint32_t next_epoch(uint32_t* counter) { return 1u + (++*counter % ((1u << 30) - 1u)); }
+                          const float* rots, const float* opac, const float* sh, int sh_deg, const FrameK* fr,
+                          const uint32_t* cell_ntiles, GRec* recs, uint64_t* grect, uint32_t* gdepth,
+                          uint32_t* gntiles);
 
 // Exclusive scan of n u32 values; *total receives the sum.  status needs
-// scan_status_words(n) 64-bit words; *ticket must be zero.
+// scan_status_words(n) 64-bit words; *ticket must be zero; *epoch is the
+// device frame counter (look-back tag j = 0).
 size_t scan_status_words(int64_t n);
 void launch_exclusive_scan(hipStream_t st, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
-                           uint64_t* status, uint32_t* epoch, uint32_t* ticket, int* err);
+                           uint64_t* status, const uint32_t* epoch, uint32_t* ticket, int* err);
 
 void launch_fill_u32(hipStream_t st, uint32_t* p, uint32_t v, size_t n);
 
-// Zeroes up to 8 small u32 buffers in one launch (graph-safe: no memset nodes).
+// Zeroes up to 8 small u32 buffers in one launch (graph-safe: no memset
+// nodes) and increments *bump (the look-back frame counter) when set.
 struct ClearList {
     uint32_t* p[8];
     size_t n[8];
     int count = 0;
+    uint32_t* bump = nullptr;
     void add(uint32_t* ptr, size_t words) {
         p[count] = ptr;
         n[count] = words;
@@ -53,7 +54,8 @@ void launch_tile_ranges(hipStream_t st, const uint64_t* keys, const uint32_t* n_
 // Onesweep LSD radix sort of (u64 key, u32 value) pairs on the low `bits`
 // bits.  The count is read on the device from *n_ptr (clamped to cap).
 // Returns true when the sorted data ends in (k1, v1), false for (k0, v0).
-// hist (8 x 256 words) and tickets (8 words) must be zero beforehand.
+// hist (8 x 256 words) and tickets (8 words) must be zero beforehand; pass p
+// tags its look-back words with epoch_tag(*epoch, 1 + p).
 struct SortScratch {
     uint32_t* hist;     // [8][256]
     uint64_t* status;   // sort_status_words(cap) look-back words
@@ -62,8 +64,8 @@ struct SortScratch {
 int sort_passes(int bits);
 size_t sort_status_words(int64_t cap);
 bool launch_radix_sort(hipStream_t st, uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1,
-                       const uint32_t* n_ptr, uint32_t cap, int bits, const SortScratch& s, uint32_t* epoch,
-                       int* err);
+                       const uint32_t* n_ptr, uint32_t cap, int bits, const SortScratch& s,
+                       const uint32_t* epoch, int* err);
 
 struct CompositeArgs {
     const uint32_t* ranges;
@@ -71,9 +73,10 @@ struct CompositeArgs {
     const GRec* recs;
     const float* cell_v;  // Duplex only
     int K;
-    CamK k;
+    const FrameK* fr;  // the frame's camera and options (device)
+    CamK k;            // filled from fr inside the kernel
     OptK o;
-    float* color;
+    float* color;  // the outputs are filled from fr inside the kernel
     float* D;
     float* T;
     int32_t* last;
@@ -99,7 +102,8 @@ struct BwdArgs {
     const GRec* recs;
     const float* cell_v;
     int K, M;
-    CamK k;
+    const FrameK* fr;  // the frame's camera and options (device)
+    CamK k;            // filled from fr inside the kernels
     OptK o;
     const float* color;
     const float* D;

@@ -132,12 +132,15 @@ __device__ inline void unit_dir(const CamK& k, float px, float py, float pz, flo
 __global__ __launch_bounds__(256) void k_cell_preprocess(int N, const float* __restrict__ pos,
                                                          const float* __restrict__ scale,
                                                          const float* __restrict__ rot,
-                                                         const float* __restrict__ vsh, int vdeg, CamK k,
-                                                         OptK o, uint32_t* __restrict__ depth_bits,
+                                                         const float* __restrict__ vsh, int vdeg,
+                                                         const FrameK* __restrict__ fr,
+                                                         uint32_t* __restrict__ depth_bits,
                                                          uint64_t* __restrict__ prect,
                                                          uint32_t* __restrict__ ntiles, float* __restrict__ v_out) {
     int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
+    const CamK k = fr->k;
+    const OptK o = fr->o;
     float p0 = pos[n], p1 = pos[N + n], p2 = pos[2 * N + n];
     float tc[3];
     view32(k, p0, p1, p2, tc);
@@ -182,10 +185,12 @@ __global__ __launch_bounds__(256) void k_cell_preprocess(int N, const float* __r
 __global__ __launch_bounds__(256) void k_gauss_project(
     int M, int K, const float* __restrict__ means, const float* __restrict__ scales,
     const float* __restrict__ rots, const float* __restrict__ opac, const float* __restrict__ sh, int sh_deg,
-    CamK k, OptK o, const uint32_t* __restrict__ cell_ntiles, GRec* __restrict__ recs,
+    const FrameK* __restrict__ fr, const uint32_t* __restrict__ cell_ntiles, GRec* __restrict__ recs,
     uint64_t* __restrict__ grect, uint32_t* __restrict__ gdepth, uint32_t* __restrict__ gntiles) {
     int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= M) return;
+    const CamK k = fr->k;
+    const OptK o = fr->o;
     if (cell_ntiles && cell_ntiles[g / K] == 0) {
         grect[g] = kEmptyRect;
         return;
@@ -257,20 +262,28 @@ __global__ __launch_bounds__(256) void k_gauss_project(
 }
 
 void launch_cell_preprocess(hipStream_t st, int N, const float* pos, const float* scale, const float* rot,
-                            const float* vsh, int vdeg, const CamK& k, const OptK& o, uint32_t* depth_bits,
+                            const float* vsh, int vdeg, const FrameK* fr, uint32_t* depth_bits,
                             uint64_t* prect, uint32_t* ntiles, float* v) {
     if (N <= 0) return;
     hipLaunchKernelGGL(k_cell_preprocess, dim3((N + 255) / 256), dim3(256), 0, st, N, pos, scale, rot, vsh, vdeg,
-                       k, o, depth_bits, prect, ntiles, v);
+                       fr, depth_bits, prect, ntiles, v);
 }
 
 void launch_gauss_project(hipStream_t st, int M, int K, const float* means, const float* scales,
-                          const float* rots, const float* opac, const float* sh, int sh_deg, const CamK& k,
-                          const OptK& o, const uint32_t* cell_ntiles, GRec* recs, uint64_t* grect,
-                          uint32_t* gdepth, uint32_t* gntiles) {
+                          const float* rots, const float* opac, const float* sh, int sh_deg, const FrameK* fr,
+                          const uint32_t* cell_ntiles, GRec* recs, uint64_t* grect, uint32_t* gdepth,
+                          uint32_t* gntiles) {
     if (M <= 0) return;
     hipLaunchKernelGGL(k_gauss_project, dim3((M + 255) / 256), dim3(256), 0, st, M, K, means, scales, rots, opac,
-                       sh, sh_deg, k, o, cell_ntiles, recs, grect, gdepth, gntiles);
+                       sh, sh_deg, fr, cell_ntiles, recs, grect, gdepth, gntiles);
+}
+
+__global__ void k_set_frame(FrameK f, FrameK* dst) {
+    if (threadIdx.x == 0) *dst = f;
+}
+
+void launch_set_frame(hipStream_t st, const FrameK& f, FrameK* dst) {
+    hipLaunchKernelGGL(k_set_frame, dim3(1), dim3(64), 0, st, f, dst);
 }
 
 }  // namespace dgs

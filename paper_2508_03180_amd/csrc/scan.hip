@@ -38,8 +38,9 @@ __device__ inline uint32_t wave_incl_scan(uint32_t v) {
 __global__ __launch_bounds__(kScanThreads) void k_scan_excl(const uint32_t* __restrict__ in,
                                                              uint32_t* __restrict__ out, int64_t n,
                                                              uint32_t* __restrict__ total, uint64_t* status,
-                                                             uint32_t epoch, uint32_t* ticket, int* err) {
+                                                             const uint32_t* ep, uint32_t* ticket, int* err) {
     __shared__ uint32_t s_part, s_wsum[kScanThreads / 64], s_excl;
+    const uint32_t epoch = epoch_tag(*ep, 0);
     const int nparts = (int)((n + kScanPart - 1) / kScanPart);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (;;) {
@@ -114,7 +115,7 @@ void launch_fill_u32(hipStream_t st, uint32_t* p, uint32_t v, size_t n) {
 size_t scan_status_words(int64_t n) { return (size_t)((n + kScanPart - 1) / kScanPart) + 1; }
 
 void launch_exclusive_scan(hipStream_t st, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
-                           uint64_t* status, uint32_t* epoch, uint32_t* ticket, int* err) {
+                           uint64_t* status, const uint32_t* epoch, uint32_t* ticket, int* err) {
     if (n <= 0) {
         launch_fill_u32(st, total, 0u, 1);
         return;
@@ -122,19 +123,20 @@ void launch_exclusive_scan(hipStream_t st, const uint32_t* in, uint32_t* out, in
     const size_t nparts = (size_t)((n + kScanPart - 1) / kScanPart);
     const unsigned grid = (unsigned)(nparts < 1024 ? nparts : 1024);
     hipLaunchKernelGGL(k_scan_excl, dim3(grid), dim3(kScanThreads), 0, st, in, out, n, total, status,
-                       next_epoch(epoch), ticket, err);
+                       epoch, ticket, err);
 }
 
 __global__ void k_clear(ClearList l) {
     const size_t gid = blockIdx.x * (size_t)blockDim.x + threadIdx.x, stride = (size_t)gridDim.x * blockDim.x;
     for (int b = 0; b < l.count; b++)
         for (size_t i = gid; i < l.n[b]; i += stride) l.p[b][i] = 0u;
+    if (l.bump && gid == 0) *l.bump += 1u;
 }
 
 void launch_clear(hipStream_t st, const ClearList& l) {
     size_t most = 0;
     for (int b = 0; b < l.count; b++) most = l.n[b] > most ? l.n[b] : most;
-    if (most == 0) return;
+    if (most == 0) most = 1;
     unsigned grid = (unsigned)((most + 255) / 256);
     if (grid > 256) grid = 256;
     hipLaunchKernelGGL(k_clear, dim3(grid), dim3(256), 0, st, l);

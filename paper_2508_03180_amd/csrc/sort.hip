@@ -117,8 +117,8 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
                                                            uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                            const uint32_t* __restrict__ n_ptr, uint32_t cap,
                                                            int shift, const uint32_t* __restrict__ goff,
-                                                           uint64_t* status, uint32_t epoch, uint32_t* ticket,
-                                                           int* err) {
+                                                           uint64_t* status, const uint32_t* ep, uint32_t pass_tag,
+                                                           uint32_t* ticket, int* err) {
     __shared__ uint64_t s_key[kSortPart];
     __shared__ uint32_t s_val[kSortPart];
     __shared__ uint32_t s_cnt[kSortWaves][256];  // per-wave digit counts, then per-wave offsets
@@ -127,6 +127,7 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
     __shared__ uint32_t s_wsum[kSortWaves];
     __shared__ uint32_t s_part;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t epoch = epoch_tag(*ep, pass_tag);
     uint32_t n = *n_ptr;
     if (n > cap) n = cap;
     const uint32_t nparts = (n + kSortPart - 1) / kSortPart;
@@ -225,8 +226,8 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
 }
 
 bool launch_radix_sort(hipStream_t st, uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1,
-                       const uint32_t* n_ptr, uint32_t cap, int bits, const SortScratch& s, uint32_t* epoch,
-                       int* err) {
+                       const uint32_t* n_ptr, uint32_t cap, int bits, const SortScratch& s,
+                       const uint32_t* epoch, int* err) {
     const int passes = sort_passes(bits);
     if (passes <= 0 || cap == 0) return false;
     hipLaunchKernelGGL(k_radix_hist, dim3(kHistBlocks), dim3(kSortThreads), 0, st, k0, n_ptr, cap, passes, s.hist);
@@ -236,9 +237,8 @@ bool launch_radix_sort(hipStream_t st, uint64_t* k0, uint32_t* v0, uint64_t* k1,
     uint64_t *ki = k0, *ko = k1;
     uint32_t *vi = v0, *vo = v1;
     for (int p = 0; p < passes; p++) {
-        const uint32_t ep = next_epoch(epoch);
         hipLaunchKernelGGL(k_onesweep, dim3(grid), dim3(kSortThreads), 0, st, ki, vi, ko, vo, n_ptr, cap, 8 * p,
-                           s.hist + p * 256, s.status, ep, s.tickets + p, err);
+                           s.hist + p * 256, s.status, epoch, (uint32_t)(1 + p), s.tickets + p, err);
         uint64_t* tk = ki; ki = ko; ko = tk;
         uint32_t* tv = vi; vi = vo; vo = tv;
     }
