@@ -53,6 +53,11 @@ def parse():
     p.add_argument("--no-alpha", action="store_true")
     p.add_argument("--cpu-frames", type=int, default=4)
     p.add_argument("--bwd-steps", type=int, default=10)
+    p.add_argument("--no-serve", action="store_true")
+    p.add_argument("--serve-seconds", type=float, default=4.0, help="length of each Poisson stream")
+    p.add_argument("--serve-rates", default="30,120,480", help="request rates (req/s)")
+    p.add_argument("--serve-slots", type=int, default=4)
+    p.add_argument("--serve-budget-gb", type=float, default=16.0, help="workspace budget of the server")
     return p.parse_args()
 
 
@@ -122,6 +127,64 @@ def differentiation(r, scene, cam, steps):
     return {"loss": "0.8 L1 + 0.2 (1 - SSIM 11x11) vs perturbed-scene target", "width": 1920, "height": 1080,
             "fwd_loss_bwd_ms": round(dt * 1e3, 3), "backward_ms": round(bt * 1e3, 3),
             "final_loss": round(float(loss), 5)}
+
+
+SERVE_SIZES = [(640, 480), (1280, 720), (1920, 1080), (3840, 2160)]
+
+
+def serving(a):
+    """Serving load: four scenes (200k, 1M, 3M, 6M Gaussians), resolution
+    uniform over SERVE_SIZES, Poisson arrivals at each rate; the native server
+    (frames in flight on several streams, graph replay, memory budget)
+    against one-at-a-time serving (one slot, direct launches) on the same
+    request stream."""
+    import numpy as np
+
+    from paper_2508_03180_amd import scenes
+    from paper_2508_03180_amd.renderer import DeviceScene
+    from paper_2508_03180_amd.serving import Server, poisson_schedule, run_load, run_saturated
+
+    gen = [lambda: scenes.make_mid_scene(40, n_cells=20_000), lambda: scenes.make_mid_scene(41),
+           lambda: scenes.make_large_scene(42, n_cells=300_000), lambda: scenes.make_large_scene(43)]
+    ds = []
+    for g in gen:
+        ds.append(DeviceScene.from_numpy(g(), "cuda:0"))
+    ncam = 12
+    cams = {}
+    for i in range(4):
+        cams[i] = {}
+        for (w, h) in SERVE_SIZES:
+            if i < 2:
+                cams[i][(w, h)] = scenes.orbit_cameras(ncam, w, h, step_deg=30.0)
+            else:
+                cams[i][(w, h)] = scenes.aerial_orbit_cameras(ncam, w, h, step_deg=30.0)
+    rates = [float(x) for x in a.serve_rates.split(",") if x]
+    warm = poisson_schedule(1000.0, 0.25, 4, cams, seed=7)
+    sat = poisson_schedule(1000.0, 0.3, 4, cams, seed=8)
+    out = {"scenes_gaussians": [d.M for d in ds], "sizes": [f"{w}x{h}" for w, h in SERVE_SIZES],
+           "seconds_per_rate": a.serve_seconds, "budget_gb": a.serve_budget_gb}
+    configs = {"server": dict(num_slots=a.serve_slots, use_graphs=True,
+                              memory_budget=int(a.serve_budget_gb * (1 << 30))),
+               "one_at_a_time": dict(num_slots=1, use_graphs=False, memory_budget=0)}
+    for name, kw in configs.items():
+        with Server(0, **kw) as srv:
+            ids = [srv.add_scene(d) for d in ds]
+            run_saturated(srv, ids, warm)  # captures graphs, learns key counts
+            res = {"saturated_frames_per_s": round(run_saturated(srv, ids, sat), 2)}
+            for k, rate in enumerate(rates):
+                sched = poisson_schedule(rate, a.serve_seconds, 4, cams, seed=100 + k)
+                res[f"{int(rate)}"] = {kk: (round(v, 4) if isinstance(v, float) else v)
+                                       for kk, v in run_load(srv, ids, sched, rate).summary().items()}
+            st = srv.stats()
+            res["stats"] = {k: st[k] for k in ("completed", "failed", "retries", "graph_captures",
+                                               "graph_replays", "releases", "peak_workspace_bytes")}
+        out[name] = res
+    for k in [f"{int(r)}" for r in rates]:
+        s, o = out["server"][k], out["one_at_a_time"][k]
+        out[f"p99_speedup_{k}"] = round(o["p99_ms"] / s["p99_ms"], 3) if s["p99_ms"] else None
+    out["throughput_speedup"] = round(out["server"]["saturated_frames_per_s"]
+                                      / out["one_at_a_time"]["saturated_frames_per_s"], 3)
+    return out
 
 
 def main():
@@ -231,6 +294,8 @@ def main():
     # against a target rendered from a perturbed copy of the scene
     bwd = differentiation(r, scene, cams[0], a.bwd_steps)
 
+    serve = None if a.no_serve else serving(a)
+
     cpu = None
     if not a.no_cpu_baseline:
         import oracle
@@ -262,6 +327,7 @@ def main():
         "termination_ratio": round(1 - cnt["n_rendered"] / max(cnt["n_val"], 1), 4),
         "roofline": roof,
         "differentiation": bwd,
+        "serving": serve,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

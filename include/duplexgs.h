@@ -223,6 +223,98 @@ dgs_status dgs_get_timing(dgs_ctx ctx, float* ms, int32_t n_stages, int32_t* fra
  * buffers of n entries. */
 dgs_status dgs_sort_pairs(dgs_ctx ctx, uint64_t* keys, uint32_t* values, int64_t n, int32_t key_bits);
 
+/*
+ * Serving runtime.  A server renders requests (scene, camera, options,
+ * output image) submitted from any host thread.  It keeps num_slots frames
+ * in flight, each slot with its own context, workspace and HIP stream, and
+ * starts the next queued request as soon as a slot frees (continuous
+ * batching).  Requests start in submission order; one whose workspace would
+ * push the slots' total over memory_budget waits until running frames finish
+ * (idle slots give their workspace back first), and one that could not fit
+ * even alone fails with DGS_ERR_OOM.  With use_graphs, the first request of
+ * each (scene, image size, mode, DGS_FLAG_STATS) on a slot is captured into a
+ * HIP graph and later ones replay it with their own camera, options and
+ * output pointers.  A frame that overflows its key capacity is run again
+ * after the slot grows (up to 4 attempts).  Results are bit-identical to
+ * dgs_render of the same request.  Every server function is thread-safe.
+ * Scene arrays and output buffers are caller-owned device memory that must
+ * stay valid until the requests using them have finished.
+ */
+typedef struct dgs_server_s* dgs_server;
+
+typedef struct {
+    int32_t num_slots;     /* frames in flight (1..16); each holds its own workspace */
+    int32_t use_graphs;    /* nonzero: capture and replay HIP graphs per request shape */
+    int64_t memory_budget; /* bytes of workspace all slots may hold together; 0 = unlimited */
+} dgs_server_config;
+
+/* Host-only stand-in for the device, for tests of the scheduler: a frame
+ * takes seconds_fixed + seconds_per_mpixel * W*H/1e6 seconds and produces
+ * keys_per_pixel * W*H keys (more than the slot's capacity is an overflow).
+ * Workspace is accounted exactly as on the device but nothing is allocated
+ * and no pointer is dereferenced. */
+typedef struct {
+    double seconds_fixed;
+    double seconds_per_mpixel;
+    double keys_per_pixel;
+} dgs_sim_device;
+
+typedef enum {
+    DGS_REQ_QUEUED = 0,
+    DGS_REQ_RUNNING = 1,
+    DGS_REQ_DONE = 2,      /* output written */
+    DGS_REQ_FAILED = 3,    /* result holds the dgs_status */
+    DGS_REQ_CANCELLED = 4
+} dgs_request_state;
+
+typedef struct {
+    int32_t state;    /* dgs_request_state */
+    int32_t result;   /* dgs_status of a finished request */
+    int32_t slot;     /* slot of the last attempt (-1 before the first) */
+    int32_t attempts; /* launches, including capacity retries */
+    int32_t graph;    /* last attempt: 0 direct launches, 1 graph replay, 2 graph captured */
+    int32_t reserved;
+    int64_t num_keys; /* (tile, primitive) keys of the last attempt */
+    double t_submit;  /* host steady-clock seconds: submission, first launch, completion seen */
+    double t_start;
+    double t_done;
+} dgs_request_info;
+
+typedef struct {
+    int64_t submitted, completed, failed, cancelled;
+    int64_t retries;        /* capacity-overflow re-runs */
+    int64_t graph_captures, graph_replays;
+    int64_t releases;       /* idle workspaces given back for the memory budget */
+    int64_t workspace_bytes, peak_workspace_bytes;
+    int64_t queued, running;
+} dgs_server_stats;
+
+/* num_slots 4, use_graphs 1, memory_budget 0. */
+void dgs_server_default_config(dgs_server_config* cfg);
+dgs_status dgs_server_create(int device, const dgs_server_config* cfg, dgs_server* out);
+dgs_status dgs_server_create_simulated(const dgs_server_config* cfg, const dgs_sim_device* sim, dgs_server* out);
+/* Registers a scene (device arrays, caller-owned); *scene_id receives its id. */
+dgs_status dgs_server_add_scene(dgs_server srv, const dgs_scene* scene, int32_t* scene_id);
+/* Validates and queues a request (host structs are copied; opts may be
+ * NULL); *request_id receives its id.  Returns at once. */
+dgs_status dgs_server_submit(dgs_server srv, int32_t scene_id, const dgs_camera* cam, const dgs_render_opts* opts,
+                             const dgs_image* out, int64_t* request_id);
+/* Current state of a request (host struct). */
+dgs_status dgs_server_query(dgs_server srv, int64_t request_id, dgs_request_info* info);
+/* Blocks until the request has finished (timeout_s < 0: no limit);
+ * DGS_ERR_TIMEOUT if it has not within timeout_s.  info may be NULL. */
+dgs_status dgs_server_wait(dgs_server srv, int64_t request_id, double timeout_s, dgs_request_info* info);
+/* Cancels a request that has not started (DGS_ERR_INVALID_ARG otherwise). */
+dgs_status dgs_server_cancel(dgs_server srv, int64_t request_id);
+/* Forgets a finished request. */
+dgs_status dgs_server_release(dgs_server srv, int64_t request_id);
+dgs_status dgs_server_get_stats(dgs_server srv, dgs_server_stats* out);
+/* Message of the server's last error (never NULL; valid until the calling
+ * thread's next call of this function). */
+const char* dgs_server_last_error(dgs_server srv);
+/* Cancels queued requests, waits for running ones and frees everything. */
+dgs_status dgs_server_destroy(dgs_server srv);
+
 #ifdef __cplusplus
 }
 #endif

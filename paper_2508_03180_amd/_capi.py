@@ -63,7 +63,30 @@ class dgs_stats(C.Structure):
                 ("device_error", C.c_int32), ("sort_passes", C.c_int32)]
 
 
+class dgs_server_config(C.Structure):
+    _fields_ = [("num_slots", C.c_int32), ("use_graphs", C.c_int32), ("memory_budget", C.c_int64)]
+
+
+class dgs_sim_device(C.Structure):
+    _fields_ = [("seconds_fixed", C.c_double), ("seconds_per_mpixel", C.c_double), ("keys_per_pixel", C.c_double)]
+
+
+class dgs_request_info(C.Structure):
+    _fields_ = [("state", C.c_int32), ("result", C.c_int32), ("slot", C.c_int32), ("attempts", C.c_int32),
+                ("graph", C.c_int32), ("reserved", C.c_int32), ("num_keys", C.c_int64), ("t_submit", C.c_double),
+                ("t_start", C.c_double), ("t_done", C.c_double)]
+
+
+class dgs_server_stats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("submitted", "completed", "failed", "cancelled", "retries",
+                                          "graph_captures", "graph_replays", "releases", "workspace_bytes",
+                                          "peak_workspace_bytes", "queued", "running")]
+
+
+DGS_REQ_QUEUED, DGS_REQ_RUNNING, DGS_REQ_DONE, DGS_REQ_FAILED, DGS_REQ_CANCELLED = range(5)
+
 dgs_ctx = C.c_void_p
+dgs_server = C.c_void_p
 
 # name -> (restype, argtypes)
 _SIGS = {
@@ -86,6 +109,20 @@ _SIGS = {
     "dgs_sort_pairs": (C.c_int, [dgs_ctx, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32]),
     "dgs_set_timing": (C.c_int, [dgs_ctx, C.c_int32]),
     "dgs_get_timing": (C.c_int, [dgs_ctx, C.POINTER(C.c_float), C.c_int32, C.POINTER(C.c_int32)]),
+    "dgs_server_default_config": (None, [C.POINTER(dgs_server_config)]),
+    "dgs_server_create": (C.c_int, [C.c_int, C.POINTER(dgs_server_config), C.POINTER(dgs_server)]),
+    "dgs_server_create_simulated": (C.c_int, [C.POINTER(dgs_server_config), C.POINTER(dgs_sim_device),
+                                              C.POINTER(dgs_server)]),
+    "dgs_server_add_scene": (C.c_int, [dgs_server, C.POINTER(dgs_scene), C.POINTER(C.c_int32)]),
+    "dgs_server_submit": (C.c_int, [dgs_server, C.c_int32, C.POINTER(dgs_camera), C.POINTER(dgs_render_opts),
+                                    C.POINTER(dgs_image), C.POINTER(C.c_int64)]),
+    "dgs_server_query": (C.c_int, [dgs_server, C.c_int64, C.POINTER(dgs_request_info)]),
+    "dgs_server_wait": (C.c_int, [dgs_server, C.c_int64, C.c_double, C.POINTER(dgs_request_info)]),
+    "dgs_server_cancel": (C.c_int, [dgs_server, C.c_int64]),
+    "dgs_server_release": (C.c_int, [dgs_server, C.c_int64]),
+    "dgs_server_get_stats": (C.c_int, [dgs_server, C.POINTER(dgs_server_stats)]),
+    "dgs_server_last_error": (C.c_char_p, [dgs_server]),
+    "dgs_server_destroy": (C.c_int, [dgs_server]),
 }
 
 DGS_NUM_STAGES = 6
@@ -201,3 +238,83 @@ def dgs_get_timing(ctx):
     frames = C.c_int32()
     check(lib().dgs_get_timing(ctx, ms, DGS_NUM_STAGES, C.byref(frames)), ctx)
     return list(ms), frames.value
+
+
+# serving runtime
+def dgs_server_default_config():
+    cfg = dgs_server_config()
+    lib().dgs_server_default_config(C.byref(cfg))
+    return cfg
+
+
+def server_check(status, srv):
+    if status != DGS_OK:
+        raise DgsError(status, lib().dgs_server_last_error(srv).decode() if srv else "")
+    return status
+
+
+def dgs_server_create(device, cfg):
+    h = dgs_server()
+    st = lib().dgs_server_create(int(device), C.byref(cfg), C.byref(h))
+    if st != DGS_OK:
+        raise DgsError(st, "server creation failed")
+    return h
+
+
+def dgs_server_create_simulated(cfg, sim):
+    h = dgs_server()
+    st = lib().dgs_server_create_simulated(C.byref(cfg), C.byref(sim), C.byref(h))
+    if st != DGS_OK:
+        raise DgsError(st, "simulated server creation failed")
+    return h
+
+
+def dgs_server_add_scene(srv, scene):
+    sid = C.c_int32()
+    server_check(lib().dgs_server_add_scene(srv, C.byref(scene), C.byref(sid)), srv)
+    return sid.value
+
+
+def dgs_server_submit(srv, scene_id, cam, opts, image):
+    rid = C.c_int64()
+    server_check(lib().dgs_server_submit(srv, int(scene_id), C.byref(cam), C.byref(opts) if opts is not None
+                                         else None, C.byref(image), C.byref(rid)), srv)
+    return rid.value
+
+
+def dgs_server_query(srv, request_id):
+    info = dgs_request_info()
+    server_check(lib().dgs_server_query(srv, int(request_id), C.byref(info)), srv)
+    return info
+
+
+def dgs_server_wait(srv, request_id, timeout_s=-1.0):
+    """The request's info once finished, or None on timeout."""
+    info = dgs_request_info()
+    st = lib().dgs_server_wait(srv, int(request_id), float(timeout_s), C.byref(info))
+    if st == DGS_ERR_TIMEOUT:
+        return None
+    server_check(st, srv)
+    return info
+
+
+def dgs_server_cancel(srv, request_id):
+    return lib().dgs_server_cancel(srv, int(request_id))
+
+
+def dgs_server_release(srv, request_id):
+    return lib().dgs_server_release(srv, int(request_id))
+
+
+def dgs_server_get_stats(srv):
+    s = dgs_server_stats()
+    server_check(lib().dgs_server_get_stats(srv, C.byref(s)), srv)
+    return s
+
+
+def dgs_server_last_error(srv):
+    return lib().dgs_server_last_error(srv).decode()
+
+
+def dgs_server_destroy(srv):
+    return lib().dgs_server_destroy(srv)

@@ -37,43 +37,49 @@ hipError_t grow_zeroed(uint64_t*& p, int64_t want, hipStream_t st) {
 }
 
 dgs_status ensure(dgs_ctx c, int64_t prims, int64_t gauss, int64_t keys, int64_t tiles) {
+    if (keys > (int64_t)(1u << 30)) return fail(c, DGS_ERR_INVALID_ARG, "key capacity above 2^30");
+    const WorkspaceCaps cur{c->cap_prims, c->cap_gauss, c->cap_keys, c->cap_tiles};
+    const WorkspaceCaps nc = dgs_internal_plan(cur, WorkspaceCaps{prims, gauss, keys, tiles});
     hipError_t e = hipSuccess;
-    if (prims > c->cap_prims) {
-        prims = prims + prims / 4;
-        if ((e = grow(c->p_depth, prims, c->stream)) != hipSuccess) goto oom;
-        if ((e = grow(c->p_ntiles, prims, c->stream)) != hipSuccess) goto oom;
-        if ((e = grow(c->p_offsets, prims, c->stream)) != hipSuccess) goto oom;
-        if ((e = grow(c->p_rect, prims, c->stream)) != hipSuccess) goto oom;
-        if ((e = grow(c->cell_v, prims, c->stream)) != hipSuccess) goto oom;
-        size_t sw = scan_status_words(prims);
+    if (nc.prims != cur.prims) {
+        c->generation++;
+        if ((e = grow(c->p_depth, nc.prims, c->stream)) != hipSuccess) goto oom;
+        if ((e = grow(c->p_ntiles, nc.prims, c->stream)) != hipSuccess) goto oom;
+        if ((e = grow(c->p_offsets, nc.prims, c->stream)) != hipSuccess) goto oom;
+        if ((e = grow(c->p_rect, nc.prims, c->stream)) != hipSuccess) goto oom;
+        if ((e = grow(c->cell_v, nc.prims, c->stream)) != hipSuccess) goto oom;
+        size_t sw = scan_status_words(nc.prims);
         if ((e = grow_zeroed(c->scan_status, (int64_t)sw, c->stream)) != hipSuccess) goto oom;
         c->scan_status_cap = sw;
-        c->cap_prims = prims;
+        c->cap_prims = nc.prims;
     }
-    if (gauss > c->cap_gauss) {
-        gauss = gauss + gauss / 4;
-        if ((e = grow(c->recs, gauss, c->stream)) != hipSuccess) goto oom;
-        if ((e = grow(c->grect, gauss, c->stream)) != hipSuccess) goto oom;
-        c->cap_gauss = gauss;
+    if (nc.gauss != cur.gauss) {
+        c->generation++;
+        if ((e = grow(c->recs, nc.gauss, c->stream)) != hipSuccess) goto oom;
+        if ((e = grow(c->grect, nc.gauss, c->stream)) != hipSuccess) goto oom;
+        c->cap_gauss = nc.gauss;
     }
-    if (keys > c->cap_keys) {
-        if (keys > (int64_t)(1u << 30)) return fail(c, DGS_ERR_INVALID_ARG, "key capacity above 2^30");
-        if ((e = grow(c->keys0, keys, c->stream)) != hipSuccess) goto oom;
-        if ((e = grow(c->keys1, keys, c->stream)) != hipSuccess) goto oom;
-        if ((e = grow(c->vals0, keys, c->stream)) != hipSuccess) goto oom;
-        if ((e = grow(c->vals1, keys, c->stream)) != hipSuccess) goto oom;
-        size_t sw = sort_status_words(keys);
+    if (nc.keys != cur.keys) {
+        c->generation++;
+        if ((e = grow(c->keys0, nc.keys, c->stream)) != hipSuccess) goto oom;
+        if ((e = grow(c->keys1, nc.keys, c->stream)) != hipSuccess) goto oom;
+        if ((e = grow(c->vals0, nc.keys, c->stream)) != hipSuccess) goto oom;
+        if ((e = grow(c->vals1, nc.keys, c->stream)) != hipSuccess) goto oom;
+        size_t sw = sort_status_words(nc.keys);
         if ((e = grow_zeroed(c->sort_status, (int64_t)sw, c->stream)) != hipSuccess) goto oom;
         c->sort_status_cap = sw;
-        c->cap_keys = keys;
+        c->cap_keys = nc.keys;
     }
-    if (tiles > c->cap_tiles) {
-        if ((e = grow(c->ranges, 2 * tiles, c->stream)) != hipSuccess) goto oom;
-        if ((e = grow(c->tile_order, 4 * tiles, c->stream)) != hipSuccess) goto oom;
-        c->cap_tiles = tiles;
+    if (nc.tiles != cur.tiles) {
+        c->generation++;
+        if ((e = grow(c->ranges, 2 * nc.tiles, c->stream)) != hipSuccess) goto oom;
+        if ((e = grow(c->tile_order, 4 * nc.tiles, c->stream)) != hipSuccess) goto oom;
+        c->cap_tiles = nc.tiles;
     }
     return DGS_OK;
 oom:
+    // a partial growth leaves the buffers of the failed group unusable: drop them all
+    dgs_internal_release(c);
     return fail(c, DGS_ERR_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
 }
 
@@ -189,6 +195,68 @@ __global__ void k_unpack_rects(const uint64_t* in, int64_t n, int32_t* out) {
 
 }  // namespace
 
+WorkspaceCaps dgs_internal_plan(const WorkspaceCaps& cur, const WorkspaceCaps& want) {
+    WorkspaceCaps c = cur;
+    if (want.prims > cur.prims) c.prims = want.prims + want.prims / 4;
+    if (want.gauss > cur.gauss) c.gauss = want.gauss + want.gauss / 4;
+    if (want.keys > cur.keys) c.keys = want.keys;
+    if (want.tiles > cur.tiles) c.tiles = want.tiles;
+    return c;
+}
+
+int64_t dgs_internal_bytes(const WorkspaceCaps& c) {
+    int64_t b = 0;
+    if (c.prims > 0) b += c.prims * (3 * 4 + 8 + 4) + (int64_t)scan_status_words(c.prims) * 8;
+    if (c.gauss > 0) b += c.gauss * ((int64_t)sizeof(GRec) + 8);
+    if (c.keys > 0) b += c.keys * (2 * 8 + 2 * 4) + (int64_t)sort_status_words(c.keys) * 8;
+    if (c.tiles > 0) b += c.tiles * (2 + 4) * 4;
+    return b;
+}
+
+WorkspaceCaps dgs_internal_caps(dgs_ctx c) { return WorkspaceCaps{c->cap_prims, c->cap_gauss, c->cap_keys, c->cap_tiles}; }
+
+void dgs_internal_release(dgs_ctx c) {
+    hipSetDevice(c->device);
+    hipStreamSynchronize(c->stream);
+    void** bufs[] = {(void**)&c->p_depth, (void**)&c->p_ntiles, (void**)&c->p_offsets, (void**)&c->p_rect,
+                     (void**)&c->cell_v, (void**)&c->recs, (void**)&c->grect, (void**)&c->keys0,
+                     (void**)&c->keys1, (void**)&c->vals0, (void**)&c->vals1, (void**)&c->ranges,
+                     (void**)&c->tile_order, (void**)&c->scan_status, (void**)&c->sort_status};
+    for (void** p : bufs) {
+        if (*p) hipFree(*p);
+        *p = nullptr;
+    }
+    c->cap_prims = c->cap_gauss = c->cap_keys = c->cap_tiles = 0;
+    c->scan_status_cap = c->sort_status_cap = 0;
+    c->last_mode = -1;
+    c->generation++;
+}
+
+dgs_status dgs_internal_frame(dgs_ctx c, const dgs_camera* cam, const dgs_render_opts* opts, const dgs_image* out,
+                              FrameK* f, int* mode) {
+    dgs_status st;
+    if ((st = make_cam(c, cam, f->k)) != DGS_OK) return st;
+    if ((st = make_opts(c, opts, f->o, *mode)) != DGS_OK) return st;
+    if (!out || !out->color) return fail(c, DGS_ERR_INVALID_ARG, "output color buffer is NULL");
+    f->color = out->color;
+    f->D = out->weight_sum;
+    f->T = out->final_T;
+    f->last = out->last;
+    return DGS_OK;
+}
+
+dgs_status dgs_internal_check_scene(dgs_ctx c, const dgs_scene* s, int mode) { return check_scene(c, s, mode); }
+
+dgs_status dgs_internal_prepare(dgs_ctx c, const dgs_scene* s, int mode, int width, int height, int64_t keys) {
+    const int64_t M = (int64_t)s->num_cells * s->gaussians_per_cell;
+    const int64_t P = mode == DGS_MODE_DUPLEX ? s->num_cells : M;
+    const int64_t tiles = (int64_t)((width + kTile - 1) / kTile) * ((height + kTile - 1) / kTile);
+    hipSetDevice(c->device);
+    return ensure(c, P, M, keys, tiles);
+}
+
+int64_t dgs_internal_default_keys(int64_t prims) { return prims * 8 > (1 << 20) ? prims * 8 : (1 << 20); }
+
 extern "C" {
 
 void dgs_default_opts(dgs_render_opts* o) {
@@ -283,7 +351,7 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     const int tiles = k.TX * k.TY;
     const int P = mode == DGS_MODE_DUPLEX ? N : M;
     int64_t want_keys = c->cap_keys;
-    if (want_keys == 0) want_keys = (int64_t)P * 8 > (1 << 20) ? (int64_t)P * 8 : (1 << 20);
+    if (want_keys == 0) want_keys = dgs_internal_default_keys(P);
     if ((st = ensure(c, P, M, want_keys, tiles)) != DGS_OK) return st;
     const uint32_t cap = (uint32_t)c->cap_keys;
     hipStream_t q = c->stream;

@@ -15,6 +15,7 @@ struct dgs_ctx_s {
     std::string err;
 
     int64_t cap_prims = 0, cap_gauss = 0, cap_keys = 0, cap_tiles = 0;
+    uint64_t generation = 0;  // bumped whenever a workspace buffer moves (captured graphs go stale)
     uint32_t *p_depth = nullptr, *p_ntiles = nullptr, *p_offsets = nullptr;
     uint64_t* p_rect = nullptr;
     float* cell_v = nullptr;
@@ -50,6 +51,21 @@ struct dgs_ctx_s {
     size_t events_used = 0;
 };
 
+// Workspace capacities (elements): cells or Gaussians that get keys,
+// projected Gaussians, sort keys, screen tiles.
+struct WorkspaceCaps {
+    int64_t prims, gauss, keys, tiles;
+};
+// Capacities after growing `cur` to hold `want` (the growth policy of every
+// render), and the device bytes a context holds at given capacities.
+WorkspaceCaps dgs_internal_plan(const WorkspaceCaps& cur, const WorkspaceCaps& want);
+int64_t dgs_internal_bytes(const WorkspaceCaps& c);
+WorkspaceCaps dgs_internal_caps(dgs_ctx c);
+// Key capacity a render starts with when none was reserved.
+int64_t dgs_internal_default_keys(int64_t prims);
+// Frees the context's workspace (capacities drop to zero); synchronises.
+void dgs_internal_release(dgs_ctx c);
+
 // The frame pipeline behind dgs_render.  With write_frame the camera,
 // options and output pointers are written to ctx->frame by the first kernel;
 // without it the caller has put them there (a captured frame replayed for a
@@ -57,6 +73,12 @@ struct dgs_ctx_s {
 dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* cam, const dgs_render_opts* opts,
                                const dgs_image* out, bool write_frame);
 
-// Validates camera and options and builds the device frame record.
+// Validates camera, options and output and builds the frame record; *mode
+// receives the render mode.  c may be a host-only context (errors land in c->err).
 dgs_status dgs_internal_frame(dgs_ctx c, const dgs_camera* cam, const dgs_render_opts* opts, const dgs_image* out,
-                              dgs::FrameK* f);
+                              dgs::FrameK* f, int* mode);
+dgs_status dgs_internal_check_scene(dgs_ctx c, const dgs_scene* s, int mode);
+
+// Grows the workspace for a render of scene s at width x height with `keys`
+// key capacity (allocates and synchronises only when growing).
+dgs_status dgs_internal_prepare(dgs_ctx c, const dgs_scene* s, int mode, int width, int height, int64_t keys);

@@ -220,6 +220,17 @@ def orbit_cameras(n_frames=60, width=1920, height=1080, radius=3.0, elevation_de
     return cams
 
 
+def aerial_orbit_cameras(n_frames=60, width=1920, height=1080, radius=120.0, altitude=80.0, step_deg=6.0,
+                         fov_x_deg=60.0):
+    """Orbit above the large scene, looking at the origin."""
+    cams = []
+    for i in range(n_frames):
+        az = math.radians(step_deg * i)
+        eye = np.array([radius * math.sin(az), altitude, radius * math.cos(az)])
+        cams.append(pinhole(look_at(eye, (0, 0, 0)), width, height, fov_x_deg))
+    return cams
+
+
 def large_scene_cameras(seed=2, width=1280, height=720, n_near=20, n_far=20, extent=100.0):
     """Near (street-level) and far (aerial) views of the large scene."""
     rng = np.random.default_rng(seed + 1000)
