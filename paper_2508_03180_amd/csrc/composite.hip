@@ -40,7 +40,11 @@ struct Chunk {
 
 __device__ inline void load_chunk(const CompositeArgs& a, uint32_t pos, int nrec, int K, int lane, bool cells,
                                   Chunk& q) {
+    // every field is set on every path: a partly set struct would be kept in
+    // scratch memory instead of registers
     q.ok = lane < nrec;
+    q.r0 = q.r1 = q.r2 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    q.v = 0.0f;
     if (!q.ok) return;
     uint32_t g;
     if (cells) {
@@ -75,6 +79,18 @@ __device__ inline void strip_ballots(const Chunk& q, int tx0, int ty0, uint64_t*
     for (int j = 0; j < 4; j++) B[j] = __ballot((sm >> j) & 1u);
 }
 
+// The owned strips' ballots: all four, or strip s0 (wave-uniform) selected
+// without indexing a register array at run time (which would spill it).
+template <int NS>
+__device__ inline void pick_strips(const uint64_t* B4, int s0, uint64_t* B) {
+    if (NS == 4) {
+#pragma unroll
+        for (int j = 0; j < 4; j++) B[j] = B4[j];
+    } else {
+        B[0] = (s0 & 2) ? ((s0 & 1) ? B4[3] : B4[2]) : ((s0 & 1) ? B4[1] : B4[0]);
+    }
+}
+
 __device__ inline void store_chunk(GRec* lds, int lane, const Chunk& q) {
     if (!q.ok) return;
     float4* d = reinterpret_cast<float4*>(lds + lane);
@@ -105,6 +121,35 @@ __device__ inline RecView read_rec(const GRec* lds, int i) {
 }
 
 
+// The frame's values the compositors use, loaded once per wavefront from the
+// device frame record (scalar registers; the kernel argument is left as is).
+struct FrameView {
+    int TX, W, H;
+    float eps, th, amax, bg0, bg1, bg2;
+    float* color;
+    float* D;
+    float* T;
+    int32_t* last;
+};
+
+__device__ inline FrameView frame_view(const FrameK* fr) {
+    FrameView f;
+    f.TX = fr->k.TX;
+    f.W = fr->k.W;
+    f.H = fr->k.H;
+    f.eps = fr->o.no_et ? 0.0f : fr->o.eps;
+    f.th = fr->o.log2_alpha_min;
+    f.amax = fr->o.alpha_max;
+    f.bg0 = fr->o.bg[0];
+    f.bg1 = fr->o.bg[1];
+    f.bg2 = fr->o.bg[2];
+    f.color = fr->color;
+    f.D = fr->D;
+    f.T = fr->T;
+    f.last = fr->last;
+    return f;
+}
+
 // Work item: tile << 3 | mode; mode 0 = all four strips, mode 4 + j = strip j.
 
 // Statistics counters (STATS only): n_val, n_rendered (the termination ratio
@@ -115,15 +160,15 @@ struct Counters {
 };
 
 template <bool STATS, int NS>
-__device__ inline void duplex_tile(const CompositeArgs& a, int tile, int s0, int lane, GRec* lds, Counters& cn) {
-    const int tx0 = (tile % a.k.TX) * kTile, ty0 = (tile / a.k.TX) * kTile;
+__device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, int tile, int s0, int lane, GRec* lds,
+                                 Counters& cn) {
+    const int tx0 = (tile % f.TX) * kTile, ty0 = (tile / f.TX) * kTile;
     const int px = tx0 + (lane & 15), py0 = ty0 + 4 * s0 + (lane >> 4);
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
     const int K = a.K;
     const int cpc = 64 / K;  // cells per chunk
     const uint32_t kmask = K == 32 ? 0xffffffffu : ((1u << K) - 1u);
-    const float eps = a.o.no_et ? 0.0f : a.o.eps;
-    const float th = a.o.log2_alpha_min, amax = a.o.alpha_max;
+    const float eps = f.eps, th = f.th, amax = f.amax;
 
     float T[NS], N0[NS], N1[NS], N2[NS], D[NS];
     int32_t last[NS];
@@ -131,7 +176,7 @@ __device__ inline void duplex_tile(const CompositeArgs& a, int tile, int s0, int
 #pragma unroll
     for (int j = 0; j < NS; j++) {
         T[j] = 1.0f; N0[j] = N1[j] = N2[j] = D[j] = 0.0f; last[j] = 0;
-        act[j] = px < a.k.W && py0 + 4 * j < a.k.H;
+        act[j] = px < f.W && py0 + 4 * j < f.H;
     }
 
     Chunk q;
@@ -143,8 +188,7 @@ __device__ inline void duplex_tile(const CompositeArgs& a, int tile, int s0, int
         uint64_t B4[4];
         strip_ballots(q, tx0, ty0, B4);
         uint64_t B[NS];
-#pragma unroll
-        for (int j = 0; j < NS; j++) B[j] = B4[s0 + j];
+        pick_strips<NS>(B4, s0, B);
         const float cv = q.v;
         const uint32_t next = pos + nch;
         if (next < end) load_chunk(a, next, (int)min((uint32_t)cpc, end - next) * K, K, lane, true, q);
@@ -220,35 +264,35 @@ __device__ inline void duplex_tile(const CompositeArgs& a, int tile, int s0, int
         }
         pos = next;
     }
-    const size_t HW = (size_t)a.k.W * a.k.H;
+    const size_t HW = (size_t)f.W * f.H;
 #pragma unroll
     for (int j = 0; j < NS; j++) {
         const int py = py0 + 4 * j;
-        if (px >= a.k.W || py >= a.k.H) continue;
-        const size_t p = (size_t)py * a.k.W + px;
+        if (px >= f.W || py >= f.H) continue;
+        const size_t p = (size_t)py * f.W + px;
         if (D[j] > 0.0f) {
             const float inv = 1.0f / D[j];
-            a.color[p] = N0[j] * inv;
-            a.color[HW + p] = N1[j] * inv;
-            a.color[2 * HW + p] = N2[j] * inv;
+            f.color[p] = N0[j] * inv;
+            f.color[HW + p] = N1[j] * inv;
+            f.color[2 * HW + p] = N2[j] * inv;
         } else {
-            a.color[p] = a.o.bg[0];
-            a.color[HW + p] = a.o.bg[1];
-            a.color[2 * HW + p] = a.o.bg[2];
+            f.color[p] = f.bg0;
+            f.color[HW + p] = f.bg1;
+            f.color[2 * HW + p] = f.bg2;
         }
-        if (a.D) a.D[p] = D[j];
-        if (a.T) a.T[p] = T[j];
-        if (a.last) a.last[p] = last[j];
+        if (f.D) f.D[p] = D[j];
+        if (f.T) f.T[p] = T[j];
+        if (f.last) f.last[p] = last[j];
     }
 }
 
 template <bool STATS, int NS>
-__device__ inline void alpha_tile(const CompositeArgs& a, int tile, int s0, int lane, GRec* lds, Counters& cn) {
-    const int tx0 = (tile % a.k.TX) * kTile, ty0 = (tile / a.k.TX) * kTile;
+__device__ inline void alpha_tile(const CompositeArgs& a, const FrameView& f, int tile, int s0, int lane, GRec* lds,
+                                 Counters& cn) {
+    const int tx0 = (tile % f.TX) * kTile, ty0 = (tile / f.TX) * kTile;
     const int px = tx0 + (lane & 15), py0 = ty0 + 4 * s0 + (lane >> 4);
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
-    const float eps = a.o.no_et ? 0.0f : a.o.eps;
-    const float th = a.o.log2_alpha_min, amax = a.o.alpha_max;
+    const float eps = f.eps, th = f.th, amax = f.amax;
 
     float T[NS], C0[NS], C1[NS], C2[NS];
     int32_t last[NS];
@@ -256,7 +300,7 @@ __device__ inline void alpha_tile(const CompositeArgs& a, int tile, int s0, int 
 #pragma unroll
     for (int j = 0; j < NS; j++) {
         T[j] = 1.0f; C0[j] = C1[j] = C2[j] = 0.0f; last[j] = 0;
-        act[j] = px < a.k.W && py0 + 4 * j < a.k.H;
+        act[j] = px < f.W && py0 + 4 * j < f.H;
     }
     Chunk q;
     if (start < end) load_chunk(a, start, (int)min(64u, end - start), 1, lane, false, q);
@@ -267,11 +311,9 @@ __device__ inline void alpha_tile(const CompositeArgs& a, int tile, int s0, int 
         uint64_t B4[4];
         strip_ballots(q, tx0, ty0, B4);
         uint64_t B[NS], any = 0;
+        pick_strips<NS>(B4, s0, B);
 #pragma unroll
-        for (int j = 0; j < NS; j++) {
-            B[j] = B4[s0 + j];
-            any |= B[j];
-        }
+        for (int j = 0; j < NS; j++) any |= B[j];
         const uint32_t next = pos + n;
         if (next < end) load_chunk(a, next, (int)min(64u, end - next), 1, lane, false, q);
         int since_check = 0;
@@ -324,18 +366,18 @@ __device__ inline void alpha_tile(const CompositeArgs& a, int tile, int s0, int 
         }
         pos = next;
     }
-    const size_t HW = (size_t)a.k.W * a.k.H;
+    const size_t HW = (size_t)f.W * f.H;
 #pragma unroll
     for (int j = 0; j < NS; j++) {
         const int py = py0 + 4 * j;
-        if (px >= a.k.W || py >= a.k.H) continue;
-        const size_t p = (size_t)py * a.k.W + px;
-        a.color[p] = fmaf(T[j], a.o.bg[0], C0[j]);
-        a.color[HW + p] = fmaf(T[j], a.o.bg[1], C1[j]);
-        a.color[2 * HW + p] = fmaf(T[j], a.o.bg[2], C2[j]);
-        if (a.D) a.D[p] = 1.0f - T[j];
-        if (a.T) a.T[p] = T[j];
-        if (a.last) a.last[p] = last[j];
+        if (px >= f.W || py >= f.H) continue;
+        const size_t p = (size_t)py * f.W + px;
+        f.color[p] = fmaf(T[j], f.bg0, C0[j]);
+        f.color[HW + p] = fmaf(T[j], f.bg1, C1[j]);
+        f.color[2 * HW + p] = fmaf(T[j], f.bg2, C2[j]);
+        if (f.D) f.D[p] = 1.0f - T[j];
+        if (f.T) f.T[p] = T[j];
+        if (f.last) f.last[p] = last[j];
     }
 }
 
@@ -345,12 +387,7 @@ __device__ inline void alpha_tile(const CompositeArgs& a, int tile, int s0, int 
 template <bool DUPLEX, bool STATS>
 __global__ __launch_bounds__(256) void k_composite(CompositeArgs a) {
     __shared__ GRec s_rec[kWaves][64];
-    a.k = a.fr->k;
-    a.o = a.fr->o;
-    a.color = a.fr->color;
-    a.D = a.fr->D;
-    a.T = a.fr->T;
-    a.last = a.fr->last;
+    const FrameView f = frame_view(a.fr);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     GRec* lds = s_rec[wave];
     const uint32_t nitems = a.queue[1];
@@ -364,14 +401,14 @@ __global__ __launch_bounds__(256) void k_composite(CompositeArgs a) {
         const int tile = (int)(item >> 3), mode = (int)(item & 7u);
         if (DUPLEX) {
             if (mode == 0)
-                duplex_tile<STATS, 4>(a, tile, 0, lane, lds, cn);
+                duplex_tile<STATS, 4>(a, f, tile, 0, lane, lds, cn);
             else
-                duplex_tile<STATS, 1>(a, tile, mode - 4, lane, lds, cn);
+                duplex_tile<STATS, 1>(a, f, tile, mode - 4, lane, lds, cn);
         } else {
             if (mode == 0)
-                alpha_tile<STATS, 4>(a, tile, 0, lane, lds, cn);
+                alpha_tile<STATS, 4>(a, f, tile, 0, lane, lds, cn);
             else
-                alpha_tile<STATS, 1>(a, tile, mode - 4, lane, lds, cn);
+                alpha_tile<STATS, 1>(a, f, tile, mode - 4, lane, lds, cn);
         }
     }
     if (STATS) {
