@@ -357,7 +357,6 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     hipStream_t q = c->stream;
 
     StageMarks sm(c);
-    if (write_frame) launch_set_frame(q, FrameK{k, o, out->color, out->weight_sum, out->final_T, out->last}, c->frame);
     {
         // per-frame zeroing: digit histograms, scan/sort tickets and the
         // compositor queue (misc[1..12]), tile ranges, statistics counters
@@ -367,7 +366,8 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
         cl.add(c->ranges, 2 * (size_t)tiles);
         if (o.stats) cl.add((uint32_t*)c->counters, 8);
         cl.bump = c->misc + 13;
-        launch_clear(q, cl);
+        const FrameK f{k, o, out->color, out->weight_sum, out->final_T, out->last};
+        launch_clear(q, cl, write_frame ? &f : nullptr, c->frame);
     }
     sm.mark(0);
     if (mode == DGS_MODE_DUPLEX) {
@@ -385,12 +385,13 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     const uint64_t* prect = mode == DGS_MODE_DUPLEX ? c->p_rect : c->grect;
     launch_exclusive_scan(q, c->p_ntiles, c->p_offsets, P, c->misc + 0, c->scan_status, c->misc + 13, c->misc + 1,
                           c->dev_err);
-    launch_emit_keys(q, P, c->p_ntiles, c->p_offsets, prect, c->p_depth, k.TX, cap, c->keys0, c->vals0, c->dev_err);
+    const int bits = 32 + tile_bits(tiles);
+    launch_emit_keys(q, P, c->p_ntiles, c->p_offsets, prect, c->p_depth, k.TX, cap, c->keys0, c->vals0, c->hist,
+                     sort_passes(bits), c->dev_err);
     sm.mark(3);
     SortScratch ss{c->hist, c->sort_status, c->misc + 2};
-    const int bits = 32 + tile_bits(tiles);
     const bool in1 = launch_radix_sort(q, c->keys0, c->vals0, c->keys1, c->vals1, c->misc + 0, cap, bits, ss,
-                                       c->misc + 13, c->dev_err);
+                                       c->misc + 13, c->dev_err, true);
     const uint64_t* skeys = in1 ? c->keys1 : c->keys0;
     const uint32_t* svals = in1 ? c->vals1 : c->vals0;
     sm.mark(4);

@@ -38,13 +38,16 @@ struct ClearList {
         count++;
     }
 };
-void launch_clear(hipStream_t st, const ClearList& l);
+// With f set, also writes *f to fdst (the frame record) in the same launch.
+void launch_clear(hipStream_t st, const ClearList& l, const FrameK* f = nullptr, FrameK* fdst = nullptr);
 
 // One key per (primitive, touched tile): key = tile << 32 | depth bits,
 // value = primitive id, written at offsets[p] in row-major tile order.
+// Also accumulates the radix sort's digit histogram of the kept keys into
+// hist ([passes][256], zeroed beforehand).
 void launch_emit_keys(hipStream_t st, int P, const uint32_t* ntiles, const uint32_t* offsets,
                       const uint64_t* prect, const uint32_t* depth, int TX, uint32_t cap, uint64_t* keys,
-                      uint32_t* vals, int* err);
+                      uint32_t* vals, uint32_t* hist, int passes, int* err);
 
 // [start, end) per tile of the sorted keys; ranges (2 words per tile) must
 // be zero beforehand (tiles without keys keep [0, 0)).
@@ -54,8 +57,10 @@ void launch_tile_ranges(hipStream_t st, const uint64_t* keys, const uint32_t* n_
 // Onesweep LSD radix sort of (u64 key, u32 value) pairs on the low `bits`
 // bits.  The count is read on the device from *n_ptr (clamped to cap).
 // Returns true when the sorted data ends in (k1, v1), false for (k0, v0).
-// hist (8 x 256 words) and tickets (8 words) must be zero beforehand; pass p
-// tags its look-back words with epoch_tag(*epoch, 1 + p).
+// hist (8 x 256 words) and tickets (8 words) must be zero beforehand; with
+// hist_ready, hist already holds the digit counts of the keys (the key
+// emission counts them).  Pass p tags its look-back words with
+// epoch_tag(*epoch, 1 + p).
 struct SortScratch {
     uint32_t* hist;     // [8][256]
     uint64_t* status;   // sort_status_words(cap) look-back words
@@ -65,7 +70,7 @@ int sort_passes(int bits);
 size_t sort_status_words(int64_t cap);
 bool launch_radix_sort(hipStream_t st, uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1,
                        const uint32_t* n_ptr, uint32_t cap, int bits, const SortScratch& s,
-                       const uint32_t* epoch, int* err);
+                       const uint32_t* epoch, int* err, bool hist_ready = false);
 
 struct CompositeArgs {
     const uint32_t* ranges;

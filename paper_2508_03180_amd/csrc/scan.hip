@@ -3,6 +3,8 @@
 // offsets of every primitive's keys come from a scan over all primitives in
 // id order, so the emitted sequence (and the ties of the stable sort) are
 // deterministic.
+#include <string.h>
+
 #include "common.h"
 #include "launch.h"
 
@@ -11,6 +13,7 @@ namespace dgs {
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanPart = kScanThreads * kScanItems;
+constexpr int kEmitBlocks = 512;
 constexpr int kSpinLimit = 1 << 22;
 
 // status word: epoch << 34 | flag << 32 | value; flag 1 = partition total,
@@ -96,6 +99,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_excl(const uint32_t* __re
             if (base + i < n) out[base + i] = run;
             run += x[i];
         }
+        if (gridDim.x >= (unsigned)nparts) break;  // the other partitions went to other workgroups
         __syncthreads();  // s_part / s_wsum are reused by the next partition
     }
 }
@@ -126,55 +130,138 @@ void launch_exclusive_scan(hipStream_t st, const uint32_t* in, uint32_t* out, in
                        epoch, ticket, err);
 }
 
-__global__ void k_clear(ClearList l) {
+__global__ void k_clear(ClearList l, FrameK f, FrameK* fdst) {
     const size_t gid = blockIdx.x * (size_t)blockDim.x + threadIdx.x, stride = (size_t)gridDim.x * blockDim.x;
     for (int b = 0; b < l.count; b++)
         for (size_t i = gid; i < l.n[b]; i += stride) l.p[b][i] = 0u;
     if (l.bump && gid == 0) *l.bump += 1u;
+    if (fdst) {
+        static_assert(sizeof(FrameK) % 4 == 0, "frame record in words");
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(&f);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(fdst);
+        for (size_t i = gid; i < sizeof(FrameK) / 4; i += stride) dst[i] = src[i];
+    }
 }
 
-void launch_clear(hipStream_t st, const ClearList& l) {
+void launch_clear(hipStream_t st, const ClearList& l, const FrameK* f, FrameK* fdst) {
     size_t most = 0;
     for (int b = 0; b < l.count; b++) most = l.n[b] > most ? l.n[b] : most;
     if (most == 0) most = 1;
     unsigned grid = (unsigned)((most + 255) / 256);
     if (grid > 256) grid = 256;
-    hipLaunchKernelGGL(k_clear, dim3(grid), dim3(256), 0, st, l);
+    FrameK fv;
+    if (f) fv = *f;
+    else memset(&fv, 0, sizeof(fv));
+    hipLaunchKernelGGL(k_clear, dim3(grid), dim3(256), 0, st, l, fv, f ? fdst : nullptr);
 }
 
 // ---------------------------------------------------------------- keys
 
+// Key emission, fused with the digit histogram of the radix sort that
+// follows (hist[p][d]: keys whose byte p is d; `passes` bytes).  The depth
+// bytes are the same for every key of a primitive, so they are counted once
+// per primitive.  Along one row of a primitive's tile rectangle the tile ids
+// are consecutive: the low tile byte then covers a run of bins, counted with
+// a difference array (a +1 / -1 pair per run, prefix-summed at the end), and
+// each higher tile byte changes at most a few times, counted once per run.
+// Only keys below the capacity are counted (they are the ones sorted).
 __global__ __launch_bounds__(256) void k_emit_keys(int P, const uint32_t* __restrict__ ntiles,
                                                    const uint32_t* __restrict__ offsets,
                                                    const uint64_t* __restrict__ prect,
                                                    const uint32_t* __restrict__ depth, int TX, uint32_t cap,
                                                    uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                                                   int* err) {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
-    uint32_t nt = ntiles[p];
-    if (nt == 0) return;
-    uint32_t off = offsets[p];
-    if ((uint64_t)off + nt > cap) atomicOr(err, 1 << kErrCapacity);
-    uint64_t r = prect[p];
-    uint64_t d = depth[p];
-    int tx0 = rect_x0(r) / kTile, tx1 = rect_x1(r) / kTile;
-    int ty0 = rect_y0(r) / kTile, ty1 = rect_y1(r) / kTile;
-    uint32_t i = off;
-    for (int ty = ty0; ty <= ty1; ty++)
-        for (int tx = tx0; tx <= tx1; tx++, i++) {
-            if (i >= cap) return;
-            keys[i] = ((uint64_t)(ty * TX + tx) << 32) | d;
-            vals[i] = (uint32_t)p;
+                                                   uint32_t* __restrict__ hist, int passes, int* err) {
+    __shared__ uint32_t sh[8][256];
+    __shared__ int32_t s_diff[257];  // low tile byte: difference array over the bins
+    __shared__ uint32_t s_all;       // low tile byte: runs of 256 or more add to every bin
+    __shared__ uint32_t s_wsum[4];
+    for (int i = threadIdx.x; i < 8 * 256; i += blockDim.x) (&sh[0][0])[i] = 0u;
+    for (int i = threadIdx.x; i < 257; i += blockDim.x) s_diff[i] = 0;
+    if (threadIdx.x == 0) s_all = 0u;
+    __syncthreads();
+    // grid-stride over primitives: a capped grid, so each workgroup adds its
+    // histogram to the global one once
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
+        const uint32_t nt = ntiles[p];
+        if (nt) {
+            const uint32_t off = offsets[p];
+            if ((uint64_t)off + nt > cap) atomicOr(err, 1 << kErrCapacity);
+            const uint32_t nkept = off >= cap ? 0u : (cap - off < nt ? cap - off : nt);
+            const uint64_t r = prect[p];
+            const uint32_t d = depth[p];
+            const int dp = passes < 4 ? passes : 4;
+            if (nkept)
+                for (int b = 0; b < dp; b++) atomicAdd(&sh[b][(d >> (8 * b)) & 255u], nkept);
+            const int tx0 = rect_x0(r) / kTile, tx1 = rect_x1(r) / kTile;
+            const int ty0 = rect_y0(r) / kTile, ty1 = rect_y1(r) / kTile;
+            uint32_t i = off;
+            for (int ty = ty0; ty <= ty1 && i < cap; ty++) {
+                // one row of tiles: consecutive tile ids t0 .. t0 + kept - 1
+                const uint32_t t0 = (uint32_t)(ty * TX + tx0);
+                const uint32_t len = (uint32_t)(tx1 - tx0 + 1);
+                const uint32_t kept = cap - i < len ? cap - i : len;
+                for (uint32_t j = 0; j < kept; j++) {
+                    keys[i + j] = ((uint64_t)(t0 + j) << 32) | d;
+                    vals[i + j] = (uint32_t)p;
+                }
+                if (passes > 4 && kept) {
+                    if (kept >= 256u) atomicAdd(&s_all, kept >> 8);
+                    const uint32_t rem = kept & 255u, a = t0 & 255u;
+                    if (rem) {
+                        atomicAdd(&s_diff[a], 1);
+                        if (a + rem <= 256u) {
+                            atomicAdd(&s_diff[a + rem], -1);
+                        } else {
+                            atomicAdd(&s_diff[256], -1);
+                            atomicAdd(&s_diff[0], 1);
+                            atomicAdd(&s_diff[a + rem - 256u], -1);
+                        }
+                    }
+                }
+                // higher tile bytes change rarely along a row: one count per run
+                for (int b = 5; b < passes; b++) {
+                    const int sh8 = 8 * (b - 4);
+                    for (uint32_t t = t0, te = t0 + kept; t < te;) {
+                        const uint32_t run_end = ((t >> sh8) + 1u) << sh8;
+                        const uint32_t stop = run_end < te ? run_end : te;
+                        atomicAdd(&sh[b][(t >> sh8) & 255u], stop - t);
+                        t = stop;
+                    }
+                }
+                i += kept;
+            }
+        }
+    }
+    __syncthreads();
+    if (passes > 4) {
+        // low tile byte: inclusive prefix sum of the difference array
+        const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+        int32_t x = s_diff[tid];
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t u = __shfl_up(x, o, 64);
+            if (lane >= o) x += u;
+        }
+        if (lane == 63) s_wsum[wave] = (uint32_t)x;
+        __syncthreads();
+        for (int w = 0; w < wave; w++) x += (int32_t)s_wsum[w];
+        sh[4][tid] = (uint32_t)x + s_all;
+        __syncthreads();
+    }
+    for (int b = 0; b < passes; b++)
+        for (int i = threadIdx.x; i < 256; i += blockDim.x) {
+            const uint32_t c = sh[b][i];
+            if (c) atomicAdd(&hist[b * 256 + i], c);
         }
 }
 
 void launch_emit_keys(hipStream_t st, int P, const uint32_t* ntiles, const uint32_t* offsets,
                       const uint64_t* prect, const uint32_t* depth, int TX, uint32_t cap, uint64_t* keys,
-                      uint32_t* vals, int* err) {
+                      uint32_t* vals, uint32_t* hist, int passes, int* err) {
     if (P <= 0) return;
-    hipLaunchKernelGGL(k_emit_keys, dim3((P + 255) / 256), dim3(256), 0, st, P, ntiles, offsets, prect, depth, TX,
-                       cap, keys, vals, err);
+    const int blocks = (P + 255) / 256 < kEmitBlocks ? (P + 255) / 256 : kEmitBlocks;
+    hipLaunchKernelGGL(k_emit_keys, dim3(blocks), dim3(256), 0, st, P, ntiles, offsets, prect, depth, TX,
+                       cap, keys, vals, hist, passes, err);
 }
 
 __global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t* __restrict__ keys,

@@ -19,8 +19,10 @@ constexpr int kSortThreads = 256;
 constexpr int kSortWaves = kSortThreads / 64;
 constexpr int kSortItems = 16;
 constexpr int kSortPart = kSortThreads * kSortItems;  // 4096 keys per partition
+static_assert(kSortThreads == 256, "one thread per digit");
 constexpr int kHistBlocks = 128;
 constexpr int kSortSpinLimit = 1 << 22;
+constexpr int kLookWindow = 4;
 
 int sort_passes(int bits) { return (bits + 7) / 8; }
 
@@ -49,27 +51,6 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint64_t* __restrict__
     }
 }
 
-// In place: per pass, digit counts -> exclusive digit offsets.
-__global__ __launch_bounds__(256) void k_radix_hist_scan(uint32_t* hist, int passes) {
-    __shared__ uint32_t s_w[kSortWaves];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int p = 0; p < passes; p++) {
-        const uint32_t v = hist[p * 256 + tid];
-        uint32_t x = v;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint32_t u = __shfl_up(x, d, 64);
-            if (lane >= d) x += u;
-        }
-        if (lane == 63) s_w[wave] = x;
-        __syncthreads();
-        uint32_t pre = 0;
-        for (int w = 0; w < wave; w++) pre += s_w[w];
-        hist[p * 256 + tid] = pre + x - v;
-        __syncthreads();
-    }
-}
-
 // Number of set bits of `mask` at lanes below this one.
 __device__ inline uint32_t lanes_below(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -85,17 +66,19 @@ __device__ inline void st_st64(uint64_t* p, uint64_t v) {
 }
 
 // Exclusive prefix of `col` over partitions [0, part) by decoupled look-back
-// with up to four status words in flight.  Returns false on a timeout.
+// with up to kLookWindow status words in flight: every partition is resident
+// at once, so the walk mostly crosses published totals, and a wide window
+// reaches an inclusive prefix in few round trips.  Returns false on a timeout.
 __device__ inline bool look_back(const uint64_t* status, size_t stride, int part, uint32_t epoch, uint32_t* excl) {
     uint32_t sum = 0;
     int j = part - 1, spins = 0;
     while (j >= 0) {
-        uint64_t s[4];
+        uint64_t s[kLookWindow];
 #pragma unroll
-        for (int i = 0; i < 4; i++) s[i] = j - i >= 0 ? ld_st64(status + (size_t)(j - i) * stride) : 0;
+        for (int i = 0; i < kLookWindow; i++) s[i] = j - i >= 0 ? ld_st64(status + (size_t)(j - i) * stride) : 0;
         int i = 0;
         bool done = false;
-        for (; i < 4; i++) {
+        for (; i < kLookWindow; i++) {
             if (j - i < 0) { done = true; break; }
             if ((uint32_t)(s[i] >> 34) != epoch || ((s[i] >> 32) & 3u) == 0) break;  // not published yet
             sum += (uint32_t)s[i];
@@ -116,7 +99,7 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
                                                            const uint32_t* __restrict__ vin,
                                                            uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                            const uint32_t* __restrict__ n_ptr, uint32_t cap,
-                                                           int shift, const uint32_t* __restrict__ goff,
+                                                           int shift, const uint32_t* __restrict__ dcount,
                                                            uint64_t* status, const uint32_t* ep, uint32_t pass_tag,
                                                            uint32_t* ticket, int* err) {
     __shared__ uint64_t s_key[kSortPart];
@@ -126,11 +109,27 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
     __shared__ uint32_t s_gbase[256];             // global start of each digit minus its local start
     __shared__ uint32_t s_wsum[kSortWaves];
     __shared__ uint32_t s_part;
+    __shared__ uint32_t s_goff[256];  // global start of each digit: exclusive scan of the digit counts
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t epoch = epoch_tag(*ep, pass_tag);
     uint32_t n = *n_ptr;
     if (n > cap) n = cap;
     const uint32_t nparts = (n + kSortPart - 1) / kSortPart;
+    {
+        const uint32_t c = dcount[tid];
+        uint32_t x = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t u = __shfl_up(x, o, 64);
+            if (lane >= o) x += u;
+        }
+        if (lane == 63) s_wsum[wave] = x;
+        __syncthreads();
+        uint32_t pre = 0;
+        for (int w = 0; w < wave; w++) pre += s_wsum[w];
+        s_goff[tid] = pre + x - c;
+        __syncthreads();  // s_wsum is reused below
+    }
     for (;;) {
         if (tid == 0) s_part = atomicAdd(ticket, 1u);
         for (int d = tid; d < kSortWaves * 256; d += kSortThreads) (&s_cnt[0][0])[d] = 0;
@@ -199,7 +198,7 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
         uint32_t lstart = x - tot;
         for (int w = 0; w < wave; w++) lstart += s_wsum[w];
         s_lstart[d] = lstart;
-        s_gbase[d] = goff[d] + excl - lstart;
+        s_gbase[d] = s_goff[d] + excl - lstart;
         __syncthreads();
         // partition-local digit-grouped order in LDS
 #pragma unroll
@@ -221,17 +220,19 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
                 vout[pos] = s_val[i];
             }
         }
+        if (gridDim.x >= nparts) break;  // the other partitions went to other workgroups
         __syncthreads();  // LDS is reused by the next partition
     }
 }
 
 bool launch_radix_sort(hipStream_t st, uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1,
                        const uint32_t* n_ptr, uint32_t cap, int bits, const SortScratch& s,
-                       const uint32_t* epoch, int* err) {
+                       const uint32_t* epoch, int* err, bool hist_ready) {
     const int passes = sort_passes(bits);
     if (passes <= 0 || cap == 0) return false;
-    hipLaunchKernelGGL(k_radix_hist, dim3(kHistBlocks), dim3(kSortThreads), 0, st, k0, n_ptr, cap, passes, s.hist);
-    hipLaunchKernelGGL(k_radix_hist_scan, dim3(1), dim3(256), 0, st, s.hist, passes);
+    if (!hist_ready)
+        hipLaunchKernelGGL(k_radix_hist, dim3(kHistBlocks), dim3(kSortThreads), 0, st, k0, n_ptr, cap, passes,
+                           s.hist);
     const size_t parts = max_parts(cap);
     const unsigned grid = (unsigned)(parts < 1024 ? parts : 1024);
     uint64_t *ki = k0, *ko = k1;

@@ -122,6 +122,20 @@ def test_discrete_layer_bit_exact_1080p(R, c1, frame):
     assert n > 100_000
 
 
+@pytest.mark.parametrize("size,cell_mult", [((8192, 128), 30.0), ((5000, 4000), 3.0)])
+def test_discrete_layer_bit_exact_wide_images(R, size, cell_mult):
+    """Tile rows longer than 256 tiles (8192 px wide, cells thousands of
+    pixels across) and tile ids above 2^16 (313 x 250 tiles, a 7-pass sort):
+    the key emission's run-length digit counting must give the sort the
+    exact histogram."""
+    s = scenes.make_tiny_scene(0)
+    s["cell_scale"] = (s["cell_scale"] * cell_mult).astype(np.float32)
+    base = scenes.tiny_camera()
+    cam = scenes.pinhole(base["viewmat"], size[0], size[1])
+    n = _check_discrete(R, s, cam)
+    assert n > 1_000_000
+
+
 def test_gaussian_keys_bit_exact_alpha_mode(R):
     s = scenes.make_tiny_scene(0)
     cam = scenes.tiny_camera()
