@@ -53,6 +53,8 @@ def parse():
     p.add_argument("--no-alpha", action="store_true")
     p.add_argument("--cpu-frames", type=int, default=4)
     p.add_argument("--bwd-steps", type=int, default=10)
+    p.add_argument("--no-large", action="store_true")
+    p.add_argument("--large-cams", type=int, default=20, help="cameras of each kind (near, far) per resolution")
     p.add_argument("--no-serve", action="store_true")
     p.add_argument("--serve-seconds", type=float, default=4.0, help="length of each Poisson stream")
     p.add_argument("--serve-rates", default="30,120,480", help="request rates (req/s)")
@@ -126,7 +128,59 @@ def differentiation(r, scene, cam, steps):
     capi.check(capi.dgs_sync(r.ctx), r.ctx)
     return {"loss": "0.8 L1 + 0.2 (1 - SSIM 11x11) vs perturbed-scene target", "width": 1920, "height": 1080,
             "fwd_loss_bwd_ms": round(dt * 1e3, 3), "backward_ms": round(bt * 1e3, 3),
-            "final_loss": round(float(loss), 5)}
+            "final_loss": round(float(loss.detach()), 5)}
+
+
+LARGE_SIZES = [(1280, 720), (1920, 1080), (3840, 2160)]
+
+
+def large_scene(a):
+    """6M-Gaussian aerial-scale scene (600k cells x 10) at 720p, 1080p and 4K
+    over near and far cameras: sort-key reduction of per-cell keys against
+    per-Gaussian keys, the early-termination rate 1 - sum N^rendered / sum
+    N^val, and frames/s of both modes."""
+    import numpy as np
+    import torch
+
+    from paper_2508_03180_amd import scenes
+    from paper_2508_03180_amd.renderer import DeviceScene, Renderer
+
+    scene = scenes.make_large_scene(2)
+    ds = DeviceScene.from_numpy(scene, "cuda:0")
+    del scene
+    r = Renderer(0)
+    out = {"gaussians": ds.M, "cells": ds.N, "cameras_per_kind": a.large_cams}
+    for (w, h) in LARGE_SIZES:
+        allc = scenes.large_scene_cameras(2, w, h, n_near=20, n_far=20)
+        cams = allc[:a.large_cams] + allc[20:20 + a.large_cams]
+        img = r.alloc_image(cams[0])
+        res = {}
+        for mode in ("duplex", "alpha"):
+            keys = nval = nrend = 0
+            for c in cams:  # sizes the workspace and counts
+                r.render(ds, c, out=img, mode=mode, stats=True)
+                st = r.stats()
+                keys += st["num_keys"]
+                nval += st["n_val"]
+                nrend += st["n_rendered"]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for c in cams:
+                r.render(ds, c, out=img, mode=mode, check=False)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            capi_check = r.sync()
+            assert capi_check == 0, capi_check
+            res[mode] = {"fps": round(len(cams) / dt, 2), "keys_mean": round(keys / len(cams), 1),
+                         "termination_ratio": round(1 - nrend / max(nval, 1), 4)}
+        res["key_reduction"] = round(1 - res["duplex"]["keys_mean"] / res["alpha"]["keys_mean"], 4)
+        res["speedup"] = round(res["duplex"]["fps"] / res["alpha"]["fps"], 3)
+        out[f"{w}x{h}"] = res
+        del img
+    r.close()
+    del ds
+    torch.cuda.empty_cache()
+    return out
 
 
 SERVE_SIZES = [(640, 480), (1280, 720), (1920, 1080), (3840, 2160)]
@@ -294,6 +348,7 @@ def main():
     # against a target rendered from a perturbed copy of the scene
     bwd = differentiation(r, scene, cams[0], a.bwd_steps)
 
+    large = None if a.no_large else large_scene(a)
     serve = None if a.no_serve else serving(a)
 
     cpu = None
@@ -327,6 +382,7 @@ def main():
         "termination_ratio": round(1 - cnt["n_rendered"] / max(cnt["n_val"], 1), 4),
         "roofline": roof,
         "differentiation": bwd,
+        "large_scene": large,
         "serving": serve,
         "cpu_baseline": cpu,
     }
