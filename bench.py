@@ -43,6 +43,27 @@ FLOP_ALPHA_HIT = 9
 # writes the 48-byte record and the 8-byte packed rectangle
 BYTES_PROJECT_SH3 = 12 + 12 + 16 + 4 + 192 + 48 + 8
 
+# HBM traffic of one Duplex compositor launch on this workload, from two
+# rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) scaled by a 1 GiB copy
+# kernel's reading (profiles/composite_traffic_1080p_1M_pmc.md): 205.86 MB
+# read + 51.51 MB written.  Valid for the compositor source it was taken
+# on; reported as null once that source changes.
+COMPOSITE_TRAFFIC_BYTES = 205.860e6 + 51.514e6
+COMPOSITE_TRAFFIC_SOURCES = {
+    "paper_2508_03180_amd/csrc/composite.hip": "514c8616147673d3cd893d5a75da0aa9f924c485f22d815e81ec0e4826605004",
+    "paper_2508_03180_amd/csrc/common.h": "2b58fbb83844827086244e12472401091ee3b1b539bf54fdaabc3416086f4546",
+}
+
+
+def composite_traffic():
+    """Measured bytes per compositor launch, or None if the kernel changed."""
+    import hashlib
+    for rel, digest in COMPOSITE_TRAFFIC_SOURCES.items():
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
+    return COMPOSITE_TRAFFIC_BYTES
+
 
 def parse():
     p = argparse.ArgumentParser()
@@ -339,7 +360,7 @@ def main():
              + FLOP_DUPLEX_CELL * cnt["n_cell_hits"])
     achieved = flops / (comp_ms * 1e-3) / 1e12
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+            "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": composite_traffic(),
             "kernel": "k_composite<true, false>", "kernel_ms": round(comp_ms, 4),
             "algorithmic_gflop_per_launch": round(flops / 1e9, 4)}
     proj_gbs = cnt["projected"] * BYTES_PROJECT_SH3 / (st_dup["gauss_project"] * 1e-3) / 1e9
