@@ -129,11 +129,17 @@ def build_lists(visible, depth_bits, rect, width, height):
 
 
 DEFAULTS = dict(eps=1e-4, alpha_min=1.0 / 255.0, alpha_max=0.99, delta=0.3, kappa=1.0,
-                bg=(0.0, 0.0, 0.0), v_one=False, no_et=False, band_alpha=1e-4, band_T=1e-4)
+                bg=(0.0, 0.0, 0.0), v_one=False, no_et=False, band_alpha=1e-4, band_T=1e-4, tau=0.0)
+
+MODES = {"duplex": 0, "alpha": 1, "lcwsr": 2}
 
 
 def render(scene, cam, mode="duplex", pixels=None, alt_cap=None, **opts):
     """Render the whole image (pixels=None) or the listed (x, y) pixels.
+
+    mode: "duplex" (the hybrid renderer), "alpha" (per-Gaussian sorted
+    alpha blending) or "lcwsr" (the Duplex pipeline with LC-WSR cell weights
+    v max(0, 1 - d / tau), tau > 0 given as an option).
 
     Returns a dict with color [P,3], D, T, last, nrend, nval, status
     (0 exact, 1 marginal, 2 unverifiable), n_alt, alt_slot and alt
@@ -152,7 +158,10 @@ def render(scene, cam, mode="duplex", pixels=None, alt_cap=None, **opts):
         pix = np.ascontiguousarray(pixels, np.int32).reshape(-1, 2)
         P = pix.shape[0]
     ro = np.array([o["eps"], o["alpha_min"], o["alpha_max"], o["delta"], o["kappa"], o["bg"][0], o["bg"][1],
-                   o["bg"][2], float(o["v_one"]), float(o["no_et"]), o["band_alpha"], o["band_T"]], np.float64)
+                   o["bg"][2], float(o["v_one"]), float(o["no_et"]), o["band_alpha"], o["band_T"], o["tau"]],
+                  np.float64)
+    if mode == "lcwsr" and not o["tau"] > 0:
+        raise ValueError("the lcwsr mode needs tau > 0")
     color = np.zeros((P, 3), np.float64)
     D = np.zeros(P, np.float64)
     T = np.zeros(P, np.float64)
@@ -169,7 +178,7 @@ def render(scene, cam, mode="duplex", pixels=None, alt_cap=None, **opts):
     nkeys = np.zeros(1, np.int32)
     sh = _f32(scene["sh"])
     vsh = _f32(scene["cell_v_sh"])
-    cnt = L.orc_render(C.c_int(0 if mode == "duplex" else 1), C.c_int(N), C.c_int(K),
+    cnt = L.orc_render(C.c_int(MODES[mode]), C.c_int(N), C.c_int(K),
                        _p(_f32(scene["cell_pos"])), _p(_f32(scene["cell_scale"])), _p(_f32(scene["cell_rot"])),
                        _p(vsh), C.c_int(int(scene["v_sh_degree"])), _p(_f32(scene["means"])),
                        _p(_f32(scene["scales"])), _p(_f32(scene["rots"])), _p(_f32(scene["opacities"])),

@@ -447,6 +447,46 @@ static void walk_duplex(const ctx_t *c, int px, int py, dec_t *st, int no_et, pi
     out->D = D; out->T = T; out->last = last; out->nrend = nrend;
 }
 
+/* "w/o T^cell" ablation (Sec. VII, cell-level transmittance): the pipeline of
+ * the Duplex walk with the cell transmittance replaced by the LC-WSR weight
+ * (eqs. WSR and LC-WSR, background weight 0): c->v[n] already holds
+ * w_n = v_n max(0, 1 - d_n / tau), and the colour is
+ *   C = sum_n w_n sum_i alpha_i c_i / sum_n w_n sum_i alpha_i.
+ * Nothing decays along the list, so nothing terminates. */
+static void walk_lcwsr(const ctx_t *c, int px, int py, dec_t *st, pix_t *out) {
+    int tile = (py / TILE) * c->k->TX + (px / TILE);
+    int s = c->ranges[2 * tile], e = c->ranges[2 * tile + 1];
+    double qx = px + 0.5, qy = py + 0.5;
+    double N[3] = {0, 0, 0}, D = 0.0;
+    int32_t last = 0, nrend = 0;
+    for (int i = s; i < e; i++) {
+        int n = c->ids[i];
+        double w = c->v[n];
+        int cnt = 0;
+        for (int kk = 0; kk < c->K; kk++) {
+            int g = n * c->K + kk;
+            if (!c->gvis[g] || !in_rect(c->grect + 4 * g, px, py)) continue;
+            const g64_t *G = c->G + g;
+            double dx = qx - G->u[0], dy = qy - G->u[1];
+            double pw = -0.5 * (G->con[0] * dx * dx + 2.0 * G->con[1] * dx * dy + G->con[2] * dy * dy);
+            double alpha = G->op * exp(pw);
+            if (alpha > c->o.amax) alpha = c->o.amax;
+            if (!decide_ge(st, alpha, c->o.amin, c->o.band_a)) continue;
+            for (int ch = 0; ch < 3; ch++) N[ch] += w * alpha * G->col[ch];
+            D += w * alpha;
+            cnt++;
+        }
+        if (cnt) { last = i - s + 1; nrend += cnt; }
+    }
+    for (int ch = 0; ch < 3; ch++) out->C[ch] = D > 0 ? N[ch] / D : c->o.bg[ch];
+    out->D = D; out->T = 1.0; out->last = last; out->nrend = nrend;
+}
+
+/* camera-space depth of a cell centre in binary64 */
+static double cell_depth64(const cam_t *k, int n, const float *pos) {
+    return k->Rd[6] * pos[3 * n] + k->Rd[7] * pos[3 * n + 1] + k->Rd[8] * pos[3 * n + 2] + k->td[2];
+}
+
 /* Per-Gaussian sorted alpha blending over the tile list of pixel (px, py). */
 static void walk_alpha(const ctx_t *c, int px, int py, dec_t *st, int no_et, pix_t *out) {
     int tile = (py / TILE) * c->k->TX + (px / TILE);
@@ -475,9 +515,10 @@ static void walk_alpha(const ctx_t *c, int px, int py, dec_t *st, int no_et, pix
 /*
  * Render the requested pixels (pix[2*i] = x, pix[2*i+1] = y; pix == NULL means
  * the whole image in row-major order).
- *   mode 0: Duplex hybrid renderer; mode 1: per-Gaussian alpha blending.
+ *   mode 0: Duplex hybrid renderer; mode 1: per-Gaussian alpha blending;
+ *   mode 2: the Duplex pipeline with LC-WSR cell weights ("w/o T^cell").
  *   ropt[] = eps, alpha_min, alpha_max, delta, kappa, bg0, bg1, bg2,
- *            v_one, no_et, band_alpha, band_T
+ *            v_one, no_et, band_alpha, band_T, tau (mode 2)
  * Outputs per pixel: color[3], D, T, last, nrend, nval, status
  * (0 exact, 1 marginal with n_alt admissible alternatives, 2 unverifiable).
  * Alternatives (C[3], D, T per entry, up to 8 per pixel) go to alt[] in
@@ -514,7 +555,7 @@ int64_t orc_render(int mode, int N, int K, const float *cell_pos, const float *c
     int64_t cnt;
     double *vv = NULL;
     uint8_t *cvis = NULL;
-    if (mode == 0) {
+    if (mode == 0 || mode == 2) {
         cvis = malloc(N ? N : 1);
         uint32_t *cdep = malloc(sizeof(uint32_t) * (N ? N : 1));
         int32_t *crect = malloc(sizeof(int32_t) * 4 * (N ? N : 1));
@@ -526,6 +567,13 @@ int64_t orc_render(int mode, int N, int K, const float *cell_pos, const float *c
         orc_build_lists(N, cvis, cdep, crect, k.W, k.H, ids, NULL, ranges);
         vv = malloc(sizeof(double) * (N ? N : 1));
         for (int n = 0; n < N; n++) vv[n] = v_one ? 1.0 : cell_v64(&k, n, cell_pos, cell_vsh, vdeg);
+        if (mode == 2) {
+            double tau = ropt[12];
+            for (int n = 0; n < N; n++) {
+                double lin = 1.0 - cell_depth64(&k, n, cell_pos) / tau;
+                vv[n] *= lin > 0 ? lin : 0.0;
+            }
+        }
         free(cdep); free(crect); free(ctr); free(cnt_t);
     } else {
         cnt = orc_build_lists(M, gvis, gdep, grect, k.W, k.H, NULL, NULL, ranges);
@@ -536,7 +584,7 @@ int64_t orc_render(int mode, int N, int K, const float *cell_pos, const float *c
     g64_t *G = calloc(M ? M : 1, sizeof(g64_t));
 #pragma omp parallel for schedule(static)
     for (int g = 0; g < M; g++)
-        if (gvis[g] && (mode != 0 || cvis[g / K])) gauss64(&k, g, means, scales, rots, opac, sh, sh_deg, delta, &G[g]);
+        if (gvis[g] && (mode == 1 || cvis[g / K])) gauss64(&k, g, means, scales, rots, opac, sh, sh_deg, delta, &G[g]);
     c.G = G; c.gvis = gvis; c.grect = grect; c.v = vv; c.ids = ids; c.ranges = ranges;
 
     int total = pix ? npix : k.W * k.H;
@@ -546,10 +594,12 @@ int64_t orc_render(int mode, int N, int K, const float *cell_pos, const float *c
         pix_t r, rv;
         dec_t st = {0, 0};
         if (mode == 0) walk_duplex(&c, px, py, &st, c.o.no_et, &r);
+        else if (mode == 2) walk_lcwsr(&c, px, py, &st, &r);
         else walk_alpha(&c, px, py, &st, c.o.no_et, &r);
         /* N^val: gated members of every listed cell, without termination */
         dec_t sv = {0, 0};
         if (mode == 0) walk_duplex(&c, px, py, &sv, 1, &rv);
+        else if (mode == 2) walk_lcwsr(&c, px, py, &sv, &rv);
         else walk_alpha(&c, px, py, &sv, 1, &rv);
         for (int ch = 0; ch < 3; ch++) color[3 * i + ch] = r.C[ch];
         Dout[i] = r.D; Tout[i] = r.T; last[i] = r.last; nrend[i] = r.nrend; nval[i] = rv.nrend;
@@ -568,6 +618,7 @@ int64_t orc_render(int mode, int N, int K, const float *cell_pos, const float *c
             dec_t s2 = {0, f};
             pix_t a;
             if (mode == 0) walk_duplex(&c, px, py, &s2, c.o.no_et, &a);
+            else if (mode == 2) walk_lcwsr(&c, px, py, &s2, &a);
             else walk_alpha(&c, px, py, &s2, c.o.no_et, &a);
             double *o = alt + ((int64_t)slot * MAX_ALT + na) * 5;
             o[0] = a.C[0]; o[1] = a.C[1]; o[2] = a.C[2]; o[3] = a.D; o[4] = a.T;

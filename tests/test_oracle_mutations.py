@@ -47,6 +47,15 @@ MUTATIONS = {
                                    "        if (!no_et && T * P < c->o.eps) break;\n        for (int ch = 0; ch < 3; ch++) N[ch] += v * T * A[ch];")],
     "no_cell_pad": [("float hx = kappa * sqrtf(cov[0]) + pad;", "float hx = kappa * sqrtf(cov[0]);")],
     "empty_pixel_not_bg": [("out->C[ch] = D > 0 ? N[ch] / D : c->o.bg[ch];", "out->C[ch] = D > 0 ? N[ch] / D : 0.0;")],
+    # the LC-WSR cell weights of the "w/o T^cell" mode
+    "lcwsr_no_depth_clamp": [("vv[n] *= lin > 0 ? lin : 0.0;", "vv[n] *= lin;")],
+    "lcwsr_weight_grows_with_depth": [("double lin = 1.0 - cell_depth64(&k, n, cell_pos) / tau;",
+                                       "double lin = cell_depth64(&k, n, cell_pos) / tau;")],
+    "lcwsr_without_v": [("vv[n] *= lin > 0 ? lin : 0.0;", "vv[n] = lin > 0 ? lin : 0.0;")],
+    "lcwsr_terminates": [("        int n = c->ids[i];\n        double w = c->v[n];",
+                          "        if (D > 1.0) break;\n        int n = c->ids[i];\n        double w = c->v[n];")],
+    "lcwsr_depth_along_x": [("return k->Rd[6] * pos[3 * n] + k->Rd[7] * pos[3 * n + 1] + k->Rd[8] * pos[3 * n + 2] + k->td[2];",
+                             "return k->Rd[0] * pos[3 * n] + k->Rd[1] * pos[3 * n + 1] + k->Rd[2] * pos[3 * n + 2] + k->td[0];")],
 }
 
 

@@ -268,6 +268,91 @@ def test_hand_worked_two_cell_scene():
         assert r["last"][0] == 2
 
 
+def test_lcwsr_hand_worked_two_cell_scene():
+    """The "w/o T^cell" weights (eqs. WSR, LC-WSR per cell, no background
+    weight): hand-worked rationals in tests/golden, including a cell beyond
+    tau (weight clamped to 0) and both cells beyond it (background)."""
+    g = json.load(open(os.path.join(GOLDEN, "two_cell_hand.json")))
+    cam = dict(g["camera"], viewmat=np.array(g["camera"]["viewmat"], np.float32))
+    cells = [dict(pos=c["pos"], members=[dict(sigma=m["sigma"], rgb=m["rgb"]) for m in c["members"]])
+             for c in g["cells"]]
+    for case in g["lcwsr_cases"]:
+        v = case["v"]
+        sc = manual_scene(cells, K=2, v_logit=0.0 if v == 0.5 else 30.0)
+        r = oracle.render(sc, cam, mode="lcwsr", pixels=[g["pixel"]], v_one=(v == 1.0), tau=case["tau"])
+        np.testing.assert_allclose(r["color"][0], [float(Fraction(x)) for x in case["C"]], atol=1e-12)
+        np.testing.assert_allclose(r["D"][0], float(Fraction(case["D"])), atol=1e-12)
+        assert r["T"][0] == 1.0
+    with pytest.raises(ValueError):
+        oracle.render(manual_scene(cells, K=2), cam, mode="lcwsr", pixels=[g["pixel"]])
+
+
+def test_lcwsr_one_cell_equals_duplex():
+    """With one cell in front of tau both weightings reduce to the cell's
+    plain weighted sum A / B, along two different code paths."""
+    s = scenes.make_tiny_scene(0)
+    one = scenes.subset_scene(s, [7])
+    cam = scenes.tiny_camera()
+    a = oracle.render(one, cam)
+    b = oracle.render(one, cam, mode="lcwsr", tau=50.0)
+    hit = a["D"] > 0
+    assert hit.sum() > 20
+    np.testing.assert_allclose(b["color"][hit], a["color"][hit], atol=1e-12)
+    assert (b["D"][hit] > 0).all() and (b["D"][~hit] == 0).all()
+
+
+def test_lcwsr_brute_force_and_no_termination():
+    """At sampled pixels of an opaque scene, the lcwsr colour equals the
+    order-free sum over every cell whose tile rectangle holds the pixel
+    (brute force over all cells, no tile lists), and every valid member is
+    rendered (nothing terminates), unlike the Duplex renderer."""
+    s = scenes.make_tiny_scene(3, n_cells=1500, K=6)
+    s["opacities"] = np.full_like(s["opacities"], 0.99)
+    s["scales"] = (s["scales"] * 3.0).astype(np.float32)
+    cam = scenes.tiny_camera(64, 64)
+    tau = 4.5
+    rng = np.random.default_rng(0)
+    pix = np.stack([rng.integers(0, 64, 200), rng.integers(0, 64, 200)], 1).astype(np.int32)
+    r = oracle.render(s, cam, mode="lcwsr", pixels=pix, tau=tau, v_one=True)
+    d = oracle.render(s, cam, pixels=pix, v_one=True)
+    assert (r["nrend"] == r["nval"]).all()
+    assert (d["nrend"] < d["nval"]).any()  # the Duplex walk does terminate here
+    cd = oracle.cells_discrete(s, cam)
+    gd = oracle.gauss_discrete(s, cam)
+    K, N = s["K"], len(s["cell_pos"])
+    cont = oracle.gauss_continuous(s, cam, np.arange(N * K, dtype=np.int32))
+    V = np.asarray(cam["viewmat"], np.float64)
+    depth = s["cell_pos"].astype(np.float64) @ V[2, :3] + V[2, 3]
+    w = np.maximum(0.0, 1.0 - depth / tau)  # v = 1
+    checked = 0
+    for i, (px, py) in enumerate(pix):
+        if r["status"][i] != 0:
+            continue
+        tx, ty = px // 16, py // 16
+        tr = cd["trect"]
+        cells = np.nonzero(cd["visible"].astype(bool) & (tr[:, 0] <= tx) & (tr[:, 1] >= tx) & (tr[:, 2] <= ty)
+                           & (tr[:, 3] >= ty))[0]
+        num, den = np.zeros(3), 0.0
+        for n in cells:
+            for k in range(K):
+                g = n * K + k
+                x0, x1, y0, y1 = gd["rect"][g]
+                if not gd["visible"][g] or not (x0 <= px <= x1 and y0 <= py <= y1):
+                    continue
+                dx, dy = px + 0.5 - cont[g, 0], py + 0.5 - cont[g, 1]
+                a, b, c = cont[g, 8:11]
+                alpha = min(0.99, float(s["opacities"][g]) * math.exp(-0.5 * (a * dx * dx + 2 * b * dx * dy + c * dy * dy)))
+                if alpha < 1 / 255:
+                    continue
+                num += w[n] * alpha * cont[g, 5:8]
+                den += w[n] * alpha
+        want = num / den if den > 0 else np.zeros(3)
+        np.testing.assert_allclose(r["color"][i], want, atol=1e-12)
+        np.testing.assert_allclose(r["D"][i], den, atol=1e-12)
+        checked += 1
+    assert checked > 150
+
+
 def test_front_to_back_order_matters_across_cells():
     """Swapping the depths of the two cells changes the colour (ordered
     across cells), while the member order inside a cell does not."""
