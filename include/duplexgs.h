@@ -55,7 +55,11 @@ typedef enum {
 
 typedef enum {
     DGS_MODE_DUPLEX = 0, /* per-cell keys + hybrid weighted-sum renderer (Sec. IV-V) */
-    DGS_MODE_ALPHA = 1   /* per-Gaussian keys + sorted alpha blending (comparison path) */
+    DGS_MODE_ALPHA = 1,  /* per-Gaussian keys + sorted alpha blending (comparison path) */
+    DGS_MODE_LCWSR = 2   /* the "w/o T^cell" ablation (Sec. VII): the Duplex pipeline with the cell
+                            transmittance replaced by the LC-WSR weight (eqs. WSR, LC-WSR) per cell,
+                            w_n = v_n max(0, 1 - d_n / lcwsr_tau), d_n the cell's camera depth;
+                            C = sum w_n A_n / sum w_n B_n, no termination, final_T = 1 */
 } dgs_mode;
 
 #define DGS_FLAG_V_ONE 1u  /* v_n = 1 for every cell (the "w/o v_n" ablation) */
@@ -100,6 +104,7 @@ typedef struct {
     float cov2d_dilation;  /* screen-space variance added to every Gaussian, px^2 (0.3) */
     float proxy_kappa;     /* cell footprint = kappa-sigma box of the projected proxy (1.0) */
     float bg[3];           /* colour of pixels no Gaussian reaches (0, 0, 0) */
+    float lcwsr_tau;       /* DGS_MODE_LCWSR only: the depth where the weight reaches 0 (> 0; default 0) */
 } dgs_render_opts;
 
 /* Output image, caller-owned device buffers, row-major. */

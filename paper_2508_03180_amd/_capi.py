@@ -23,6 +23,7 @@ STATUS_NAMES = {0: "DGS_OK", 1: "DGS_ERR_INVALID_ARG", 2: "DGS_ERR_OOM", 3: "DGS
 
 DGS_MODE_DUPLEX = 0
 DGS_MODE_ALPHA = 1
+DGS_MODE_LCWSR = 2
 DGS_FLAG_V_ONE = 1
 DGS_FLAG_NO_ET = 2
 DGS_FLAG_STATS = 4
@@ -44,7 +45,7 @@ class dgs_camera(C.Structure):
 class dgs_render_opts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("flags", C.c_uint32), ("eps_T", C.c_float), ("alpha_min", C.c_float),
                 ("alpha_max", C.c_float), ("cov2d_dilation", C.c_float), ("proxy_kappa", C.c_float),
-                ("bg", C.c_float * 3)]
+                ("bg", C.c_float * 3), ("lcwsr_tau", C.c_float)]
 
 
 class dgs_image(C.Structure):

@@ -117,7 +117,10 @@ dgs_status make_opts(dgs_ctx c, const dgs_render_opts* in, OptK& o, int& mode) {
     dgs_render_opts d;
     dgs_default_opts(&d);
     const dgs_render_opts& p = in ? *in : d;
-    if (p.mode != DGS_MODE_DUPLEX && p.mode != DGS_MODE_ALPHA) return fail(c, DGS_ERR_INVALID_ARG, "unknown mode");
+    if (p.mode != DGS_MODE_DUPLEX && p.mode != DGS_MODE_ALPHA && p.mode != DGS_MODE_LCWSR)
+        return fail(c, DGS_ERR_INVALID_ARG, "unknown mode");
+    if (p.mode == DGS_MODE_LCWSR && !(p.lcwsr_tau > 0 && finite_f(p.lcwsr_tau)))
+        return fail(c, DGS_ERR_INVALID_ARG, "DGS_MODE_LCWSR needs a finite lcwsr_tau > 0");
     if (!(p.alpha_min > 0) || !(p.alpha_max > 0) || !(p.alpha_max <= 1.0f) || !(p.eps_T >= 0) ||
         !(p.cov2d_dilation >= 0) || !(p.proxy_kappa > 0))
         return fail(c, DGS_ERR_INVALID_ARG, "render options out of range");
@@ -131,6 +134,7 @@ dgs_status make_opts(dgs_ctx c, const dgs_render_opts* in, OptK& o, int& mode) {
     o.v_one = (p.flags & DGS_FLAG_V_ONE) != 0;
     o.no_et = (p.flags & DGS_FLAG_NO_ET) != 0;
     o.stats = (p.flags & DGS_FLAG_STATS) != 0;
+    o.tau = p.mode == DGS_MODE_LCWSR ? p.lcwsr_tau : 0.0f;
     return DGS_OK;
 }
 
@@ -146,7 +150,7 @@ dgs_status check_scene(dgs_ctx c, const dgs_scene* s, int mode) {
     if (s->num_cells == 0) return DGS_OK;
     if (!s->means || !s->scales || !s->rots || !s->opacities || !s->sh)
         return fail(c, DGS_ERR_INVALID_ARG, "Gaussian arrays must not be NULL");
-    if (mode == DGS_MODE_DUPLEX && (!s->cell_pos || !s->cell_scale || !s->cell_rot || !s->cell_v_sh))
+    if (mode != DGS_MODE_ALPHA && (!s->cell_pos || !s->cell_scale || !s->cell_rot || !s->cell_v_sh))
         return fail(c, DGS_ERR_INVALID_ARG, "cell arrays must not be NULL");
     return DGS_OK;
 }
@@ -249,7 +253,7 @@ dgs_status dgs_internal_check_scene(dgs_ctx c, const dgs_scene* s, int mode) { r
 
 dgs_status dgs_internal_prepare(dgs_ctx c, const dgs_scene* s, int mode, int width, int height, int64_t keys) {
     const int64_t M = (int64_t)s->num_cells * s->gaussians_per_cell;
-    const int64_t P = mode == DGS_MODE_DUPLEX ? s->num_cells : M;
+    const int64_t P = mode != DGS_MODE_ALPHA ? s->num_cells : M;
     const int64_t tiles = (int64_t)((width + kTile - 1) / kTile) * ((height + kTile - 1) / kTile);
     hipSetDevice(c->device);
     return ensure(c, P, M, keys, tiles);
@@ -269,6 +273,7 @@ void dgs_default_opts(dgs_render_opts* o) {
     o->cov2d_dilation = 0.3f;
     o->proxy_kappa = 1.0f;
     o->bg[0] = o->bg[1] = o->bg[2] = 0.0f;
+    o->lcwsr_tau = 0.0f;
 }
 
 dgs_status dgs_create(int device, void* hip_stream, dgs_ctx* out) {
@@ -349,7 +354,8 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     const int N = s->num_cells, K = s->gaussians_per_cell;
     const int M = N * K;
     const int tiles = k.TX * k.TY;
-    const int P = mode == DGS_MODE_DUPLEX ? N : M;
+    const bool cells = mode != DGS_MODE_ALPHA;
+    const int P = cells ? N : M;
     int64_t want_keys = c->cap_keys;
     if (want_keys == 0) want_keys = dgs_internal_default_keys(P);
     if ((st = ensure(c, P, M, want_keys, tiles)) != DGS_OK) return st;
@@ -370,7 +376,7 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
         launch_clear(q, cl, write_frame ? &f : nullptr, c->frame);
     }
     sm.mark(0);
-    if (mode == DGS_MODE_DUPLEX) {
+    if (cells) {
         launch_cell_preprocess(q, N, s->cell_pos, s->cell_scale, s->cell_rot, s->cell_v_sh, s->v_sh_degree,
                                c->frame, c->p_depth, c->p_rect, c->p_ntiles, c->cell_v);
         sm.mark(1);
@@ -382,7 +388,7 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
                              nullptr, c->recs, c->grect, c->p_depth, c->p_ntiles);
     }
     sm.mark(2);
-    const uint64_t* prect = mode == DGS_MODE_DUPLEX ? c->p_rect : c->grect;
+    const uint64_t* prect = cells ? c->p_rect : c->grect;
     launch_exclusive_scan(q, c->p_ntiles, c->p_offsets, P, c->misc + 0, c->scan_status, c->misc + 13, c->misc + 1,
                           c->dev_err);
     const int bits = 32 + tile_bits(tiles);
@@ -416,6 +422,8 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     sm.mark(5);
     if (mode == DGS_MODE_DUPLEX)
         launch_composite_duplex(q, a);
+    else if (mode == DGS_MODE_LCWSR)
+        launch_composite_lcwsr(q, a);
     else
         launch_composite_alpha(q, a);
     sm.mark(6);
@@ -576,7 +584,7 @@ dgs_status dgs_read_prims(dgs_ctx c, int32_t* rect, uint32_t* depth_bits, uint32
     hipSetDevice(c->device);
     const int64_t P = c->last_prims;
     if (P == 0) return DGS_OK;
-    const uint64_t* pr = c->last_mode == DGS_MODE_DUPLEX ? c->p_rect : c->grect;
+    const uint64_t* pr = c->last_mode != DGS_MODE_ALPHA ? c->p_rect : c->grect;
     if (rect) hipLaunchKernelGGL(k_unpack_rects, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, c->stream, pr, P, rect);
     if (depth_bits) hipMemcpyAsync(depth_bits, c->p_depth, P * sizeof(uint32_t), hipMemcpyDeviceToDevice, c->stream);
     if (ntiles) hipMemcpyAsync(ntiles, c->p_ntiles, P * sizeof(uint32_t), hipMemcpyDeviceToDevice, c->stream);

@@ -10,6 +10,11 @@ constexpr int kMaxK = 32;        // Gaussians per cell supported by the composit
 constexpr int kBatchSlots = 256; // Gaussian records staged in LDS per batch
 constexpr int kXcds = 8;         // MI355X: 8 accelerator complex dies
 
+// Compositor modes (the dgs_mode values).
+constexpr int kModeDuplex = 0;
+constexpr int kModeAlpha = 1;
+constexpr int kModeLcwsr = 2;
+
 // Device-side error codes (mirror dgs_status values).
 constexpr int kErrCapacity = 3;
 constexpr int kErrTimeout = 6;
@@ -28,6 +33,7 @@ struct OptK {
     float eps, alpha_max, log2_alpha_min, delta, kappa;
     float bg[3];
     int v_one, no_et, stats;
+    float tau;  // > 0: LC-WSR cell weights v max(0, 1 - depth / tau) instead of the cell transmittance
 };
 
 // Camera and options of one frame.  Kernels read them from device memory

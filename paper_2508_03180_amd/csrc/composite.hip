@@ -159,7 +159,9 @@ struct Counters {
     uint32_t val = 0, rend = 0, box = 0, cellhit = 0;
 };
 
-template <bool STATS, int NS>
+// LC: the "w/o T^cell" weights -- cell_v holds w_n = v_n max(0, 1 - d_n / tau),
+// N += w A, D += w B, no transmittance and no termination.
+template <bool STATS, int NS, bool LC>
 __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, int tile, int s0, int lane, GRec* lds,
                                  Counters& cn) {
     const int tx0 = (tile % f.TX) * kTile, ty0 = (tile / f.TX) * kTile;
@@ -201,15 +203,17 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
                 any |= mj[j];
             }
             if (!any) continue;  // no member of this cell touches the owned strips
-            bool anyact = false;
+            if constexpr (!LC) {
+                bool anyact = false;
 #pragma unroll
-            for (int j = 0; j < NS; j++) {
-                act[j] = act[j] && !(T[j] < eps);  // cell-level termination
-                anyact = anyact || act[j];
-            }
-            if (!STATS && !__any(anyact)) {
-                alive = false;
-                break;
+                for (int j = 0; j < NS; j++) {
+                    act[j] = act[j] && !(T[j] < eps);  // cell-level termination
+                    anyact = anyact || act[j];
+                }
+                if (!STATS && !__any(anyact)) {
+                    alive = false;
+                    break;
+                }
             }
             const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cv), base));
             float A0[NS], A1[NS], A2[NS], Bs[NS], P[NS];
@@ -243,7 +247,7 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
                         A1[j] = fmaf(al, e.g, A1[j]);
                         A2[j] = fmaf(al, e.b, A2[j]);
                         Bs[j] += al;
-                        P[j] = fmaf(-P[j], v * al, P[j]);
+                        if constexpr (!LC) P[j] = fmaf(-P[j], v * al, P[j]);
                     }
                 }
             }
@@ -251,12 +255,12 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
             for (int j = 0; j < NS; j++) {
                 if (!mj[j]) continue;  // scalar: nothing of this cell in strip j
                 if (act[j]) {
-                    const float w = v * T[j];
+                    const float w = LC ? v : v * T[j];
                     N0[j] = fmaf(w, A0[j], N0[j]);
                     N1[j] = fmaf(w, A1[j], N1[j]);
                     N2[j] = fmaf(w, A2[j], N2[j]);
                     D[j] = fmaf(w, Bs[j], D[j]);
-                    T[j] *= P[j];
+                    if constexpr (!LC) T[j] *= P[j];
                     if (Bs[j] > 0.0f) last[j] = (int32_t)(pos + c - start + 1);
                     if (STATS) cn.cellhit += Bs[j] > 0.0f;
                 }
@@ -384,7 +388,8 @@ __device__ inline void alpha_tile(const CompositeArgs& a, const FrameView& f, in
 // Persistent wavefronts: each takes the next work item of a queue that lists
 // them heaviest first, so long tiles start early and short ones fill in
 // behind them on every XCD.  Every wavefront leaves once the queue is empty.
-template <bool DUPLEX, bool STATS>
+// MODE: kModeDuplex, kModeAlpha or kModeLcwsr.
+template <int MODE, bool STATS>
 __global__ __launch_bounds__(256) void k_composite(CompositeArgs a) {
     __shared__ GRec s_rec[kWaves][64];
     const FrameView f = frame_view(a.fr);
@@ -399,16 +404,17 @@ __global__ __launch_bounds__(256) void k_composite(CompositeArgs a) {
         if (t >= nitems) break;
         const uint32_t item = a.order[t];
         const int tile = (int)(item >> 3), mode = (int)(item & 7u);
-        if (DUPLEX) {
-            if (mode == 0)
-                duplex_tile<STATS, 4>(a, f, tile, 0, lane, lds, cn);
-            else
-                duplex_tile<STATS, 1>(a, f, tile, mode - 4, lane, lds, cn);
-        } else {
+        if (MODE == kModeAlpha) {
             if (mode == 0)
                 alpha_tile<STATS, 4>(a, f, tile, 0, lane, lds, cn);
             else
                 alpha_tile<STATS, 1>(a, f, tile, mode - 4, lane, lds, cn);
+        } else {
+            constexpr bool LC = MODE == kModeLcwsr;
+            if (mode == 0)
+                duplex_tile<STATS, 4, LC>(a, f, tile, 0, lane, lds, cn);
+            else
+                duplex_tile<STATS, 1, LC>(a, f, tile, mode - 4, lane, lds, cn);
         }
     }
     if (STATS) {
@@ -472,24 +478,19 @@ void launch_tile_order(hipStream_t st, const uint32_t* ranges, int tiles, uint32
     hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, st, ranges, tiles, split_len, order, queue);
 }
 
-static void launch_composite(hipStream_t st, const CompositeArgs& a, bool duplex) {
+template <int MODE>
+static void launch_mode(hipStream_t st, const CompositeArgs& a) {
     const int tiles = a.k.TX * a.k.TY;  // host copy of the frame's tile grid
     if (tiles <= 0) return;
     const dim3 g(persistent_grid(tiles)), b(256);
-    if (duplex) {
-        if (a.counters)
-            hipLaunchKernelGGL((k_composite<true, true>), g, b, 0, st, a);
-        else
-            hipLaunchKernelGGL((k_composite<true, false>), g, b, 0, st, a);
-    } else {
-        if (a.counters)
-            hipLaunchKernelGGL((k_composite<false, true>), g, b, 0, st, a);
-        else
-            hipLaunchKernelGGL((k_composite<false, false>), g, b, 0, st, a);
-    }
+    if (a.counters)
+        hipLaunchKernelGGL((k_composite<MODE, true>), g, b, 0, st, a);
+    else
+        hipLaunchKernelGGL((k_composite<MODE, false>), g, b, 0, st, a);
 }
 
-void launch_composite_duplex(hipStream_t st, const CompositeArgs& a) { launch_composite(st, a, true); }
-void launch_composite_alpha(hipStream_t st, const CompositeArgs& a) { launch_composite(st, a, false); }
+void launch_composite_duplex(hipStream_t st, const CompositeArgs& a) { launch_mode<kModeDuplex>(st, a); }
+void launch_composite_alpha(hipStream_t st, const CompositeArgs& a) { launch_mode<kModeAlpha>(st, a); }
+void launch_composite_lcwsr(hipStream_t st, const CompositeArgs& a) { launch_mode<kModeLcwsr>(st, a); }
 
 }  // namespace dgs

@@ -97,6 +97,8 @@ void launch_tile_order(hipStream_t st, const uint32_t* ranges, int tiles, uint32
 constexpr uint32_t kSplitLen = 64;
 void launch_composite_duplex(hipStream_t st, const CompositeArgs& a);
 void launch_composite_alpha(hipStream_t st, const CompositeArgs& a);
+// The Duplex walk with LC-WSR cell weights (cell_v holds the weights).
+void launch_composite_lcwsr(hipStream_t st, const CompositeArgs& a);
 
 // Backward of the Duplex compositor: per-Gaussian screen-space gradients
 // g2d[9][M] (mean x, y, conic A, B, C, sigma, r, g, b) and per-cell dL/dv,

@@ -174,6 +174,7 @@ __global__ __launch_bounds__(256) void k_cell_preprocess(int N, const float* __r
         float s = sh_eval(vdeg, d[0], d[1], d[2], vsh + n, N);
         v = 1.0f / (1.0f + __expf(-s));
     }
+    if (o.tau > 0.0f) v *= fmaxf(0.0f, 1.0f - tc[2] / o.tau);  // LC-WSR weight of the cell
     v_out[n] = v;
 }
 

@@ -335,7 +335,7 @@ struct dgs_server_s {
     WorkspaceCaps want_of(const Request& r) const {
         const dgs_scene& sc = scenes[r.scene];
         const int64_t M = (int64_t)sc.num_cells * sc.gaussians_per_cell;
-        const int64_t P = r.mode == DGS_MODE_DUPLEX ? sc.num_cells : M;
+        const int64_t P = r.mode != DGS_MODE_ALPHA ? sc.num_cells : M;
         const int64_t tiles = (int64_t)((r.cam.width + kTile - 1) / kTile) * ((r.cam.height + kTile - 1) / kTile);
         auto it = key_est.find(r.shape);
         int64_t keys = it == key_est.end() ? dgs_internal_default_keys(P) : it->second + it->second / 4 + 4096;
@@ -602,8 +602,8 @@ dgs_status dgs_server_submit(dgs_server srv, int32_t scene_id, const dgs_camera*
         srv->err = "unknown scene id";
         return DGS_ERR_INVALID_ARG;
     }
-    if (r.mode == DGS_MODE_DUPLEX && !srv->scene_has_cells[scene_id]) {
-        srv->err = "a Duplex render needs the scene's cell arrays";
+    if (r.mode != DGS_MODE_ALPHA && !srv->scene_has_cells[scene_id]) {
+        srv->err = "a Duplex or LC-WSR render needs the scene's cell arrays";
         return DGS_ERR_INVALID_ARG;
     }
     r.id = srv->next_id++;

@@ -83,11 +83,16 @@ def camera_struct(cam):
     return c
 
 
+MODES = {"duplex": capi.DGS_MODE_DUPLEX, "alpha": capi.DGS_MODE_ALPHA, "lcwsr": capi.DGS_MODE_LCWSR}
+
+
 def opts_struct(mode="duplex", v_one=False, no_et=False, stats=False, eps=None, alpha_min=None, alpha_max=None,
-                delta=None, kappa=None, bg=None):
+                delta=None, kappa=None, bg=None, tau=None):
     o = capi.dgs_render_opts()
     capi.dgs_default_opts(o)
-    o.mode = capi.DGS_MODE_DUPLEX if mode == "duplex" else capi.DGS_MODE_ALPHA
+    o.mode = MODES[mode]
+    if tau is not None:
+        o.lcwsr_tau = tau
     o.flags = (capi.DGS_FLAG_V_ONE if v_one else 0) | (capi.DGS_FLAG_NO_ET if no_et else 0) | \
               (capi.DGS_FLAG_STATS if stats else 0)
     if eps is not None:

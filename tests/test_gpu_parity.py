@@ -186,6 +186,37 @@ def test_tiny_scene_alpha_mode_parity(R):
     check_image(out, ref)
 
 
+@pytest.mark.parametrize("flags", [dict(tau=4.5), dict(tau=3.2, v_one=True), dict(tau=4.5, bg=(0.3, 0.1, 0.2)),
+                                   dict(tau=3.0, kappa=3.0)])
+def test_tiny_scene_lcwsr_parity(R, flags):
+    """The "w/o T^cell" mode (LC-WSR cell weights): whole image against the
+    oracle; no transmittance (T = 1) and the last contributing entry."""
+    s = scenes.make_tiny_scene(0)
+    cam = scenes.tiny_camera()
+    out = R.render(upload(s), cam, mode="lcwsr", **flags)
+    ref = oracle.render(s, cam, mode="lcwsr", **flags)
+    check_image(out, ref)
+    exact = ref["status"] == 0
+    D = out["D"].reshape(-1).double().cpu().numpy()
+    np.testing.assert_allclose(D[exact], ref["D"][exact], rtol=1e-5, atol=TOL)
+    assert (out["T"] == 1.0).all()
+    last = out["last"].reshape(-1).cpu().numpy()
+    assert (last[exact] == ref["last"][exact]).mean() > 0.999
+
+
+def test_lcwsr_mode_is_checked_and_has_no_backward(R):
+    from paper_2508_03180_amd import _capi
+    from paper_2508_03180_amd.renderer import opts_struct
+    s = upload(scenes.make_tiny_scene(0))
+    cam = scenes.tiny_camera()
+    out = R.alloc_image(cam)
+    assert R.render_into(s, cam, out, opts_struct(mode="lcwsr")) == _capi.DGS_ERR_INVALID_ARG
+    assert R.render_into(s, cam, out, opts_struct(mode="lcwsr", tau=float("inf"))) == _capi.DGS_ERR_INVALID_ARG
+    R.render(s, cam, out=out, mode="lcwsr", tau=4.0)
+    with pytest.raises(_capi.DgsError, match="UNSUPPORTED"):
+        R.render_backward(s, cam, out, torch.zeros((3, 256, 256), device="cuda"), mode="lcwsr", tau=4.0)
+
+
 def test_ragged_image_and_opaque_scene(R):
     """Image sides that are not multiples of 16 (partial tiles) and a scene of
     near-opaque Gaussians (early termination on most pixels)."""
@@ -245,6 +276,19 @@ def test_1080p_alpha_mode_sampled_pixels(R, c1):
     err = oracle.admissible_max_err(col, ref)
     assert np.isfinite(err).mean() > 0.998
     assert np.nanmax(err) <= TOL
+
+
+def test_1080p_lcwsr_sampled_pixels(R, c1):
+    cam = scenes.orbit_cameras(60, 1920, 1080)[20]
+    out = R.render(upload(c1), cam, mode="lcwsr", tau=8.0)
+    rng = np.random.default_rng(11)
+    pix = np.stack([rng.integers(0, 1920, 3000), rng.integers(0, 1080, 3000)], 1)
+    ref = oracle.render(c1, cam, mode="lcwsr", pixels=pix, tau=8.0)
+    col = out["color"].permute(1, 2, 0).double().cpu().numpy()[pix[:, 1], pix[:, 0]]
+    err = oracle.admissible_max_err(col, ref)
+    assert np.isfinite(err).mean() > 0.998
+    assert np.nanmax(err) <= TOL, f"max abs error {np.nanmax(err):.3e}"
+    assert (ref["nrend"] == ref["nval"]).all()
 
 
 # ------------------------------------------------------------------ edge cases
