@@ -74,6 +74,9 @@ def parse():
     p.add_argument("--no-alpha", action="store_true")
     p.add_argument("--cpu-frames", type=int, default=4)
     p.add_argument("--bwd-steps", type=int, default=10)
+    p.add_argument("--no-ablation", action="store_true")
+    p.add_argument("--no-ksweep", action="store_true")
+    p.add_argument("--ksweep-frames", type=int, default=20)
     p.add_argument("--no-large", action="store_true")
     p.add_argument("--large-cams", type=int, default=20, help="cameras of each kind (near, far) per resolution")
     p.add_argument("--no-serve", action="store_true")
@@ -150,6 +153,90 @@ def differentiation(r, scene, cam, steps):
     return {"loss": "0.8 L1 + 0.2 (1 - SSIM 11x11) vs perturbed-scene target", "width": 1920, "height": 1080,
             "fwd_loss_bwd_ms": round(dt * 1e3, 3), "backward_ms": round(bt * 1e3, 3),
             "final_loss": round(float(loss.detach()), 5)}
+
+
+# LC-WSR weights of the "w/o T^cell" variant on the mid scene: the farthest
+# cell of the orbit sits at depth ~5.6, so weights fall linearly from ~0.8 in
+# front to ~0.3 at the back and none is clamped to 0
+ABLATION_TAU = 8.0
+
+
+def ablation(r, ds, cams, timed_frames):
+    """Frames/s of the variants of the ablation table on the benchmark orbit:
+    the full method, w/o T^cell (LC-WSR cell weights), w/o ET, w/o v_n."""
+    import torch
+    variants = {"full": {}, "wo_Tcell": dict(mode="lcwsr", tau=ABLATION_TAU), "wo_ET": dict(no_et=True),
+                "wo_v": dict(v_one=True)}
+    out = {}
+    for name, kw in variants.items():
+        nval = nrend = 0
+        for c in cams[::6]:
+            r.render(ds, c, **kw, stats=True)
+            st = r.stats()
+            nval += st["n_val"]
+            nrend += st["n_rendered"]
+        img = r.alloc_image(cams[0])
+        for c in cams[:5]:
+            r.render(ds, c, out=img, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(timed_frames):
+            r.render(ds, cams[i % len(cams)], out=img, check=False, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        assert r.sync() == 0
+        out[name] = {"fps": round(timed_frames / dt, 2), "termination_ratio": round(1 - nrend / max(nval, 1), 4),
+                     "rendered_per_pixel": round(nrend / len(cams[::6]) / (cams[0]["width"] * cams[0]["height"]), 3)}
+    out["tau"] = ABLATION_TAU
+    return out
+
+
+KSWEEP = (1, 2, 5, 10, 20, 32)
+
+
+def k_sweep(a):
+    """Members per cell K at a fixed 1M Gaussians (mid-scene generator with
+    1M / K cells), 1080p orbit: keys, cells in the frustum, valid Gaussians
+    per pixel and frames/s of both modes."""
+    import torch
+
+    from paper_2508_03180_amd import scenes
+    from paper_2508_03180_amd.renderer import DeviceScene, Renderer
+
+    cams = scenes.orbit_cameras(60, 1920, 1080)[::60 // a.ksweep_frames][:a.ksweep_frames]
+    r = Renderer(0)
+    out = {"gaussians": 1_000_000, "frames": len(cams)}
+    for K in KSWEEP:
+        ds = DeviceScene.from_numpy(scenes.make_mid_scene(1, n_cells=1_000_000 // K, K=K), "cuda:0")
+        img = r.alloc_image(cams[0])
+        res = {}
+        for mode in ("duplex", "alpha"):
+            keys = nval = vis = 0
+            for c in cams:
+                r.render(ds, c, out=img, mode=mode, stats=True)
+                st = r.stats()
+                keys += st["num_keys"]
+                nval += st["n_val"]
+                if mode == "duplex":
+                    _, _, nt = r.read_prims(ds.N)
+                    vis += int((nt > 0).sum().item())
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for c in cams:
+                r.render(ds, c, out=img, mode=mode, check=False)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            assert r.sync() == 0
+            res[mode] = {"fps": round(len(cams) / dt, 2), "keys_mean": round(keys / len(cams), 1),
+                         "valid_per_pixel": round(nval / len(cams) / (1920 * 1080), 3)}
+            if mode == "duplex":
+                res[mode]["cells_in_frustum"] = round(vis / len(cams), 1)
+        res["speedup"] = round(res["duplex"]["fps"] / res["alpha"]["fps"], 3)
+        out[f"K{K}"] = res
+        del ds, img
+    r.close()
+    torch.cuda.empty_cache()
+    return out
 
 
 LARGE_SIZES = [(1280, 720), (1920, 1080), (3840, 2160)]
@@ -369,6 +456,8 @@ def main():
     # against a target rendered from a perturbed copy of the scene
     bwd = differentiation(r, scene, cams[0], a.bwd_steps)
 
+    abl = None if a.no_ablation else ablation(r, ds, cams, a.steps)
+    ksw = None if a.no_ksweep else k_sweep(a)
     large = None if a.no_large else large_scene(a)
     serve = None if a.no_serve else serving(a)
 
@@ -403,6 +492,8 @@ def main():
         "termination_ratio": round(1 - cnt["n_rendered"] / max(cnt["n_val"], 1), 4),
         "roofline": roof,
         "differentiation": bwd,
+        "ablation": abl,
+        "k_sweep": ksw,
         "large_scene": large,
         "serving": serve,
         "cpu_baseline": cpu,
