@@ -239,3 +239,62 @@ def admissible_max_err(gpu_color, res):
             err[i] = min(err[i], np.abs(g[i] - res["alt"][s, a, :3]).max())
     err[res["status"] == 2] = np.nan
     return err
+
+
+# ------------------------------------------------------------- neural decode
+
+DECODER_OUTPUTS = (1, 3, 3, 4)  # opacity, colour, scale ratio, quaternion (per Gaussian)
+
+
+def decoder_size(F, H, K):
+    return int(_load().orc_decoder_size(C.c_int(F), C.c_int(H), C.c_int(K)))
+
+
+def exp32(x):
+    """The binary32 exp of the decode (Cody-Waite + degree-7 Taylor)."""
+    x = np.ascontiguousarray(x, np.float32).reshape(-1)
+    out = np.zeros_like(x)
+    _load().orc_exp32(C.c_int(x.size), _p(x), _p(out))
+    return out
+
+
+def decode(scene, decoder, cam, raw=False):
+    """Decode the Gaussians of a neural scene for a camera (Sec. III-A,
+    Sec. IV-A): returns an explicit scene (cells kept; means, scales and raw
+    quaternions in binary32; opacity tanh(y) and colour sigmoid(y) rounded
+    to binary32, colour as SH degree 0) plus the binary64 opacity/colour and,
+    with raw=True, the raw decoder outputs [N, sum K a].
+
+    scene: cell_pos [N,3], cell_scale, cell_rot, cell_v_sh, v_sh_degree, K,
+    features [N,F], offsets [N*K,3]; decoder: dict(F, H, weights) with the
+    packed float32 weights (see orc_decode)."""
+    L = _load()
+    N = scene["cell_pos"].shape[0]
+    K = int(scene["K"])
+    F, H = int(decoder["F"]), int(decoder["H"])
+    w = _f32(decoder["weights"]).reshape(-1)
+    assert w.size == decoder_size(F, H, K), "decoder weights have the wrong size"
+    feat = _f32(scene["features"]).reshape(N, F)
+    offs = _f32(scene["offsets"]).reshape(N * K, 3)
+    M = N * K
+    means = np.zeros((M, 3), np.float32)
+    scales = np.zeros((M, 3), np.float32)
+    rots = np.zeros((M, 4), np.float32)
+    opac = np.zeros(M, np.float64)
+    col = np.zeros((M, 3), np.float64)
+    ysz = K * sum(DECODER_OUTPUTS)
+    rawv = np.zeros((N, ysz), np.float32) if raw else None
+    rc = L.orc_decode(C.c_int(N), C.c_int(K), C.c_int(F), C.c_int(H), _p(_f32(scene["cell_pos"])),
+                      _p(_f32(scene["cell_scale"])), _p(_f32(scene["cell_rot"])), _p(feat), _p(offs), _p(w),
+                      _p(camera_vector(cam)), _p(means), _p(scales), _p(rots), _p(opac), _p(col),
+                      _p(rawv) if raw else None)
+    if rc != 0:
+        raise RuntimeError("orc_decode failed")
+    y00 = 1.0 / (2.0 * np.sqrt(np.pi))
+    out = {k: scene[k] for k in ("cell_pos", "cell_scale", "cell_rot", "cell_v_sh", "v_sh_degree", "K")}
+    out.update(means=means, scales=scales, rots=rots, opacities=opac.astype(np.float32),
+               sh=((col - 0.5) / y00).astype(np.float32).reshape(M, 1, 3), sh_degree=0,
+               opacity64=opac, color64=col)
+    if raw:
+        out["raw"] = rawv
+    return out

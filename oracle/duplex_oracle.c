@@ -632,6 +632,145 @@ int64_t orc_render(int mode, int N, int K, const float *cell_pos, const float *c
     return cnt;
 }
 
+/* ================================================================== */
+/* Neural decode of cells (Sec. III-A neural Gaussians, Sec. IV-A):    */
+/* K Gaussians per cell from the cell feature f_n, the viewing distance */
+/* delta_n and direction d_n through four MLPs F_sigma, F_c, F_s, F_q.  */
+/* ================================================================== */
+/*
+ * The decoded scales, rotations and centres decide every Gaussian's pixel
+ * box (an integer), so they are computed in binary32 in one fixed order that
+ * the GPU follows too; opacity and colour only enter the continuous layer
+ * and are activated in binary64.
+ *
+ * Weights: one float array holding, for the decoders d = 0 (opacity, a = 1),
+ * 1 (colour, a = 3), 2 (scale ratio, a = 3), 3 (quaternion, a = 4) in this
+ * order, W1[(F+4)][H] (input-major), b1[H], W2[H][K a], b2[K a]; output o of
+ * decoder d belongs to member o / a, component o % a.
+ * Input vector: (f_0 .. f_{F-1}, delta, d_x, d_y, d_z).
+ */
+static const int DEC_A[4] = {1, 3, 3, 4};
+
+int64_t orc_decoder_size(int F, int H, int K) {
+    int64_t n = 0;
+    for (int d = 0; d < 4; d++) n += (int64_t)(F + 4) * H + H + (int64_t)H * K * DEC_A[d] + (int64_t)K * DEC_A[d];
+    return n;
+}
+
+/* exp(x) in binary32 by the Cody-Waite reduction x = n ln2 + r (ln2 split
+ * into an 8-significant-bit high part and the rest, so n * ln2_hi is exact)
+ * and the degree-7 Taylor polynomial of e^r on |r| <= ln2 / 2, Horner form,
+ * one rounding per operation; then scaled by 2^n. */
+static float exp32_def(float x) {
+    if (x > 88.0f) x = 88.0f;
+    if (x < -88.0f) x = -88.0f;
+    const float log2e = 1.44269504088896341f;
+    const float ln2_hi = 0.693145751953125f, ln2_lo = 1.42860682030941723e-6f;
+    float n = rintf(x * log2e);
+    float r = (x - n * ln2_hi) - n * ln2_lo;
+    float p = 1.0f / 5040.0f;
+    p = p * r + 1.0f / 720.0f;
+    p = p * r + 1.0f / 120.0f;
+    p = p * r + 1.0f / 24.0f;
+    p = p * r + 1.0f / 6.0f;
+    p = p * r + 0.5f;
+    p = p * r + 1.0f;
+    p = p * r + 1.0f;
+    return ldexpf(p, (int)n);
+}
+
+/* logistic sigmoid in binary32 on exp32_def */
+static float sigmoid32_def(float y) { return 1.0f / (1.0f + exp32_def(-y)); }
+
+void orc_exp32(int n, const float *x, float *out) {
+    for (int i = 0; i < n; i++) out[i] = exp32_def(x[i]);
+}
+
+/* two-layer MLP of decoder d for one input vector, binary32 fixed order:
+ * h_j = max(0, b1_j + sum_i x_i W1_ij) and y_o = b2_o + sum_j h_j W2_jo, each
+ * sum accumulated by fused multiply-adds in ascending index order */
+static void mlp32(const float *w, int I, int H, int O, const float *x, float *h, float *y) {
+    const float *W1 = w, *b1 = W1 + (int64_t)I * H, *W2 = b1 + H, *b2 = W2 + (int64_t)H * O;
+    for (int j = 0; j < H; j++) {
+        float acc = b1[j];
+        for (int i = 0; i < I; i++) acc = fmaf(x[i], W1[(int64_t)i * H + j], acc);
+        h[j] = acc > 0.0f ? acc : 0.0f;
+    }
+    for (int o = 0; o < O; o++) {
+        float acc = b2[o];
+        for (int j = 0; j < H; j++) acc = fmaf(h[j], W2[(int64_t)j * O + o], acc);
+        y[o] = acc;
+    }
+}
+
+/*
+ * Decode every cell (row-major [N][.] inputs): feat [N][F], offsets O^pos
+ * [N*K][3] (components in [-1, 1]).  Outputs per Gaussian: mean, scale and
+ * raw quaternion (binary32), opacity sigma = tanh(y) and colour sigmoid(y)
+ * (binary64), and the raw decoder outputs y [N][sum K a] when raw != NULL.
+ *   centre (eq. scaffold_offset, offsets in the cell frame):
+ *       mu = x_n + R(Q_n) (O^pos * S_n)
+ *   scale (eqs. nerual_scales, scale_res):
+ *       r = max(0, min(sigmoid(y_s), 1 - |O^pos|)),  s = r * S_n
+ */
+int orc_decode(int N, int K, int F, int H, const float *cell_pos, const float *cell_scale, const float *cell_rot,
+               const float *feat, const float *offs, const float *weights, const float *camv, float *means,
+               float *scales, float *rots, double *opac, double *color, float *raw) {
+    if (F < 1 || H < 1 || K < 1) return -1;
+    cam_t k; cam_load(camv, &k);
+    float o32[3] = {(float)k.od[0], (float)k.od[1], (float)k.od[2]};
+    const int I = F + 4;
+    int64_t off[4], ysz = 0, yoff[4];
+    {
+        int64_t acc = 0;
+        for (int d = 0; d < 4; d++) {
+            off[d] = acc;
+            acc += (int64_t)I * H + H + (int64_t)H * K * DEC_A[d] + (int64_t)K * DEC_A[d];
+            yoff[d] = ysz;
+            ysz += (int64_t)K * DEC_A[d];
+        }
+    }
+    int err = 0;
+#pragma omp parallel
+    {
+        float *x = malloc(sizeof(float) * I), *h = malloc(sizeof(float) * H), *y = malloc(sizeof(float) * ysz);
+        if (!x || !h || !y) err = 1;
+#pragma omp for schedule(static)
+        for (int n = 0; n < N; n++) {
+            if (!x || !h || !y) continue;
+            const float *p = cell_pos + 3 * n, *S = cell_scale + 3 * n;
+            for (int i = 0; i < F; i++) x[i] = feat[(int64_t)n * F + i];
+            float ex = p[0] - o32[0], ey = p[1] - o32[1], ez = p[2] - o32[2];
+            float dist = sqrtf((ex * ex + ey * ey) + ez * ez);
+            x[F] = dist;
+            x[F + 1] = ex / dist; x[F + 2] = ey / dist; x[F + 3] = ez / dist;
+            for (int d = 0; d < 4; d++) mlp32(weights + off[d], I, H, K * DEC_A[d], x, h, y + yoff[d]);
+            if (raw) memcpy(raw + (int64_t)n * ysz, y, sizeof(float) * ysz);
+            float R[9];
+            quat_rot32(cell_rot + 4 * n, R);
+            for (int kk = 0; kk < K; kk++) {
+                int64_t g = (int64_t)n * K + kk;
+                const float *O = offs + 3 * g;
+                float u[3] = {O[0] * S[0], O[1] * S[1], O[2] * S[2]};
+                for (int a = 0; a < 3; a++)
+                    means[3 * g + a] = p[a] + ((R[3 * a] * u[0] + R[3 * a + 1] * u[1]) + R[3 * a + 2] * u[2]);
+                float lim = 1.0f - sqrtf((O[0] * O[0] + O[1] * O[1]) + O[2] * O[2]);
+                for (int a = 0; a < 3; a++) {
+                    float r = sigmoid32_def(y[yoff[2] + 3 * kk + a]);
+                    r = r < lim ? r : lim;
+                    r = r > 0.0f ? r : 0.0f;
+                    scales[3 * g + a] = r * S[a];
+                }
+                for (int a = 0; a < 4; a++) rots[4 * g + a] = y[yoff[3] + 4 * kk + a];
+                opac[g] = tanh((double)y[yoff[0] + kk]);
+                for (int c = 0; c < 3; c++) color[3 * g + c] = 1.0 / (1.0 + exp(-(double)y[yoff[1] + 3 * kk + c]));
+            }
+        }
+        free(x); free(h); free(y);
+    }
+    return err ? -1 : 0;
+}
+
 /* FP64 continuous quantities of selected Gaussians, for the pins:
  * out[11*i] = u.x, u.y, cov.xx, cov.xy, cov.yy (no dilation), r, g, b,
  * and the conic of the dilated covariance. */

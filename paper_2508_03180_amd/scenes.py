@@ -164,6 +164,38 @@ def make_large_scene(seed=2, n_cells=600_000, K=10, sh_degree=3, extent=100.0,
                      rots=rots, opacities=opac, sh=sh, sh_degree=sh_degree, K=K))
 
 
+def make_neural_scene(seed=1, n_cells=100_000, K=10, F=32, H=32):
+    """Cells of the clustered generator with a latent feature each and K
+    offsets in the unit ball (|O^pos| <= 0.9), plus random decoder weights
+    (no trained ones exist): N(0, 1/fan-in) matrices; biases set so that
+    most Gaussians are valid (opacity logit +1.5), colours are mid-grey on
+    average and scale ratios sit near 0.22 (member scale / cell scale of the
+    explicit generator).  Returns (scene, decoder)."""
+    rng = np.random.default_rng(seed)
+    N = n_cells
+    cell_pos = _clustered_centres(rng, N)
+    cell_scale = np.exp(rng.normal(-4.0, 0.3, (N, 3)))
+    cell_rot = _unit_quats(rng, N)
+    cell_v_sh = _v_sh(rng, N, 1)
+    feats = rng.normal(0.0, 1.0, (N, F))
+    offs = _points_in_unit_ball(rng, N * K) * 0.9
+    parts = []
+    for a, bias in zip((1, 3, 3, 4), (1.5, 0.0, -1.25, None)):
+        I, O = F + 4, K * a
+        W1 = rng.normal(0.0, 1.0 / math.sqrt(I), (I, H))
+        b1 = rng.normal(0.0, 0.1, H)
+        W2 = rng.normal(0.0, 0.5 / math.sqrt(H), (H, O))
+        if bias is None:  # quaternions: identity plus noise
+            b2 = np.tile([2.0, 0.0, 0.0, 0.0], K) + rng.normal(0.0, 0.3, O)
+        else:
+            b2 = bias + rng.normal(0.0, 0.3, O)
+        parts += [W1.ravel(), b1, W2.ravel(), b2]
+    scene = _f32(dict(cell_pos=cell_pos, cell_scale=cell_scale, cell_rot=cell_rot, cell_v_sh=cell_v_sh,
+                      v_sh_degree=1, K=K, features=feats, offsets=offs))
+    decoder = dict(F=F, H=H, weights=np.concatenate(parts).astype(np.float32))
+    return scene, decoder
+
+
 def subset_scene(scene, cells):
     """Scene restricted to the given cell indices (members follow their cells)."""
     cells = np.asarray(cells)

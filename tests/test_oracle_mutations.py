@@ -1,7 +1,8 @@
 """Planted-mistake check of the oracle pins (CPU only).
 
 Each case copies the C oracle, plants one plausible mistake, builds it and
-runs the pin suite against the mutated library; the pins must fail.
+runs the pin suites (renderer and neural decode) against the mutated
+library; the pins must fail.
 """
 import os
 import subprocess
@@ -54,6 +55,17 @@ MUTATIONS = {
     "lcwsr_without_v": [("vv[n] *= lin > 0 ? lin : 0.0;", "vv[n] = lin > 0 ? lin : 0.0;")],
     "lcwsr_terminates": [("        int n = c->ids[i];\n        double w = c->v[n];",
                           "        if (D > 1.0) break;\n        int n = c->ids[i];\n        double w = c->v[n];")],
+    # the neural decode
+    "decode_no_relu": [("h[j] = acc > 0.0f ? acc : 0.0f;", "h[j] = acc;")],
+    "decode_no_scale_clamp": [("r = r < lim ? r : lim;", "")],
+    "decode_offset_not_rotated": [("means[3 * g + a] = p[a] + ((R[3 * a] * u[0] + R[3 * a + 1] * u[1]) + R[3 * a + 2] * u[2]);",
+                                   "means[3 * g + a] = p[a] + u[a];")],
+    "decode_inputs_swapped": [("x[F] = dist;\n            x[F + 1] = ex / dist;",
+                               "x[F + 1] = dist;\n            x[F] = ex / dist;")],
+    "decode_opacity_sigmoid": [("opac[g] = tanh((double)y[yoff[0] + kk]);",
+                                "opac[g] = 1.0 / (1.0 + exp(-(double)y[yoff[0] + kk]));")],
+    "decode_exp_short_series": [("    p = p * r + 1.0f / 120.0f;\n", "")],
+    "decode_ratio_of_cell_scale_missing": [("scales[3 * g + a] = r * S[a];", "scales[3 * g + a] = r;")],
     "lcwsr_depth_along_x": [("return k->Rd[6] * pos[3 * n] + k->Rd[7] * pos[3 * n + 1] + k->Rd[8] * pos[3 * n + 2] + k->td[2];",
                              "return k->Rd[0] * pos[3 * n] + k->Rd[1] * pos[3 * n + 1] + k->Rd[2] * pos[3 * n + 2] + k->td[0];")],
 }
@@ -72,6 +84,7 @@ def test_pins_catch_planted_mistake(name, tmp_path):
                            "-o", str(lib), str(cfile), "-lm"])
     env = dict(os.environ, DUPLEX_ORACLE_LIB=str(lib), OMP_NUM_THREADS="2")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")], env=env, cwd=ROOT,
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_decode_pins.py")], env=env, cwd=ROOT,
                        capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"planted mistake '{name}' passed every pin"
