@@ -210,6 +210,57 @@ dgs_status dgs_read_prims(dgs_ctx ctx, int32_t* rect, uint32_t* depth_bits, uint
  * render ([M][4] int32, -1 when culled or not projected). */
 dgs_status dgs_read_gauss_rects(dgs_ctx ctx, int32_t* rect);
 
+/*
+ * Neural scenes (Sec. III-A neural Gaussians with the cell proxy of
+ * Sec. IV-A): each cell carries a latent feature f_n and emits K Gaussians
+ * whose attributes four shared two-layer MLPs decode from (f_n, delta_n,
+ * d_n), delta_n / d_n the distance / unit direction from the camera centre
+ * to x_n.  Each decoder is Linear(F+4 -> H), ReLU, Linear(H -> K a) with
+ *   d = 0  opacity       a = 1  sigma = tanh(y) (a Gaussian is valid iff sigma > 0)
+ *   d = 1  colour        a = 3  c = sigmoid(y)
+ *   d = 2  scale ratio   a = 3  r = max(0, min(sigmoid(y), 1 - |O^pos|)), s = r * S_n
+ *                               (eqs. nerual_scales, scale_res)
+ *   d = 3  quaternion    a = 4  q = y (normalised where used)
+ * and centres mu = x_n + R(Q_n)(O^pos * S_n) (eq. scaffold_offset, the
+ * offset O^pos in the cell frame).  Output o of decoder d belongs to member
+ * o / a, component o % a.  Only cells that pass cell rasterization are
+ * decoded (every cell in DGS_MODE_ALPHA).
+ */
+typedef struct {
+    int32_t feature_dim;   /* F in 1..64 */
+    int32_t hidden_dim;    /* H in 1..64 */
+    const float* weights;  /* device; for d = 0..3 in order: W1[(F+4)][H] (input-major: W1[i*H + j]),
+                              b1[H], W2[H][K a] (W2[j*K*a + o]), b2[K a]; input order
+                              (f_0 .. f_{F-1}, delta, d_x, d_y, d_z) */
+} dgs_decoder;
+
+typedef struct {
+    int32_t num_cells;          /* N >= 0 */
+    int32_t gaussians_per_cell; /* K in 1..32 */
+    const float* cell_pos;      /* [3][N] */
+    const float* cell_scale;    /* [3][N] */
+    const float* cell_rot;      /* [4][N] */
+    const float* cell_v_sh;     /* [Cv][N] */
+    int32_t v_sh_degree;        /* 0..3 */
+    const float* features;      /* [F][N] latent features */
+    const float* offsets;       /* [3][M] O^pos per Gaussian, |O^pos| <= 1 expected */
+} dgs_neural_scene;
+
+/* Renders a neural scene: cell rasterization, decode of the visible cells'
+ * Gaussians, then the same pipeline as dgs_render (DGS_MODE_DUPLEX,
+ * DGS_MODE_LCWSR or DGS_MODE_ALPHA).  The decoded attributes stay in the
+ * context's workspace until the next render (dgs_read_decoded).  No
+ * backward. */
+dgs_status dgs_render_neural(dgs_ctx ctx, const dgs_neural_scene* scene, const dgs_decoder* decoder,
+                             const dgs_camera* cam, const dgs_render_opts* opts, const dgs_image* out);
+
+/* Copies (asynchronously) the Gaussians decoded by the last
+ * dgs_render_neural into caller device buffers, planar: means [3][M],
+ * scales [3][M], raw quaternions [4][M], opacities [M], colours [3][M]; any
+ * pointer may be NULL.  Entries of cells that were not decoded are
+ * undefined. */
+dgs_status dgs_read_decoded(dgs_ctx ctx, float* means, float* scales, float* rots, float* opacities, float* colors);
+
 /* Stage timing.  While enabled, every render records HIP events on the
  * context stream at the boundaries of its stages:
  *   0 cell preprocess (or nothing in alpha mode), 1 Gaussian projection,

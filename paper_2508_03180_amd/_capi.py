@@ -64,6 +64,17 @@ class dgs_stats(C.Structure):
                 ("device_error", C.c_int32), ("sort_passes", C.c_int32)]
 
 
+class dgs_decoder(C.Structure):
+    _fields_ = [("feature_dim", C.c_int32), ("hidden_dim", C.c_int32), ("weights", C.c_void_p)]
+
+
+class dgs_neural_scene(C.Structure):
+    _fields_ = [("num_cells", C.c_int32), ("gaussians_per_cell", C.c_int32),
+                ("cell_pos", C.c_void_p), ("cell_scale", C.c_void_p), ("cell_rot", C.c_void_p),
+                ("cell_v_sh", C.c_void_p), ("v_sh_degree", C.c_int32), ("features", C.c_void_p),
+                ("offsets", C.c_void_p)]
+
+
 class dgs_server_config(C.Structure):
     _fields_ = [("num_slots", C.c_int32), ("use_graphs", C.c_int32), ("memory_budget", C.c_int64)]
 
@@ -101,6 +112,9 @@ _SIGS = {
     "dgs_render_backward": (C.c_int, [dgs_ctx, C.POINTER(dgs_scene), C.POINTER(dgs_camera),
                                       C.POINTER(dgs_render_opts), C.POINTER(dgs_image), C.c_void_p, C.c_void_p,
                                       C.POINTER(dgs_grads)]),
+    "dgs_render_neural": (C.c_int, [dgs_ctx, C.POINTER(dgs_neural_scene), C.POINTER(dgs_decoder),
+                                    C.POINTER(dgs_camera), C.POINTER(dgs_render_opts), C.POINTER(dgs_image)]),
+    "dgs_read_decoded": (C.c_int, [dgs_ctx, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "dgs_sync": (C.c_int, [dgs_ctx]),
     "dgs_get_stats": (C.c_int, [dgs_ctx, C.POINTER(dgs_stats)]),
     "dgs_last_error": (C.c_char_p, [dgs_ctx]),
@@ -195,6 +209,16 @@ def dgs_render(ctx, scene, cam, opts, image):
 def dgs_render_backward(ctx, scene, cam, opts, image, grad_color_ptr, grad_weight_sum_ptr, grads):
     return lib().dgs_render_backward(ctx, C.byref(scene), C.byref(cam), C.byref(opts), C.byref(image),
                                      C.c_void_p(grad_color_ptr), C.c_void_p(grad_weight_sum_ptr), C.byref(grads))
+
+
+def dgs_render_neural(ctx, scene, decoder, cam, opts, image):
+    return lib().dgs_render_neural(ctx, C.byref(scene), C.byref(decoder), C.byref(cam), C.byref(opts),
+                                   C.byref(image))
+
+
+def dgs_read_decoded(ctx, means_ptr, scales_ptr, rots_ptr, opac_ptr, colors_ptr):
+    return check(lib().dgs_read_decoded(ctx, C.c_void_p(means_ptr), C.c_void_p(scales_ptr), C.c_void_p(rots_ptr),
+                                        C.c_void_p(opac_ptr), C.c_void_p(colors_ptr)), ctx)
 
 
 def dgs_sync(ctx):

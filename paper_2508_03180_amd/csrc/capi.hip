@@ -138,14 +138,14 @@ dgs_status make_opts(dgs_ctx c, const dgs_render_opts* in, OptK& o, int& mode) {
     return DGS_OK;
 }
 
-dgs_status check_scene(dgs_ctx c, const dgs_scene* s, int mode) {
+dgs_status check_scene(dgs_ctx c, const dgs_scene* s, int mode, bool decoded = false) {
     if (!s) return fail(c, DGS_ERR_INVALID_ARG, "scene is NULL");
     if (s->num_cells < 0) return fail(c, DGS_ERR_INVALID_ARG, "num_cells < 0");
     if (s->gaussians_per_cell < 1 || s->gaussians_per_cell > kMaxK)
         return fail(c, DGS_ERR_INVALID_ARG, "gaussians_per_cell must be in 1..32");
     if ((int64_t)s->num_cells * s->gaussians_per_cell > (int64_t)(1 << 30))
         return fail(c, DGS_ERR_INVALID_ARG, "too many Gaussians");
-    if (s->sh_degree < 0 || s->sh_degree > 3 || s->v_sh_degree < 0 || s->v_sh_degree > 3)
+    if (s->sh_degree < (decoded ? -1 : 0) || s->sh_degree > 3 || s->v_sh_degree < 0 || s->v_sh_degree > 3)
         return fail(c, DGS_ERR_INVALID_ARG, "SH degree must be in 0..3");
     if (s->num_cells == 0) return DGS_OK;
     if (!s->means || !s->scales || !s->rots || !s->opacities || !s->sh)
@@ -195,6 +195,41 @@ __global__ void k_unpack_rects(const uint64_t* in, int64_t n, int32_t* out) {
         out[4 * i] = rect_x0(r); out[4 * i + 1] = rect_x1(r);
         out[4 * i + 2] = rect_y0(r); out[4 * i + 3] = rect_y1(r);
     }
+}
+
+int64_t decoder_floats(int F, int H, int K, int64_t* woff) {
+    static const int A[4] = {1, 3, 3, 4};
+    int64_t n = 0;
+    for (int d = 0; d < 4; d++) {
+        if (woff) woff[d] = n;
+        n += (int64_t)(F + 4) * H + H + (int64_t)H * K * A[d] + (int64_t)K * A[d];
+    }
+    return n;
+}
+
+DecodeArgs decode_args(dgs_ctx c, const NeuralSrc& nn, const uint32_t* cell_ntiles) {
+    const dgs_neural_scene& s = *nn.scene;
+    DecodeArgs a;
+    a.N = s.num_cells;
+    a.K = s.gaussians_per_cell;
+    a.F = nn.decoder->feature_dim;
+    a.H = nn.decoder->hidden_dim;
+    a.cell_pos = s.cell_pos;
+    a.cell_scale = s.cell_scale;
+    a.cell_rot = s.cell_rot;
+    a.features = s.features;
+    a.offsets = s.offsets;
+    a.weights = nn.decoder->weights;
+    decoder_floats(a.F, a.H, a.K, a.woff);
+    a.cell_ntiles = cell_ntiles;
+    a.fr = c->frame;
+    const int64_t M = (int64_t)a.N * a.K;
+    a.means = c->dec;
+    a.scales = c->dec + 3 * M;
+    a.rots = c->dec + 6 * M;
+    a.opac = c->dec + 10 * M;
+    a.color = c->dec + 11 * M;
+    return a;
 }
 
 }  // namespace
@@ -308,7 +343,7 @@ dgs_status dgs_destroy(dgs_ctx c) {
     for (auto& a : c->events)
         for (auto& e : a) hipEventDestroy(e);
     void* ptrs[] = {c->p_depth, c->p_ntiles, c->p_offsets, c->p_rect, c->cell_v, c->recs, c->grect,
-                    c->keys0, c->keys1, c->vals0, c->vals1, c->ranges, c->tile_order, c->scan_status, c->sort_status, c->g2d, c->gv,
+                    c->keys0, c->keys1, c->vals0, c->vals1, c->ranges, c->tile_order, c->scan_status, c->sort_status, c->g2d, c->gv, c->dec,
                     c->hist, c->misc, c->dev_err, c->counters, c->frame};
     for (void* p : ptrs)
         if (p) hipFree(p);
@@ -334,13 +369,70 @@ dgs_status dgs_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* cam, cons
     return dgs_internal_render(c, s, cam, opts, out, true);
 }
 
+dgs_status dgs_render_neural(dgs_ctx c, const dgs_neural_scene* ns, const dgs_decoder* dec, const dgs_camera* cam,
+                             const dgs_render_opts* opts, const dgs_image* out) {
+    if (!c) return DGS_ERR_INVALID_ARG;
+    if (!ns || !dec) return fail(c, DGS_ERR_INVALID_ARG, "neural scene or decoder is NULL");
+    if (ns->num_cells < 0) return fail(c, DGS_ERR_INVALID_ARG, "num_cells < 0");
+    if (ns->gaussians_per_cell < 1 || ns->gaussians_per_cell > kMaxK)
+        return fail(c, DGS_ERR_INVALID_ARG, "gaussians_per_cell must be in 1..32");
+    if (dec->feature_dim < 1 || dec->feature_dim > kMaxFeature || dec->hidden_dim < 1 ||
+        dec->hidden_dim > kMaxHidden)
+        return fail(c, DGS_ERR_INVALID_ARG, "feature_dim and hidden_dim must be in 1..64");
+    if (ns->num_cells > 0 && (!ns->features || !ns->offsets || !dec->weights))
+        return fail(c, DGS_ERR_INVALID_ARG, "features, offsets and decoder weights must not be NULL");
+    const int64_t M = (int64_t)ns->num_cells * ns->gaussians_per_cell;
+    if (M > (int64_t)(1 << 30)) return fail(c, DGS_ERR_INVALID_ARG, "too many Gaussians");
+    hipSetDevice(c->device);
+    if (14 * M > c->cap_dec) {
+        hipError_t e = grow(c->dec, 14 * M, c->stream);
+        if (e != hipSuccess) {
+            c->cap_dec = 0;
+            return fail(c, DGS_ERR_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+        }
+        c->cap_dec = 14 * M;
+    }
+    dgs_scene s;
+    s.num_cells = ns->num_cells;
+    s.gaussians_per_cell = ns->gaussians_per_cell;
+    s.cell_pos = ns->cell_pos;
+    s.cell_scale = ns->cell_scale;
+    s.cell_rot = ns->cell_rot;
+    s.cell_v_sh = ns->cell_v_sh;
+    s.v_sh_degree = ns->v_sh_degree;
+    s.means = c->dec;
+    s.scales = c->dec + 3 * M;
+    s.rots = c->dec + 6 * M;
+    s.opacities = c->dec + 10 * M;
+    s.sh = c->dec + 11 * M;
+    s.sh_degree = -1;
+    const NeuralSrc nn{ns, dec};
+    dgs_status st = dgs_internal_render(c, &s, cam, opts, out, true, &nn);
+    if (st == DGS_OK) c->dec_gauss = M;
+    return st;
+}
+
+dgs_status dgs_read_decoded(dgs_ctx c, float* means, float* scales, float* rots, float* opacities, float* colors) {
+    if (!c) return DGS_ERR_INVALID_ARG;
+    if (c->last_mode < 0 || !c->last_neural) return fail(c, DGS_ERR_INVALID_ARG, "the last render was not neural");
+    hipSetDevice(c->device);
+    const int64_t M = c->dec_gauss;
+    float* dst[5] = {means, scales, rots, opacities, colors};
+    const int64_t off[5] = {0, 3 * M, 6 * M, 10 * M, 11 * M}, len[5] = {3 * M, 3 * M, 4 * M, M, 3 * M};
+    for (int i = 0; i < 5; i++)
+        if (dst[i] && len[i] > 0)
+            hipMemcpyAsync(dst[i], c->dec + off[i], sizeof(float) * (size_t)len[i], hipMemcpyDeviceToDevice,
+                           c->stream);
+    return launched(c);
+}
+
 }  // extern "C"
 
 // The frame pipeline.  With write_frame the frame's camera and options are
 // written to the context's device FrameK by the first kernel; without it the
 // caller has put them there (a captured graph replayed for a new camera).
 dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* cam, const dgs_render_opts* opts,
-                               const dgs_image* out, bool write_frame) {
+                               const dgs_image* out, bool write_frame, const NeuralSrc* nn) {
     if (!c) return DGS_ERR_INVALID_ARG;
     CamK k;
     OptK o;
@@ -348,7 +440,7 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     dgs_status st;
     if ((st = make_cam(c, cam, k)) != DGS_OK) return st;
     if ((st = make_opts(c, opts, o, mode)) != DGS_OK) return st;
-    if ((st = check_scene(c, s, mode)) != DGS_OK) return st;
+    if ((st = check_scene(c, s, mode, nn != nullptr)) != DGS_OK) return st;
     if (!out || !out->color) return fail(c, DGS_ERR_INVALID_ARG, "output color buffer is NULL");
     hipSetDevice(c->device);
     const int N = s->num_cells, K = s->gaussians_per_cell;
@@ -379,10 +471,12 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     if (cells) {
         launch_cell_preprocess(q, N, s->cell_pos, s->cell_scale, s->cell_rot, s->cell_v_sh, s->v_sh_degree,
                                c->frame, c->p_depth, c->p_rect, c->p_ntiles, c->cell_v);
+        if (nn) launch_decode(q, decode_args(c, *nn, c->p_ntiles));
         sm.mark(1);
         launch_gauss_project(q, M, K, s->means, s->scales, s->rots, s->opacities, s->sh, s->sh_degree, c->frame,
                              c->p_ntiles, c->recs, c->grect, nullptr, nullptr);
     } else {
+        if (nn) launch_decode(q, decode_args(c, *nn, nullptr));
         sm.mark(1);
         launch_gauss_project(q, M, K, s->means, s->scales, s->rots, s->opacities, s->sh, s->sh_degree, c->frame,
                              nullptr, c->recs, c->grect, c->p_depth, c->p_ntiles);
@@ -428,6 +522,7 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
         launch_composite_alpha(q, a);
     sm.mark(6);
     c->last_mode = mode;
+    c->last_neural = nn != nullptr;
     c->last_passes = sort_passes(bits);
     c->last_prims = P;
     c->last_gauss = M;
@@ -456,6 +551,7 @@ dgs_status dgs_render_backward(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
         !gr->d_cell_pos)
         return fail(c, DGS_ERR_INVALID_ARG, "gradient buffers must not be NULL (only d_mean2d is optional)");
     const int N = s->num_cells, K = s->gaussians_per_cell, M = N * K, tiles = k.TX * k.TY;
+    if (c->last_neural) return fail(c, DGS_ERR_UNSUPPORTED, "no backward for neural renders");
     if (c->last_mode != DGS_MODE_DUPLEX || c->last_prims != N || c->last_gauss != M || c->last_tiles != tiles)
         return fail(c, DGS_ERR_INVALID_ARG, "backward must follow a Duplex render of the same scene and camera");
     if (M == 0) return DGS_OK;

@@ -9,6 +9,8 @@ constexpr int kTile = 16;        // screen tile edge, pixels
 constexpr int kMaxK = 32;        // Gaussians per cell supported by the compositor
 constexpr int kBatchSlots = 256; // Gaussian records staged in LDS per batch
 constexpr int kXcds = 8;         // MI355X: 8 accelerator complex dies
+constexpr int kMaxFeature = 64;  // neural decode: latent feature size limit
+constexpr int kMaxHidden = 64;   // neural decode: hidden layer size limit
 
 // Compositor modes (the dgs_mode values).
 constexpr int kModeDuplex = 0;

@@ -30,6 +30,9 @@ struct dgs_ctx_s {
     uint64_t* sort_status = nullptr;
     size_t sort_status_cap = 0;
     dgs::FrameK* frame = nullptr;  // device copy of the current frame's camera and options
+    float* dec = nullptr;  // decoded Gaussians of a neural render: [14][M] (means, scales, rots, opacity, colour)
+    int64_t cap_dec = 0, dec_gauss = 0;
+    bool last_neural = false;
     float* g2d = nullptr;  // [9][M] backward screen-space gradients
     float* gv = nullptr;   // [N] backward dL/dv
     int64_t cap_g2d = 0, cap_gv = 0;
@@ -70,8 +73,15 @@ void dgs_internal_release(dgs_ctx c);
 // options and output pointers are written to ctx->frame by the first kernel;
 // without it the caller has put them there (a captured frame replayed for a
 // new camera).  Host-side validation is the same in both cases.
+// With nn set, the Gaussians of s are the ones the neural decode writes into
+// ctx->dec (sh_degree -1: colour given directly), decoded after cell
+// rasterization.
+struct NeuralSrc {
+    const dgs_neural_scene* scene;
+    const dgs_decoder* decoder;
+};
 dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* cam, const dgs_render_opts* opts,
-                               const dgs_image* out, bool write_frame);
+                               const dgs_image* out, bool write_frame, const NeuralSrc* nn = nullptr);
 
 // Validates camera, options and output and builds the frame record; *mode
 // receives the render mode.  c may be a host-only context (errors land in c->err).

@@ -7,6 +7,24 @@ namespace dgs {
 // Writes the frame's camera and options to device memory (graph-safe kernel).
 void launch_set_frame(hipStream_t st, const FrameK& f, FrameK* dst);
 
+// Neural decode of the cells' Gaussians into planar attribute arrays
+// (means [3][M], scales [3][M], raw quaternions [4][M], opacity [M], colour
+// [3][M]); cells with cell_ntiles[n] == 0 are skipped (cell_ntiles may be
+// null: decode every cell).  weights: the four decoders packed (opacity,
+// colour, scale ratio, quaternion), woff[d] = offset of decoder d.
+struct DecodeArgs {
+    int N, K, F, H;
+    const float *cell_pos, *cell_scale, *cell_rot;  // [3][N], [3][N], [4][N]
+    const float* features;                          // [F][N]
+    const float* offsets;                           // [3][M]
+    const float* weights;
+    int64_t woff[4];
+    const uint32_t* cell_ntiles;
+    const FrameK* fr;
+    float *means, *scales, *rots, *opac, *color;
+};
+void launch_decode(hipStream_t st, const DecodeArgs& a);
+
 void launch_cell_preprocess(hipStream_t st, int N, const float* pos, const float* scale, const float* rot,
                             const float* vsh, int vdeg, const FrameK* fr, uint32_t* depth_bits,
                             uint64_t* prect, uint32_t* ntiles, float* v);

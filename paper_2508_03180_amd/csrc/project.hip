@@ -250,9 +250,16 @@ __global__ __launch_bounds__(256) void k_gauss_project(
     float d[3];
     unit_dir(k, m0, m1, m2, d);
     int64_t cs = 3 * (int64_t)M;
-    float cr = 0.5f + sh_eval(sh_deg, d[0], d[1], d[2], sh + g, cs);
-    float cg = 0.5f + sh_eval(sh_deg, d[0], d[1], d[2], sh + M + g, cs);
-    float cb = 0.5f + sh_eval(sh_deg, d[0], d[1], d[2], sh + 2 * (int64_t)M + g, cs);
+    float cr, cg, cb;
+    if (sh_deg < 0) {  // decoded Gaussians: colour given directly, planar [3][M]
+        cr = sh[g];
+        cg = sh[M + g];
+        cb = sh[2 * (int64_t)M + g];
+    } else {
+        cr = 0.5f + sh_eval(sh_deg, d[0], d[1], d[2], sh + g, cs);
+        cg = 0.5f + sh_eval(sh_deg, d[0], d[1], d[2], sh + M + g, cs);
+        cb = 0.5f + sh_eval(sh_deg, d[0], d[1], d[2], sh + 2 * (int64_t)M + g, cs);
+    }
     e.r = fmaxf(cr, 0.0f);
     e.g = fmaxf(cg, 0.0f);
     e.b = fmaxf(cb, 0.0f);

@@ -72,6 +72,35 @@ class DeviceScene:
         return s
 
 
+class NeuralDeviceScene:
+    """Neural scene (cells + features + offsets) and its decoder weights in
+    device memory, planar."""
+
+    def __init__(self, tensors, N, K, v_sh_degree, F, H, weights):
+        self.t, self.N, self.K, self.v_sh_degree = tensors, N, K, v_sh_degree
+        self.F, self.H, self.weights = F, H, weights
+        self.M = N * K
+
+    @classmethod
+    def from_numpy(cls, scene, decoder, device="cuda"):
+        N, K = scene["cell_pos"].shape[0], int(scene["K"])
+        t = {k: _planar(scene[k], device) for k in ("cell_pos", "cell_scale", "cell_rot", "cell_v_sh", "features",
+                                                   "offsets")}
+        w = torch.tensor(np.asarray(decoder["weights"], np.float32).reshape(-1), device=device)
+        return cls(t, N, K, int(scene["v_sh_degree"]), int(decoder["F"]), int(decoder["H"]), w)
+
+    def struct(self):
+        s = capi.dgs_neural_scene()
+        s.num_cells, s.gaussians_per_cell = self.N, self.K
+        for k in ("cell_pos", "cell_scale", "cell_rot", "cell_v_sh", "features", "offsets"):
+            setattr(s, k, self.t[k].data_ptr() if self.t[k].numel() else None)
+        s.v_sh_degree = self.v_sh_degree
+        return s
+
+    def decoder_struct(self):
+        return capi.dgs_decoder(self.F, self.H, self.weights.data_ptr())
+
+
 def camera_struct(cam):
     c = capi.dgs_camera()
     V = np.asarray(cam["viewmat"], np.float32).reshape(-1)
@@ -197,6 +226,43 @@ class Renderer:
                 st = capi.dgs_sync(self.ctx)
             capi.check(st, self.ctx)
         return out
+
+    def render_neural(self, scene: NeuralDeviceScene, cam, out=None, check=True, **kw):
+        """Render a neural scene (decode of the visible cells, then the same
+        pipeline); with check=True synchronises and retries on key-capacity
+        overflow like render()."""
+        opts = opts_struct(**kw)
+        if out is None:
+            out = self.alloc_image(cam)
+
+        def go():
+            img = capi.dgs_image(out["color"].data_ptr(), out["D"].data_ptr() if "D" in out else None,
+                                 out["T"].data_ptr() if "T" in out else None,
+                                 out["last"].data_ptr() if "last" in out else None)
+            self.frame_id += 1
+            return capi.dgs_render_neural(self.ctx, scene.struct(), scene.decoder_struct(), camera_struct(cam), opts,
+                                          img)
+        capi.check(go(), self.ctx)
+        if check:
+            st = capi.dgs_sync(self.ctx)
+            if st == capi.DGS_ERR_CAPACITY:
+                self.reserve(int(capi.dgs_get_stats(self.ctx).num_keys * 1.25) + 4096)
+                capi.check(go(), self.ctx)
+                st = capi.dgs_sync(self.ctx)
+            capi.check(st, self.ctx)
+        return out
+
+    def read_decoded(self, M):
+        """Decoded Gaussians of the last neural render, row-major numpy-style
+        tensors: means [M,3], scales [M,3], rots [M,4], opacities [M], colours [M,3]."""
+        d = self.device
+        t = dict(means=torch.empty((3, M), device=d), scales=torch.empty((3, M), device=d),
+                 rots=torch.empty((4, M), device=d), opacities=torch.empty((M,), device=d),
+                 colors=torch.empty((3, M), device=d))
+        capi.dgs_read_decoded(self.ctx, t["means"].data_ptr(), t["scales"].data_ptr(), t["rots"].data_ptr(),
+                              t["opacities"].data_ptr(), t["colors"].data_ptr())
+        self.sync()
+        return {k: (v.t().contiguous() if v.dim() == 2 else v) for k, v in t.items()}
 
     def sync(self):
         return capi.dgs_sync(self.ctx)
