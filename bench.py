@@ -74,6 +74,7 @@ def parse():
     p.add_argument("--no-alpha", action="store_true")
     p.add_argument("--cpu-frames", type=int, default=4)
     p.add_argument("--bwd-steps", type=int, default=10)
+    p.add_argument("--no-neural", action="store_true")
     p.add_argument("--no-ablation", action="store_true")
     p.add_argument("--no-ksweep", action="store_true")
     p.add_argument("--ksweep-frames", type=int, default=20)
@@ -189,6 +190,45 @@ def ablation(r, ds, cams, timed_frames):
                      "rendered_per_pixel": round(nrend / len(cams[::6]) / (cams[0]["width"] * cams[0]["height"]), 3)}
     out["tau"] = ABLATION_TAU
     return out
+
+
+def neural(a, cams, steps):
+    """The neural variant of the mid scene (100,000 cells x 10, features 32,
+    hidden 32, random decoder weights): frames/s of the whole frame
+    including the decode of the visible cells, and the decode's share."""
+    import torch
+
+    from paper_2508_03180_amd import _capi as capi
+    from paper_2508_03180_amd import scenes
+    from paper_2508_03180_amd.renderer import NeuralDeviceScene, Renderer
+
+    s, d = scenes.make_neural_scene(1)
+    ns = NeuralDeviceScene.from_numpy(s, d, "cuda:0")
+    r = Renderer(0)
+    img = r.alloc_image(cams[0])
+    for c in cams[:10]:
+        r.render_neural(ns, c, out=img)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        r.render_neural(ns, cams[i % len(cams)], out=img, check=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert r.sync() == 0
+    capi.dgs_set_timing(r.ctx, 1)
+    for c in cams:
+        r.render_neural(ns, c, out=img, check=False)
+    ms, nfr = capi.dgs_get_timing(r.ctx)
+    capi.dgs_set_timing(r.ctx, 0)
+    st = {k: round(v / nfr, 4) for k, v in zip(capi.STAGE_NAMES, ms)}
+    r.close()
+    macs = 0
+    F, H, K = d["F"], d["H"], s["K"]
+    for a_ in (1, 3, 3, 4):
+        macs += (F + 4) * H + H * K * a_
+    return {"fps": round(steps / dt, 2), "feature_dim": F, "hidden_dim": H,
+            "decode_macs_per_cell": macs,
+            "stages_ms": st, "note": "stage cell_preprocess includes the decode of the visible cells"}
 
 
 KSWEEP = (1, 2, 5, 10, 20, 32)
@@ -456,6 +496,7 @@ def main():
     # against a target rendered from a perturbed copy of the scene
     bwd = differentiation(r, scene, cams[0], a.bwd_steps)
 
+    neu = None if a.no_neural else neural(a, cams, a.steps)
     abl = None if a.no_ablation else ablation(r, ds, cams, a.steps)
     ksw = None if a.no_ksweep else k_sweep(a)
     large = None if a.no_large else large_scene(a)
@@ -492,6 +533,7 @@ def main():
         "termination_ratio": round(1 - cnt["n_rendered"] / max(cnt["n_val"], 1), 4),
         "roofline": roof,
         "differentiation": bwd,
+        "neural": neu,
         "ablation": abl,
         "k_sweep": ksw,
         "large_scene": large,

@@ -6,11 +6,15 @@
 // cell frame, mu = x_n + R(Q_n)(O^pos * S_n), and scales eqs. nerual_scales
 // and scale_res, s = max(0, min(sigmoid(y_s), 1 - |O^pos|)) * S_n.
 //
-// Mapping: a workgroup of four wavefronts decodes 64 cells; wavefront w runs
-// decoder w with one cell per lane, so every lane reads the same weight at
-// the same time (scalar loads) and writes its decoder's attribute of the
-// cell's Gaussians straight to the planar outputs.  The opacity wavefront,
-// whose second layer is the smallest, also places the centres.
+// Mapping: one decoder per workgroup (blockIdx.y), one cell per thread, so
+// all lanes read the same weight at the same time and it comes through a
+// scalar load; each thread writes its decoder's attribute of the cell's
+// Gaussians straight to the planar outputs.  The opacity decoder, whose
+// second layer is the smallest, also places the centres.  F = H = 32 (the
+// neural-Gaussian default) has an exact-size kernel whose first layer runs
+// input-major over contiguous weight rows; other sizes use register
+// capacities of 36 x 32 or 68 x 64 with predicated loops (the largest
+// spills to scratch).
 //
 // The scales, quaternions and centres decide each Gaussian's pixel box, so
 // they are computed in binary32 in one fixed order: every sum is a chain of
@@ -21,8 +25,6 @@
 #include "launch.h"
 
 namespace dgs {
-
-constexpr int kDecCells = 64;
 
 // exp(x) in binary32: Cody-Waite reduction x = n ln2 + r with ln2 split so
 // that n * ln2_hi is exact, the degree-7 Taylor polynomial of e^r in Horner
@@ -69,8 +71,8 @@ __device__ inline void cell_rot32(float w, float x, float y, float z, float* R) 
 template <int CI, int CH>
 __global__ __launch_bounds__(256) void k_decode(DecodeArgs a) {
 #pragma clang fp contract(off)
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int n = blockIdx.x * kDecCells + lane;
+    const int wave = blockIdx.y;  // the decoder
+    const int n = blockIdx.x * 256 + threadIdx.x;
     const int N = a.N, K = a.K, F = a.F, H = a.H, I = a.F + 4;
     const bool live = n < N && (a.cell_ntiles == nullptr || a.cell_ntiles[n] != 0);
     if (!__any(live)) return;  // uniform per wavefront
@@ -163,13 +165,135 @@ __global__ __launch_bounds__(256) void k_decode(DecodeArgs a) {
     }
 }
 
+// Exact-size variant (F, H known at compile time): layer 1 runs input-major
+// (every weight row is one contiguous scalar load) and layer 2 reads, per
+// hidden unit, the A contiguous outputs of one member.  Each sum keeps the
+// order of the general kernel: bias first, then ascending index.
+struct DecodeOut {
+    float* __restrict__ means;
+    float* __restrict__ scales;
+    float* __restrict__ rots;
+    float* __restrict__ opac;
+    float* __restrict__ color;
+};
+
+template <int F, int H, int A>
+__device__ inline void decode_wave(const DecodeArgs& a, const float* __restrict__ w, const float (&x)[F + 4],
+                                   bool live, int n, float px, float py, float pz, int wave, const DecodeOut& out) {
+#pragma clang fp contract(off)
+    constexpr int I = F + 4;
+    const int K = a.K, N = a.N;
+    const int O = K * A;
+    const float* W1 = w;
+    const float* b1 = W1 + I * H;
+    const float* W2 = b1 + H;
+    const float* b2 = W2 + (int64_t)H * O;
+    float h[H];
+#pragma unroll
+    for (int j = 0; j < H; j++) h[j] = b1[j];
+#pragma unroll
+    for (int i = 0; i < I; i++) {
+        const float xi = x[i];
+#pragma unroll
+        for (int j = 0; j < H; j++) h[j] = fmaf(xi, W1[i * H + j], h[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < H; j++) h[j] = h[j] > 0.0f ? h[j] : 0.0f;
+    // every lane stays in the loop (uniform control flow keeps the weight
+    // loads scalar); only live lanes store
+    const int64_t M = (int64_t)N * K;
+    const int nn = live ? n : 0;
+    const float S[3] = {a.cell_scale[nn], a.cell_scale[N + nn], a.cell_scale[2 * N + nn]};
+    for (int kk = 0; kk < K; kk++) {
+        const int64_t g = (int64_t)n * K + kk;
+        float y[A];
+#pragma unroll
+        for (int c = 0; c < A; c++) y[c] = b2[kk * A + c];
+#pragma unroll
+        for (int j = 0; j < H; j++) {
+#pragma unroll
+            for (int c = 0; c < A; c++) y[c] = fmaf(h[j], W2[(int64_t)j * O + kk * A + c], y[c]);
+        }
+        if (!live) continue;
+        if (wave == 0) {
+            out.opac[g] = tanhf(y[0]);
+            float R[9];
+            cell_rot32(a.cell_rot[n], a.cell_rot[N + n], a.cell_rot[2 * N + n], a.cell_rot[3 * N + n], R);
+            const float u0 = a.offsets[g] * S[0], u1 = a.offsets[M + g] * S[1], u2 = a.offsets[2 * M + g] * S[2];
+            out.means[g] = px + ((R[0] * u0 + R[1] * u1) + R[2] * u2);
+            out.means[M + g] = py + ((R[3] * u0 + R[4] * u1) + R[5] * u2);
+            out.means[2 * M + g] = pz + ((R[6] * u0 + R[7] * u1) + R[8] * u2);
+        } else if (wave == 1) {
+#pragma unroll
+            for (int c = 0; c < A; c++) out.color[c * M + g] = 1.0f / (1.0f + __expf(-y[c]));
+        } else if (wave == 2) {
+            const float o0 = a.offsets[g], o1 = a.offsets[M + g], o2 = a.offsets[2 * M + g];
+            const float lim = 1.0f - sqrtf((o0 * o0 + o1 * o1) + o2 * o2);
+#pragma unroll
+            for (int c = 0; c < A; c++) {
+                float r = sigmoid32_def(y[c]);
+                r = r < lim ? r : lim;
+                r = r > 0.0f ? r : 0.0f;
+                out.scales[c * M + g] = r * S[c];
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < A; c++) out.rots[c * M + g] = y[c];
+        }
+    }
+}
+
+template <int F, int H>
+__global__ __launch_bounds__(256) void k_decode_exact(DecodeArgs a, const float* __restrict__ weights,
+                                                      float* __restrict__ means, float* __restrict__ scales,
+                                                      float* __restrict__ rots, float* __restrict__ opac,
+                                                      float* __restrict__ color) {
+#pragma clang fp contract(off)
+    // one decoder per workgroup (blockIdx.y), one cell per thread: the
+    // wavefronts of a compute unit mostly run the same code
+    const int wave = blockIdx.y;
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    const int N = a.N;
+    const bool live = n < N && (a.cell_ntiles == nullptr || a.cell_ntiles[n] != 0);
+    if (!__any(live)) return;  // uniform per wavefront
+    const CamK& k = a.fr->k;
+    float x[F + 4];
+    float px = 0.0f, py = 0.0f, pz = 0.0f, ex = 0.0f, ey = 0.0f, ez = 0.0f, dist = 1.0f;
+    if (live) {
+        px = a.cell_pos[n];
+        py = a.cell_pos[N + n];
+        pz = a.cell_pos[2 * N + n];
+        ex = px - k.o[0];
+        ey = py - k.o[1];
+        ez = pz - k.o[2];
+        dist = sqrtf((ex * ex + ey * ey) + ez * ez);
+    }
+#pragma unroll
+    for (int i = 0; i < F; i++) x[i] = live ? a.features[(int64_t)i * N + n] : 0.0f;
+    x[F] = dist;
+    x[F + 1] = ex / dist;
+    x[F + 2] = ey / dist;
+    x[F + 3] = ez / dist;
+    const DecodeOut out{means, scales, rots, opac, color};
+    const float* __restrict__ w = weights + a.woff[wave];
+    if (wave == 0)
+        decode_wave<F, H, 1>(a, w, x, live, n, px, py, pz, wave, out);
+    else if (wave == 3)
+        decode_wave<F, H, 4>(a, w, x, live, n, px, py, pz, wave, out);
+    else
+        decode_wave<F, H, 3>(a, w, x, live, n, px, py, pz, wave, out);
+}
+
 void launch_decode(hipStream_t st, const DecodeArgs& a) {
     if (a.N <= 0) return;
-    const unsigned grid = (unsigned)((a.N + kDecCells - 1) / kDecCells);
-    if (a.F <= 32 && a.H <= 32)
-        hipLaunchKernelGGL((k_decode<36, 32>), dim3(grid), dim3(256), 0, st, a);
+    const dim3 grid((unsigned)((a.N + 255) / 256), 4);
+    if (a.F == 32 && a.H == 32)
+        hipLaunchKernelGGL((k_decode_exact<32, 32>), grid, dim3(256), 0, st, a, a.weights, a.means, a.scales, a.rots,
+                           a.opac, a.color);
+    else if (a.F <= 32 && a.H <= 32)
+        hipLaunchKernelGGL((k_decode<36, 32>), grid, dim3(256), 0, st, a);
     else
-        hipLaunchKernelGGL((k_decode<kMaxFeature + 4, kMaxHidden>), dim3(grid), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_decode<kMaxFeature + 4, kMaxHidden>), grid, dim3(256), 0, st, a);
 }
 
 }  // namespace dgs
