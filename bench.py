@@ -88,19 +88,33 @@ def parse():
     return p.parse_args()
 
 
+def _gauss_blur(x, g):
+    """Separable 11-tap Gaussian blur of [C, H, W] with zero padding (the
+    same values as a 2D convolution with the outer-product kernel and
+    padding 5), as shifted weighted sums along each axis."""
+    import torch.nn.functional as F
+    H, W = x.shape[-2], x.shape[-1]
+    xp = F.pad(x, (5, 5, 0, 0))
+    y = g[0] * xp[..., 0:W]
+    for i in range(1, 11):
+        y = y + g[i] * xp[..., i:i + W]
+    yp = F.pad(y, (0, 0, 5, 5))
+    z = g[0] * yp[..., 0:H, :]
+    for i in range(1, 11):
+        z = z + g[i] * yp[..., i:i + H, :]
+    return z
+
+
 def ssim_loss(C, T):
     """1 - SSIM with an 11x11 Gaussian window (sigma 1.5), per channel."""
     import torch
-    import torch.nn.functional as F
-    g = torch.exp(-0.5 * ((torch.arange(11, device=C.device, dtype=C.dtype) - 5) / 1.5) ** 2)
-    g = g / g.sum()
-    w = (g[:, None] * g[None, :]).expand(3, 1, 11, 11).contiguous()
-    x, y = C[None], T[None]
-    mu_x = F.conv2d(x, w, padding=5, groups=3)
-    mu_y = F.conv2d(y, w, padding=5, groups=3)
-    sxx = F.conv2d(x * x, w, padding=5, groups=3) - mu_x ** 2
-    syy = F.conv2d(y * y, w, padding=5, groups=3) - mu_y ** 2
-    sxy = F.conv2d(x * y, w, padding=5, groups=3) - mu_x * mu_y
+    g = torch.exp(-0.5 * ((torch.arange(11, dtype=torch.float64) - 5) / 1.5) ** 2)
+    g = (g / g.sum()).tolist()
+    q = _gauss_blur(torch.cat([C, T, C * C, T * T, C * T], 0), g)
+    mu_x, mu_y, exx, eyy, exy = q.split(C.shape[0], 0)
+    sxx = exx - mu_x ** 2
+    syy = eyy - mu_y ** 2
+    sxy = exy - mu_x * mu_y
     c1, c2 = 0.01 ** 2, 0.03 ** 2
     ssim = ((2 * mu_x * mu_y + c1) * (2 * sxy + c2)) / ((mu_x ** 2 + mu_y ** 2 + c1) * (sxx + syy + c2))
     return 1 - ssim.mean()

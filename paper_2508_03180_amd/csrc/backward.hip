@@ -31,6 +31,30 @@ __device__ inline float wave_sum(float v) {
     return v;
 }
 
+// Sums eight per-lane values over the wavefront with a transposed butterfly
+// (each exchange step keeps half of the values and sends the other half, so
+// 4 + 2 + 1 + 3 shuffles instead of 8 x 6): every lane of group
+// g = lane >> 3 returns the wavefront total of value g.
+__device__ inline float wave_sum8(const float (&v)[8], int lane) {
+    const bool b5 = (lane & 32) != 0, b4 = (lane & 16) != 0, b3 = (lane & 8) != 0;
+    float w4[4], w2[2];
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const float keep = b5 ? v[4 + i] : v[i], send = b5 ? v[i] : v[4 + i];
+        w4[i] = keep + __shfl_xor(send, 32, 64);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; i++) {
+        const float keep = b4 ? w4[2 + i] : w4[i], send = b4 ? w4[i] : w4[2 + i];
+        w2[i] = keep + __shfl_xor(send, 16, 64);
+    }
+    float w = (b3 ? w2[1] : w2[0]) + __shfl_xor(b3 ? w2[0] : w2[1], 8, 64);
+    w += __shfl_xor(w, 4, 64);
+    w += __shfl_xor(w, 2, 64);
+    w += __shfl_xor(w, 1, 64);
+    return w;
+}
+
 struct BRec {
     float ox, oy, ca, cb, cc, lo;  // as stored: log2(sigma G') = lo + ca dx^2 + cb dx dy + cc dy^2
     float A, B, C, sigma, r, g, b;  // natural-domain conic and sigma, for the gradients
@@ -186,13 +210,14 @@ __device__ inline void duplex_strip_bwd(const BwdArgs& a, int tile, int s0, int 
                     }
                 }
                 if (__any(hit)) {
-                    const float s[9] = {gu0, gu1, gA, gB, gC, gs, gr, gg, gb};
+                    // quantities 0..7 in one transposed reduction, one atomic
+                    // instruction (lanes 0, 8, .., 56); quantity 8 apart
+                    const float s8[8] = {gu0, gu1, gA, gB, gC, gs, gr, gg};
                     const size_t gidx = (size_t)cell * K + kk;
-#pragma unroll
-                    for (int i = 0; i < 9; i++) {
-                        const float t = wave_sum(s[i]);
-                        if (lane == 0 && t != 0.0f) atomicAdd(&a.g2d[(size_t)i * a.M + gidx], t);
-                    }
+                    const float t = wave_sum8(s8, lane);
+                    if ((lane & 7) == 0 && t != 0.0f) atomicAdd(&a.g2d[(size_t)(lane >> 3) * a.M + gidx], t);
+                    const float tb = wave_sum(gb);
+                    if (lane == 0 && tb != 0.0f) atomicAdd(&a.g2d[(size_t)8 * a.M + gidx], tb);
                 }
             }
             const float dvs = wave_sum(dv);
