@@ -25,33 +25,53 @@ namespace dgs {
 constexpr int kBwdWaves = 4;
 constexpr float kLog2e = 1.4426950408889634f;
 
+// Cross-lane steps in registers (no LDS): DPP within 16-lane rows,
+// v_permlane16_swap / v_permlane32_swap across rows and halves.
+template <int CTRL>
+__device__ inline float dpp(float v) {
+    return __uint_as_float(__builtin_amdgcn_update_dpp(0u, __float_as_uint(v), CTRL, 0xf, 0xf, false));
+}
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141; // lane i <- 7 - i within each 8
+constexpr int kDppMirror = 0x140;     // lane i <- 15 - i within each row of 16
+
+// x, y -> (x with its upper 32 lanes replaced by y's lower 32,
+//          y with its lower 32 lanes replaced by x's upper 32); summed.
+__device__ inline float swap32_sum(float x, float y) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+// x, y -> (rows 0, 2 of x with rows 0, 2 of y, rows 1, 3 of x with rows 1, 3 of y); summed.
+__device__ inline float swap16_sum(float x, float y) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Wavefront total of v in every lane.
 __device__ inline float wave_sum(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp<kDppXor1>(v);
+    v += dpp<kDppXor2>(v);
+    v += dpp<kDppHalfMirror>(v);
+    v += dpp<kDppMirror>(v);       // every lane: its row's total
+    v = swap16_sum(v, v);          // rows 0+1 and 2+3
+    return swap32_sum(v, v);       // all four rows
 }
 
 // Sums eight per-lane values over the wavefront with a transposed butterfly
-// (each exchange step keeps half of the values and sends the other half, so
-// 4 + 2 + 1 + 3 shuffles instead of 8 x 6): every lane of group
-// g = lane >> 3 returns the wavefront total of value g.
+// (each exchange step keeps half of the values and trades the other half):
+// every lane of group g = lane >> 3 returns the wavefront total of value g.
 __device__ inline float wave_sum8(const float (&v)[8], int lane) {
-    const bool b5 = (lane & 32) != 0, b4 = (lane & 16) != 0, b3 = (lane & 8) != 0;
     float w4[4], w2[2];
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
-        const float keep = b5 ? v[4 + i] : v[i], send = b5 ? v[i] : v[4 + i];
-        w4[i] = keep + __shfl_xor(send, 32, 64);
-    }
+    for (int i = 0; i < 4; i++) w4[i] = swap32_sum(v[i], v[4 + i]);    // halves: values 0..3 / 4..7
 #pragma unroll
-    for (int i = 0; i < 2; i++) {
-        const float keep = b4 ? w4[2 + i] : w4[i], send = b4 ? w4[i] : w4[2 + i];
-        w2[i] = keep + __shfl_xor(send, 16, 64);
-    }
-    float w = (b3 ? w2[1] : w2[0]) + __shfl_xor(b3 ? w2[0] : w2[1], 8, 64);
-    w += __shfl_xor(w, 4, 64);
-    w += __shfl_xor(w, 2, 64);
-    w += __shfl_xor(w, 1, 64);
+    for (int i = 0; i < 2; i++) w2[i] = swap16_sum(w4[i], w4[2 + i]);  // row r: values 2r, 2r + 1
+    const bool b3 = (lane & 8) != 0;
+    float w = (b3 ? w2[1] : w2[0]) + dpp<kDppMirror>(b3 ? w2[0] : w2[1]);  // half h of row r: value 2r + h
+    w += dpp<kDppHalfMirror>(w);
+    w += dpp<kDppXor1>(w);
+    w += dpp<kDppXor2>(w);
     return w;
 }
 
@@ -91,40 +111,53 @@ __device__ inline BRec read_brec(const GRec* lds, int i) {
     return e;
 }
 
-// Backward of one 16x4 strip (one pixel per lane).
-__device__ inline void duplex_strip_bwd(const BwdArgs& a, int tile, int s0, int lane, GRec* lds) {
+// Backward of a whole 16x16 tile (NS = 4: lane l holds pixel (l & 15,
+// 4 j + (l >> 4)) of strip j) or of one 16x4 strip s0 (NS = 1), in the
+// forward compositor's layout and with its exact gate arithmetic.  Each
+// pixel walks back from its own last contributing entry; per member, the
+// lane first sums its pixels' contributions, then the wavefront reduces
+// them once for the tile.
+template <int NS>
+__device__ inline void duplex_tile_bwd(const BwdArgs& a, int tile, int s0, int lane, GRec* lds) {
     const CamK& k = a.k;
     const int tx0 = (tile % k.TX) * kTile, ty0 = (tile / k.TX) * kTile;
-    const int px = tx0 + (lane & 15), py = ty0 + 4 * s0 + (lane >> 4);
-    const bool valid = px < k.W && py < k.H;
+    const int px = tx0 + (lane & 15), py0 = ty0 + 4 * s0 + (lane >> 4);
     const uint32_t start = a.ranges[2 * tile], len = a.ranges[2 * tile + 1] - start;
     const int K = a.K;
     const int cpc = 64 / K;
     const uint32_t kmask = K == 32 ? 0xffffffffu : ((1u << K) - 1u);
     const float th = a.o.log2_alpha_min, amax = a.o.alpha_max;
+    const size_t HW = (size_t)k.W * k.H;
 
-    const size_t HW = (size_t)k.W * k.H, pi = valid ? (size_t)py * k.W + px : 0;
-    int32_t last = 0;
-    float gN0 = 0.f, gN1 = 0.f, gN2 = 0.f, gD = 0.f, T = 1.0f;
-    if (valid) {
-        last = min(a.last[pi], (int32_t)len);  // never walk past this tile's list
-        const float D = a.D[pi];
-        if (D > 0.0f && last > 0) {
-            const float invD = 1.0f / D;
-            const float g0 = a.grad_color[pi], g1 = a.grad_color[HW + pi], g2 = a.grad_color[2 * HW + pi];
-            gN0 = g0 * invD; gN1 = g1 * invD; gN2 = g2 * invD;
-            gD = -(g0 * a.color[pi] + g1 * a.color[HW + pi] + g2 * a.color[2 * HW + pi]) * invD;
-            if (a.grad_D) gD += a.grad_D[pi];
-            T = a.T[pi];
-        } else {
-            last = 0;
+    int32_t last[NS];
+    float gN0[NS], gN1[NS], gN2[NS], gD[NS], T[NS], R[NS];
+    int maxlast = 0;
+#pragma unroll
+    for (int j = 0; j < NS; j++) {
+        const int py = py0 + 4 * j;
+        last[j] = 0;
+        gN0[j] = gN1[j] = gN2[j] = gD[j] = 0.0f;
+        T[j] = 1.0f;
+        R[j] = 0.0f;  // dL/dT after the current cell
+        if (px < k.W && py < k.H) {
+            const size_t pi = (size_t)py * k.W + px;
+            const int32_t l = min(a.last[pi], (int32_t)len);  // never walk past this tile's list
+            const float D = a.D[pi];
+            if (D > 0.0f && l > 0) {
+                const float invD = 1.0f / D;
+                const float g0 = a.grad_color[pi], g1 = a.grad_color[HW + pi], g2 = a.grad_color[2 * HW + pi];
+                gN0[j] = g0 * invD; gN1[j] = g1 * invD; gN2[j] = g2 * invD;
+                gD[j] = -(g0 * a.color[pi] + g1 * a.color[HW + pi] + g2 * a.color[2 * HW + pi]) * invD;
+                if (a.grad_D) gD[j] += a.grad_D[pi];
+                T[j] = a.T[pi];
+                last[j] = l;
+            }
         }
+        maxlast = max(maxlast, last[j]);
     }
     // the wave walks from its largest `last` down to the first cell
-    int maxlast = last;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) maxlast = max(maxlast, __shfl_xor(maxlast, o, 64));
-    float R = 0.0f;  // dL/dT after the current cell
     for (int hi = maxlast; hi > 0;) {
         // chunk of cells [lo_c, hi) (list positions relative to start)
         const int nch = hi < cpc ? hi : cpc;
@@ -143,73 +176,116 @@ __device__ inline void duplex_strip_bwd(const BwdArgs& a, int tile, int s0, int 
             const int x0 = __float_as_int(r2.y), y0 = __float_as_int(r2.z);
             const uint32_t wxy = __float_as_uint(r2.w);
             const int x1 = x0 + (int)(wxy & 0xffffu), y1 = y0 + (int)(wxy >> 16);
-            const int sy0 = ty0 + 4 * s0;
-            sm = (x0 <= tx0 + 15 && x1 >= tx0 && y0 <= sy0 + 3 && y1 >= sy0) ? 1u : 0u;
+            if (x0 <= tx0 + 15 && x1 >= tx0) {
+#pragma unroll
+                for (int j = 0; j < NS; j++) {
+                    const int sy0 = ty0 + 4 * (s0 + j);
+                    if (y0 <= sy0 + 3 && y1 >= sy0) sm |= 1u << j;
+                }
+            }
         }
-        const uint64_t Bm = __ballot(sm);
+        uint64_t Bm[NS];
+#pragma unroll
+        for (int j = 0; j < NS; j++) Bm[j] = __ballot((sm >> j) & 1u);
         for (int c = nch - 1; c >= 0; c--) {
             const int base = c * K;
             const int p = lo_c + c;  // list position (0-based) of this cell
-            const uint32_t mm = (uint32_t)(Bm >> base) & kmask;
-            const bool act = p < last;
-            if (!mm || !__any(act)) continue;  // no member touches the strip / no lane reaches it
+            uint32_t mj[NS], mm = 0;
+            bool act[NS], anyact = false;
+#pragma unroll
+            for (int j = 0; j < NS; j++) {
+                mj[j] = (uint32_t)(Bm[j] >> base) & kmask;
+                mm |= mj[j];
+                act[j] = p < last[j];
+                anyact = anyact || act[j];
+            }
+            if (!mm || !__any(anyact)) continue;  // no member touches the owned rows / no pixel reaches the cell
             const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v_lane), base));
             const uint32_t cell = a.vals[start + p];
-            // pass 1: cell totals at this pixel (same decisions as the forward)
-            float A0 = 0.f, A1 = 0.f, A2 = 0.f, Bs = 0.f, P = 1.0f;
-            for (uint32_t rem = mm; rem; rem &= rem - 1) {
-                const BRec e = read_brec(lds, base + __builtin_ctz(rem));
-                const uint32_t rx = (uint32_t)(px - e.x0), ry = (uint32_t)(py - e.y0);
-                const float dx = (float)(int)rx + e.ox, dy = (float)(int)ry + e.oy;
-                const float pw = brec_power(e, dx, dy);
-                if (act && rx <= e.wx && ry <= e.wy && pw >= th) {
-                    const float al = fminf(amax, __builtin_amdgcn_exp2f(pw));
-                    A0 = fmaf(al, e.r, A0); A1 = fmaf(al, e.g, A1); A2 = fmaf(al, e.b, A2);
-                    Bs += al;
-                    P = fmaf(-P, v * al, P);
-                }
-            }
-            float dLdA0 = 0.f, dLdA1 = 0.f, dLdA2 = 0.f, dLdB = 0.f, dLdP = 0.f, dv = 0.f;
-            if (act) {
-                const float Tn = T / P;  // transmittance in front of this cell
-                const float w = v * Tn;
-                dLdA0 = w * gN0; dLdA1 = w * gN1; dLdA2 = w * gN2;
-                dLdB = w * gD;
-                const float dLdw = gN0 * A0 + gN1 * A1 + gN2 * A2 + gD * Bs;
-                dLdP = Tn * R;
-                dv = Tn * dLdw;
-                R = v * dLdw + P * R;
-                T = Tn;
-            }
-            // pass 2: per-member gradients, reduced over the wave
+            // pass 1: cell totals at each pixel (same decisions as the forward)
+            float A0[NS], A1[NS], A2[NS], Bs[NS], P[NS];
+#pragma unroll
+            for (int j = 0; j < NS; j++) { A0[j] = A1[j] = A2[j] = Bs[j] = 0.0f; P[j] = 1.0f; }
             for (uint32_t rem = mm; rem; rem &= rem - 1) {
                 const int kk = __builtin_ctz(rem);
                 const BRec e = read_brec(lds, base + kk);
-                const uint32_t rx = (uint32_t)(px - e.x0), ry = (uint32_t)(py - e.y0);
-                const float dx = (float)(int)rx + e.ox, dy = (float)(int)ry + e.oy;
-                const float pw = brec_power(e, dx, dy);
-                const bool hit = act && rx <= e.wx && ry <= e.wy && pw >= th;
-                float gu0 = 0.f, gu1 = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, gs = 0.f, gr = 0.f, gg = 0.f, gb = 0.f;
-                if (hit) {
-                    const float sg = __builtin_amdgcn_exp2f(pw);  // sigma G'
-                    const float al = fminf(amax, sg);
-                    const float om = 1.0f - v * al;
-                    dv -= dLdP * al * P / om;
-                    const float dLda = dLdA0 * e.r + dLdA1 * e.g + dLdA2 * e.b + dLdB - dLdP * v * P / om;
-                    gr = dLdA0 * al; gg = dLdA1 * al; gb = dLdA2 * al;
-                    if (sg < amax) {
-                        // alpha = sigma exp(p): dalpha/dp = alpha, dalpha/dsigma = alpha / sigma
-                        const float gp = dLda * al;
-                        gs = dLda * al / e.sigma;
-                        const float y0 = e.A * dx + e.B * dy, y1 = e.B * dx + e.C * dy;
-                        gu0 = gp * y0;  // p depends on the mean through dx = px + 0.5 - u
-                        gu1 = gp * y1;
-                        gA = -0.5f * gp * dx * dx;
-                        gB = -gp * dx * dy;
-                        gC = -0.5f * gp * dy * dy;
+                const uint32_t rx = (uint32_t)(px - e.x0);
+                const bool inx = rx <= e.wx;
+                const float dx = (float)(int)rx + e.ox;
+                const uint32_t ry0 = (uint32_t)(py0 - e.y0);
+#pragma unroll
+                for (int j = 0; j < NS; j++) {
+                    if (!((mj[j] >> kk) & 1u)) continue;
+                    const uint32_t ry = ry0 + 4u * j;
+                    const float dy = (float)(int)ry + e.oy;
+                    const float pw = brec_power(e, dx, dy);
+                    if (act[j] && inx && ry <= e.wy && pw >= th) {
+                        const float al = fminf(amax, __builtin_amdgcn_exp2f(pw));
+                        A0[j] = fmaf(al, e.r, A0[j]); A1[j] = fmaf(al, e.g, A1[j]); A2[j] = fmaf(al, e.b, A2[j]);
+                        Bs[j] += al;
+                        P[j] = fmaf(-P[j], v * al, P[j]);
                     }
                 }
-                if (__any(hit)) {
+            }
+            float dLdA0[NS], dLdA1[NS], dLdA2[NS], dLdB[NS], dLdP[NS];
+            float dv = 0.0f;
+#pragma unroll
+            for (int j = 0; j < NS; j++) {
+                dLdA0[j] = dLdA1[j] = dLdA2[j] = dLdB[j] = dLdP[j] = 0.0f;
+                if (act[j]) {
+                    // transmittance in front of this cell (gradients are continuous:
+                    // the hardware reciprocal, not a correctly rounded division)
+                    const float Tn = T[j] * __builtin_amdgcn_rcpf(P[j]);
+                    const float w = v * Tn;
+                    dLdA0[j] = w * gN0[j]; dLdA1[j] = w * gN1[j]; dLdA2[j] = w * gN2[j];
+                    dLdB[j] = w * gD[j];
+                    const float dLdw = gN0[j] * A0[j] + gN1[j] * A1[j] + gN2[j] * A2[j] + gD[j] * Bs[j];
+                    dLdP[j] = Tn * R[j];
+                    dv += Tn * dLdw;
+                    R[j] = v * dLdw + P[j] * R[j];
+                    T[j] = Tn;
+                }
+            }
+            // pass 2: per-member gradients, summed over the lane's pixels, then the wave
+            for (uint32_t rem = mm; rem; rem &= rem - 1) {
+                const int kk = __builtin_ctz(rem);
+                const BRec e = read_brec(lds, base + kk);
+                const uint32_t rx = (uint32_t)(px - e.x0);
+                const bool inx = rx <= e.wx;
+                const float dx = (float)(int)rx + e.ox;
+                const uint32_t ry0 = (uint32_t)(py0 - e.y0);
+                float gu0 = 0.f, gu1 = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, gs = 0.f, gr = 0.f, gg = 0.f, gb = 0.f;
+                bool anyhit = false;
+                const float inv_sigma = __builtin_amdgcn_rcpf(e.sigma);
+#pragma unroll
+                for (int j = 0; j < NS; j++) {
+                    if (!((mj[j] >> kk) & 1u)) continue;
+                    const uint32_t ry = ry0 + 4u * j;
+                    const float dy = (float)(int)ry + e.oy;
+                    const float pw = brec_power(e, dx, dy);
+                    if (act[j] && inx && ry <= e.wy && pw >= th) {
+                        anyhit = true;
+                        const float sg = __builtin_amdgcn_exp2f(pw);  // sigma G'
+                        const float al = fminf(amax, sg);
+                        const float om = 1.0f - v * al;
+                        const float Pom = dLdP[j] * P[j] * __builtin_amdgcn_rcpf(om);  // dL/dP * P / (1 - v al)
+                        dv -= Pom * al;
+                        const float dLda = dLdA0[j] * e.r + dLdA1[j] * e.g + dLdA2[j] * e.b + dLdB[j] - Pom * v;
+                        gr += dLdA0[j] * al; gg += dLdA1[j] * al; gb += dLdA2[j] * al;
+                        if (sg < amax) {
+                            // alpha = sigma exp(p): dalpha/dp = alpha, dalpha/dsigma = alpha / sigma
+                            const float gp = dLda * al;
+                            gs += gp * inv_sigma;
+                            const float y0 = e.A * dx + e.B * dy, y1 = e.B * dx + e.C * dy;
+                            gu0 += gp * y0;  // p depends on the mean through dx = px + 0.5 - u
+                            gu1 += gp * y1;
+                            gA += -0.5f * gp * dx * dx;
+                            gB += -gp * dx * dy;
+                            gC += -0.5f * gp * dy * dy;
+                        }
+                    }
+                }
+                if (__any(anyhit)) {
                     // quantities 0..7 in one transposed reduction, one atomic
                     // instruction (lanes 0, 8, .., 56); quantity 8 apart
                     const float s8[8] = {gu0, gu1, gA, gB, gC, gs, gr, gg};
@@ -240,7 +316,11 @@ __global__ __launch_bounds__(256) void k_composite_bwd(BwdArgs a) {
         t = (uint32_t)__shfl((int)t, 0, 64);
         if (t >= nitems) break;
         const uint32_t item = a.order[t];
-        duplex_strip_bwd(a, (int)(item >> 3), (int)(item & 3u), lane, lds);
+        const int tile = (int)(item >> 3), mode = (int)(item & 7u);
+        if (mode == 0)
+            duplex_tile_bwd<4>(a, tile, 0, lane, lds);
+        else
+            duplex_tile_bwd<1>(a, tile, mode - 4, lane, lds);
     }
 }
 

@@ -7,6 +7,7 @@ kernels can be scaled by what the same counters read for a copy whose bytes
 are known.
 
     python -m paper_2508_03180_amd.traffic --frames 6
+    python -m paper_2508_03180_amd.traffic --frames 4 --modes duplex --backward
 """
 from __future__ import annotations
 
@@ -19,6 +20,7 @@ def main(argv=None):
     p.add_argument("--frames", type=int, default=6)
     p.add_argument("--copy-mib", type=int, default=1024)
     p.add_argument("--modes", default="duplex,alpha")
+    p.add_argument("--backward", action="store_true", help="also run the Duplex backward after each frame")
     a = p.parse_args(argv)
     import torch
 
@@ -31,10 +33,14 @@ def main(argv=None):
     r = Renderer(0)
     ds = DeviceScene.from_numpy(scene, "cuda:0")
     out = r.alloc_image(cams[0])
+    g = torch.randn((3, 1080, 1920), device="cuda", generator=torch.Generator("cuda").manual_seed(0))
     for mode in a.modes.split(","):
         for i in range(a.frames):
-            r.render(ds, cams[(10 * i) % 60], out=out, mode=mode)
-        print(f"rendered {a.frames} {mode} frames", flush=True)
+            cam = cams[(10 * i) % 60]
+            r.render(ds, cam, out=out, mode=mode)
+            if a.backward and mode == "duplex":
+                r.render_backward(ds, cam, out, g)
+        print(f"rendered {a.frames} {mode} frames" + (" with backward" if a.backward else ""), flush=True)
     n = a.copy_mib * (1 << 20) // 4
     x = torch.ones(n, dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
