@@ -286,14 +286,17 @@ __device__ inline void duplex_tile_bwd(const BwdArgs& a, int tile, int s0, int l
                     }
                 }
                 if (__any(anyhit)) {
-                    // quantities 0..7 in one transposed reduction, one atomic
-                    // instruction (lanes 0, 8, .., 56); quantity 8 apart
+                    // quantities 0..7 by one transposed reduction (group q of
+                    // eight lanes holds quantity q), quantity 8 by a plain one;
+                    // one atomic instruction, nine lanes, one 64-byte row
                     const float s8[8] = {gu0, gu1, gA, gB, gC, gs, gr, gg};
-                    const size_t gidx = (size_t)cell * K + kk;
-                    const float t = wave_sum8(s8, lane);
-                    if ((lane & 7) == 0 && t != 0.0f) atomicAdd(&a.g2d[(size_t)(lane >> 3) * a.M + gidx], t);
+                    const float t8 = wave_sum8(s8, lane);
                     const float tb = wave_sum(gb);
-                    if (lane == 0 && tb != 0.0f) atomicAdd(&a.g2d[(size_t)8 * a.M + gidx], tb);
+                    const bool head = (lane & 7) == 0;
+                    const float t = head ? t8 : tb;
+                    const int q = head ? (lane >> 3) : 8;
+                    if ((head || lane == 1) && t != 0.0f)
+                        atomicAdd(&a.g2d[((size_t)cell * K + kk) * kG2dRow + q], t);
                 }
             }
             const float dvs = wave_sum(dv);
@@ -375,13 +378,12 @@ __global__ __launch_bounds__(256) void k_gauss_project_bwd(BwdArgs a, ProjBwdArg
     a.k = a.fr->k;
     a.o = a.fr->o;
     const int M = a.M;
-    float s9[9];
+    const float4* row = reinterpret_cast<const float4*>(a.g2d + (size_t)g * kG2dRow);
+    const float4 r0 = row[0], r1 = row[1];
+    const float s9[9] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w, a.g2d[(size_t)g * kG2dRow + 8]};
     bool any = false;
 #pragma unroll
-    for (int i = 0; i < 9; i++) {
-        s9[i] = a.g2d[(size_t)i * M + g];
-        any = any || s9[i] != 0.0f;
-    }
+    for (int i = 0; i < 9; i++) any = any || s9[i] != 0.0f;
     if (!any) return;
     const CamK& k = a.k;
     const float m0 = b.means[g], m1 = b.means[M + g], m2 = b.means[2 * M + g];

@@ -557,9 +557,9 @@ dgs_status dgs_render_backward(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     if (M == 0) return DGS_OK;
     hipSetDevice(c->device);
     hipError_t e = hipSuccess;
-    if (9 * (int64_t)M > c->cap_g2d) {
-        if ((e = grow(c->g2d, 9 * (int64_t)M, c->stream)) != hipSuccess) goto oom;
-        c->cap_g2d = 9 * (int64_t)M;
+    if (kG2dRow * (int64_t)M > c->cap_g2d) {
+        if ((e = grow(c->g2d, kG2dRow * (int64_t)M, c->stream)) != hipSuccess) goto oom;
+        c->cap_g2d = kG2dRow * (int64_t)M;
     }
     if (N > c->cap_gv) {
         if ((e = grow(c->gv, (int64_t)N, c->stream)) != hipSuccess) goto oom;
@@ -567,7 +567,7 @@ dgs_status dgs_render_backward(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     }
     {
         hipStream_t q = c->stream;
-        launch_fill_u32(q, (uint32_t*)c->g2d, 0u, 9 * (size_t)M);
+        launch_fill_u32(q, (uint32_t*)c->g2d, 0u, kG2dRow * (size_t)M);
         launch_fill_u32(q, (uint32_t*)c->gv, 0u, (size_t)N);
         launch_fill_u32(q, c->misc + 11, 0u, 2);
         launch_tile_order(q, c->ranges, tiles, kSplitLen, c->tile_order, c->misc + 11);

@@ -33,7 +33,7 @@ struct dgs_ctx_s {
     float* dec = nullptr;  // decoded Gaussians of a neural render: [14][M] (means, scales, rots, opacity, colour)
     int64_t cap_dec = 0, dec_gauss = 0;
     bool last_neural = false;
-    float* g2d = nullptr;  // [9][M] backward screen-space gradients
+    float* g2d = nullptr;  // [M][kG2dRow] backward screen-space gradients
     float* gv = nullptr;   // [N] backward dL/dv
     int64_t cap_g2d = 0, cap_gv = 0;
     uint32_t* hist = nullptr;     // [8][256]

@@ -119,8 +119,11 @@ void launch_composite_alpha(hipStream_t st, const CompositeArgs& a);
 void launch_composite_lcwsr(hipStream_t st, const CompositeArgs& a);
 
 // Backward of the Duplex compositor: per-Gaussian screen-space gradients
-// g2d[9][M] (mean x, y, conic A, B, C, sigma, r, g, b) and per-cell dL/dv,
-// both accumulated atomically (zero them first).
+// g2d[M][kG2dRow] (row g: mean x, y, conic A, B, C, sigma, r, g, b, then
+// padding) and per-cell dL/dv, both accumulated atomically (zero them
+// first).  A row fills one 64-byte line, so one member's nine atomics are one
+// request.
+constexpr int kG2dRow = 16;
 struct BwdArgs {
     const uint32_t* ranges;
     const uint32_t* vals;
