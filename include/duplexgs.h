@@ -264,9 +264,10 @@ dgs_status dgs_read_decoded(dgs_ctx ctx, float* means, float* scales, float* rot
 /* Stage timing.  While enabled, every render records HIP events on the
  * context stream at the boundaries of its stages:
  *   0 cell preprocess (or nothing in alpha mode), 1 Gaussian projection,
- *   2 scan + key emission, 3 radix sort, 4 tile ranges + compositor work
- *   queue, 5 the compositor kernel alone. */
-#define DGS_NUM_STAGES 6
+ *   2 depth sort of the primitives, 3 scan + key emission, 4 radix sort of
+ *   the keys on their tile bits, 5 tile ranges + compositor work queue,
+ *   6 the compositor kernel alone. */
+#define DGS_NUM_STAGES 7
 dgs_status dgs_set_timing(dgs_ctx ctx, int32_t enable);
 
 /* Synchronises; writes the summed milliseconds of each stage over the renders

@@ -48,9 +48,15 @@ dgs_status ensure(dgs_ctx c, int64_t prims, int64_t gauss, int64_t keys, int64_t
         if ((e = grow(c->p_offsets, nc.prims, c->stream)) != hipSuccess) goto oom;
         if ((e = grow(c->p_rect, nc.prims, c->stream)) != hipSuccess) goto oom;
         if ((e = grow(c->cell_v, nc.prims, c->stream)) != hipSuccess) goto oom;
+        if ((e = grow(c->pk0, nc.prims, c->stream)) != hipSuccess) goto oom;
+        if ((e = grow(c->pk1, nc.prims, c->stream)) != hipSuccess) goto oom;
+        if ((e = grow(c->pv0, nc.prims, c->stream)) != hipSuccess) goto oom;
+        if ((e = grow(c->pv1, nc.prims, c->stream)) != hipSuccess) goto oom;
         size_t sw = scan_status_words(nc.prims);
         if ((e = grow_zeroed(c->scan_status, (int64_t)sw, c->stream)) != hipSuccess) goto oom;
         c->scan_status_cap = sw;
+        if ((e = grow_zeroed(c->psort_status, (int64_t)sort_status_words(nc.prims), c->stream)) != hipSuccess)
+            goto oom;
         c->cap_prims = nc.prims;
     }
     if (nc.gauss != cur.gauss) {
@@ -245,7 +251,8 @@ WorkspaceCaps dgs_internal_plan(const WorkspaceCaps& cur, const WorkspaceCaps& w
 
 int64_t dgs_internal_bytes(const WorkspaceCaps& c) {
     int64_t b = 0;
-    if (c.prims > 0) b += c.prims * (3 * 4 + 8 + 4) + (int64_t)scan_status_words(c.prims) * 8;
+    if (c.prims > 0)
+        b += c.prims * (3 * 4 + 8 + 4 + 4 * 4) + (int64_t)(scan_status_words(c.prims) + sort_status_words(c.prims)) * 8;
     if (c.gauss > 0) b += c.gauss * ((int64_t)sizeof(GRec) + 8);
     if (c.keys > 0) b += c.keys * (2 * 8 + 2 * 4) + (int64_t)sort_status_words(c.keys) * 8;
     if (c.tiles > 0) b += c.tiles * (2 + 4) * 4;
@@ -260,7 +267,8 @@ void dgs_internal_release(dgs_ctx c) {
     void** bufs[] = {(void**)&c->p_depth, (void**)&c->p_ntiles, (void**)&c->p_offsets, (void**)&c->p_rect,
                      (void**)&c->cell_v, (void**)&c->recs, (void**)&c->grect, (void**)&c->keys0,
                      (void**)&c->keys1, (void**)&c->vals0, (void**)&c->vals1, (void**)&c->ranges,
-                     (void**)&c->tile_order, (void**)&c->scan_status, (void**)&c->sort_status};
+                     (void**)&c->tile_order, (void**)&c->scan_status, (void**)&c->sort_status,
+                     (void**)&c->pk0, (void**)&c->pk1, (void**)&c->pv0, (void**)&c->pv1, (void**)&c->psort_status};
     for (void** p : bufs) {
         if (*p) hipFree(*p);
         *p = nullptr;
@@ -483,18 +491,26 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     }
     sm.mark(2);
     const uint64_t* prect = cells ? c->p_rect : c->grect;
-    launch_exclusive_scan(q, c->p_ntiles, c->p_offsets, P, c->misc + 0, c->scan_status, c->misc + 13, c->misc + 1,
-                          c->dev_err);
-    const int bits = 32 + tile_bits(tiles);
-    launch_emit_keys(q, P, c->p_ntiles, c->p_offsets, prect, c->p_depth, k.TX, cap, c->keys0, c->vals0, c->hist,
-                     sort_passes(bits), c->dev_err);
+    // depth order of the primitives (ties by id), then key offsets over that order
+    launch_prim_keys(q, P, c->p_ntiles, c->p_depth, c->pk0, c->pv0, c->hist);
+    const SortScratch ps{c->hist, c->psort_status, c->misc + 2};
+    const bool pin1 = launch_radix_sort32(q, c->pk0, c->pv0, c->pk1, c->pv1, (uint32_t)P, ps, c->misc + 13, 1,
+                                          c->dev_err);
+    const uint32_t* order = pin1 ? c->pv1 : c->pv0;
     sm.mark(3);
-    SortScratch ss{c->hist, c->sort_status, c->misc + 2};
-    const bool in1 = launch_radix_sort(q, c->keys0, c->vals0, c->keys1, c->vals1, c->misc + 0, cap, bits, ss,
-                                       c->misc + 13, c->dev_err, true);
+    launch_exclusive_scan(q, c->p_ntiles, c->p_offsets, P, c->misc + 0, c->scan_status, c->misc + 13, c->misc + 1,
+                          c->dev_err, order);
+    const int tbits = tile_bits(tiles);
+    launch_emit_keys(q, P, order, c->p_ntiles, c->p_offsets, prect, c->p_depth, k.TX, cap, c->keys0, c->vals0,
+                     c->hist + 4 * 256, sort_passes(tbits), c->dev_err);
+    sm.mark(4);
+    // stable sort on the tile bits
+    const SortScratch ss{c->hist + 4 * 256, c->sort_status, c->misc + 6};
+    const bool in1 = launch_radix_sort(q, c->keys0, c->vals0, c->keys1, c->vals1, c->misc + 0, cap, tbits, ss,
+                                       c->misc + 13, c->dev_err, true, 32, 5);
     const uint64_t* skeys = in1 ? c->keys1 : c->keys0;
     const uint32_t* svals = in1 ? c->vals1 : c->vals0;
-    sm.mark(4);
+    sm.mark(5);
     launch_tile_ranges(q, skeys, c->misc + 0, cap, c->ranges);
     CompositeArgs a;
     a.ranges = c->ranges;
@@ -513,17 +529,17 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     a.order = c->tile_order;
     a.queue = c->misc + 11;
     launch_tile_order(q, c->ranges, tiles, kSplitLen, c->tile_order, c->misc + 11);
-    sm.mark(5);
+    sm.mark(6);
     if (mode == DGS_MODE_DUPLEX)
         launch_composite_duplex(q, a);
     else if (mode == DGS_MODE_LCWSR)
         launch_composite_lcwsr(q, a);
     else
         launch_composite_alpha(q, a);
-    sm.mark(6);
+    sm.mark(7);
     c->last_mode = mode;
     c->last_neural = nn != nullptr;
-    c->last_passes = sort_passes(bits);
+    c->last_passes = (P > 0 ? sort_passes(32) : 0) + sort_passes(tbits);
     c->last_prims = P;
     c->last_gauss = M;
     c->last_tiles = tiles;

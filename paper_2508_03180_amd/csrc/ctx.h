@@ -18,6 +18,8 @@ struct dgs_ctx_s {
     uint64_t generation = 0;  // bumped whenever a workspace buffer moves (captured graphs go stale)
     uint32_t *p_depth = nullptr, *p_ntiles = nullptr, *p_offsets = nullptr;
     uint64_t* p_rect = nullptr;
+    uint32_t *pk0 = nullptr, *pk1 = nullptr, *pv0 = nullptr, *pv1 = nullptr;  // depth sort of the primitives
+    uint64_t* psort_status = nullptr;
     float* cell_v = nullptr;
     dgs::GRec* recs = nullptr;
     uint64_t* grect = nullptr;
@@ -36,8 +38,9 @@ struct dgs_ctx_s {
     float* g2d = nullptr;  // [M][kG2dRow] backward screen-space gradients
     float* gv = nullptr;   // [N] backward dL/dv
     int64_t cap_g2d = 0, cap_gv = 0;
-    uint32_t* hist = nullptr;     // [8][256]
-    uint32_t* misc = nullptr;     // [0] key total, [1] scan ticket, [2..9] sort tickets, [10] sort count,
+    uint32_t* hist = nullptr;     // [8][256]: [0..3] primitive depth bytes, [4..6] key tile bytes
+    uint32_t* misc = nullptr;     // [0] key total, [1] scan ticket, [2..5] depth sort tickets,
+                                  // [6..8] tile sort tickets, [9] spare, [10] sort count,
                                   // [11..12] compositor work-queue head and item count,
                                   // [13] look-back frame counter
     int* dev_err = nullptr;

@@ -34,12 +34,14 @@ void launch_gauss_project(hipStream_t st, int M, int K, const float* means, cons
                           const uint32_t* cell_ntiles, GRec* recs, uint64_t* grect, uint32_t* gdepth,
                           uint32_t* gntiles);
 
-// Exclusive scan of n u32 values; *total receives the sum.  status needs
-// scan_status_words(n) 64-bit words; *ticket must be zero; *epoch is the
-// device frame counter (look-back tag j = 0).
+// Exclusive scan of n u32 values (in[i], or in[idx[i]] when idx is set);
+// *total receives the sum.  status needs scan_status_words(n) 64-bit words;
+// *ticket must be zero; *epoch is the device frame counter (look-back tag
+// j = 0).
 size_t scan_status_words(int64_t n);
 void launch_exclusive_scan(hipStream_t st, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
-                           uint64_t* status, const uint32_t* epoch, uint32_t* ticket, int* err);
+                           uint64_t* status, const uint32_t* epoch, uint32_t* ticket, int* err,
+                           const uint32_t* idx = nullptr);
 
 void launch_fill_u32(hipStream_t st, uint32_t* p, uint32_t v, size_t n);
 
@@ -59,36 +61,50 @@ struct ClearList {
 // With f set, also writes *f to fdst (the frame record) in the same launch.
 void launch_clear(hipStream_t st, const ClearList& l, const FrameK* f = nullptr, FrameK* fdst = nullptr);
 
-// One key per (primitive, touched tile): key = tile << 32 | depth bits,
-// value = primitive id, written at offsets[p] in row-major tile order.
-// Also accumulates the radix sort's digit histogram of the kept keys into
-// hist ([passes][256], zeroed beforehand).
-void launch_emit_keys(hipStream_t st, int P, const uint32_t* ntiles, const uint32_t* offsets,
-                      const uint64_t* prect, const uint32_t* depth, int TX, uint32_t cap, uint64_t* keys,
-                      uint32_t* vals, uint32_t* hist, int passes, int* err);
+// Depth sort keys of the primitives: key p = depth bits of p when it touches
+// a tile, else all ones (it then sorts last and emits nothing); value = p.
+// Also accumulates the four byte histograms of the keys into hist
+// ([4][256], zeroed beforehand).
+void launch_prim_keys(hipStream_t st, int P, const uint32_t* ntiles, const uint32_t* depth, uint32_t* keys,
+                      uint32_t* vals, uint32_t* hist);
+
+// One key per (primitive, touched tile), the primitives taken in depth
+// order (order[i], i < P): key = tile << 32 | depth bits, value = primitive
+// id, written at offsets[i] in row-major tile order.  A stable sort of these
+// keys on the tile bits alone then yields the (tile, depth, id) order.  Also
+// accumulates the digit histograms of the kept keys' tile bytes into hist
+// ([tile_passes][256], zeroed beforehand).
+void launch_emit_keys(hipStream_t st, int P, const uint32_t* order, const uint32_t* ntiles,
+                      const uint32_t* offsets, const uint64_t* prect, const uint32_t* depth, int TX, uint32_t cap,
+                      uint64_t* keys, uint32_t* vals, uint32_t* hist, int tile_passes, int* err);
 
 // [start, end) per tile of the sorted keys; ranges (2 words per tile) must
 // be zero beforehand (tiles without keys keep [0, 0)).
 void launch_tile_ranges(hipStream_t st, const uint64_t* keys, const uint32_t* n_ptr, uint32_t cap,
                         uint32_t* ranges);
 
-// Onesweep LSD radix sort of (u64 key, u32 value) pairs on the low `bits`
-// bits.  The count is read on the device from *n_ptr (clamped to cap).
-// Returns true when the sorted data ends in (k1, v1), false for (k0, v0).
-// hist (8 x 256 words) and tickets (8 words) must be zero beforehand; with
-// hist_ready, hist already holds the digit counts of the keys (the key
-// emission counts them).  Pass p tags its look-back words with
-// epoch_tag(*epoch, 1 + p).
+// Onesweep LSD radix sort of (u64 key, u32 value) pairs on key bits
+// [first_bit, first_bit + bits).  The count is read on the device from
+// *n_ptr (clamped to cap).  Returns true when the sorted data ends in
+// (k1, v1), false for (k0, v0).  hist (8 x 256 words) and tickets (8 words)
+// must be zero beforehand; with hist_ready, hist already holds the digit
+// counts of the keys (the key emission counts them).  Pass p tags its
+// look-back words with epoch_tag(*epoch, tag0 + p).
 struct SortScratch {
-    uint32_t* hist;     // [8][256]
+    uint32_t* hist;     // [passes][256]
     uint64_t* status;   // sort_status_words(cap) look-back words
-    uint32_t* tickets;  // [8]
+    uint32_t* tickets;  // [passes]
 };
 int sort_passes(int bits);
 size_t sort_status_words(int64_t cap);
 bool launch_radix_sort(hipStream_t st, uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1,
                        const uint32_t* n_ptr, uint32_t cap, int bits, const SortScratch& s,
-                       const uint32_t* epoch, int* err, bool hist_ready = false);
+                       const uint32_t* epoch, int* err, bool hist_ready = false, int first_bit = 0,
+                       uint32_t tag0 = 1);
+// The same for n (host count) u32 keys on all 32 bits; hist must hold the
+// keys' four byte histograms.  Returns true when the data ends in (k1, v1).
+bool launch_radix_sort32(hipStream_t st, uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t n,
+                         const SortScratch& s, const uint32_t* epoch, uint32_t tag0, int* err);
 
 struct CompositeArgs {
     const uint32_t* ranges;

@@ -1,8 +1,9 @@
 // Single-pass exclusive prefix sum with decoupled look-back, plus the key
-// emission and tile-range kernels of cell rasterization (Sec. IV-B): the
-// offsets of every primitive's keys come from a scan over all primitives in
-// id order, so the emitted sequence (and the ties of the stable sort) are
-// deterministic.
+// emission and tile-range kernels of cell rasterization (Sec. IV-B).  The
+// primitives are first sorted by depth (ties by id); the offsets of their
+// keys come from a scan over that order, so the emitted sequence is already
+// in (depth, id) order within every tile and a stable sort on the tile bits
+// alone completes the (tile, depth) order.
 #include <string.h>
 
 #include "common.h"
@@ -41,7 +42,8 @@ __device__ inline uint32_t wave_incl_scan(uint32_t v) {
 __global__ __launch_bounds__(kScanThreads) void k_scan_excl(const uint32_t* __restrict__ in,
                                                              uint32_t* __restrict__ out, int64_t n,
                                                              uint32_t* __restrict__ total, uint64_t* status,
-                                                             const uint32_t* ep, uint32_t* ticket, int* err) {
+                                                             const uint32_t* ep, uint32_t* ticket, int* err,
+                                                             const uint32_t* __restrict__ idx) {
     __shared__ uint32_t s_part, s_wsum[kScanThreads / 64], s_excl;
     const uint32_t epoch = epoch_tag(*ep, 0);
     const int nparts = (int)((n + kScanPart - 1) / kScanPart);
@@ -55,7 +57,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_excl(const uint32_t* __re
         uint32_t x[kScanItems], sum = 0;
 #pragma unroll
         for (int i = 0; i < kScanItems; i++) {
-            x[i] = (base + i < n) ? in[base + i] : 0u;
+            uint32_t j = (uint32_t)(base + i);
+            if (idx && base + i < n) j = idx[base + i];  // a permutation of [0, n)
+            x[i] = (base + i < n && j < (uint64_t)n) ? in[j] : 0u;
             sum += x[i];
         }
         uint32_t incl = wave_incl_scan(sum);
@@ -119,7 +123,8 @@ void launch_fill_u32(hipStream_t st, uint32_t* p, uint32_t v, size_t n) {
 size_t scan_status_words(int64_t n) { return (size_t)((n + kScanPart - 1) / kScanPart) + 1; }
 
 void launch_exclusive_scan(hipStream_t st, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
-                           uint64_t* status, const uint32_t* epoch, uint32_t* ticket, int* err) {
+                           uint64_t* status, const uint32_t* epoch, uint32_t* ticket, int* err,
+                           const uint32_t* idx) {
     if (n <= 0) {
         launch_fill_u32(st, total, 0u, 1);
         return;
@@ -127,7 +132,7 @@ void launch_exclusive_scan(hipStream_t st, const uint32_t* in, uint32_t* out, in
     const size_t nparts = (size_t)((n + kScanPart - 1) / kScanPart);
     const unsigned grid = (unsigned)(nparts < 1024 ? nparts : 1024);
     hipLaunchKernelGGL(k_scan_excl, dim3(grid), dim3(kScanThreads), 0, st, in, out, n, total, status,
-                       epoch, ticket, err);
+                       epoch, ticket, err, idx);
 }
 
 __global__ void k_clear(ClearList l, FrameK f, FrameK* fdst) {
@@ -157,41 +162,68 @@ void launch_clear(hipStream_t st, const ClearList& l, const FrameK* f, FrameK* f
 
 // ---------------------------------------------------------------- keys
 
-// Key emission, fused with the digit histogram of the radix sort that
-// follows (hist[p][d]: keys whose byte p is d; `passes` bytes).  The depth
-// bytes are the same for every key of a primitive, so they are counted once
-// per primitive.  Along one row of a primitive's tile rectangle the tile ids
-// are consecutive: the low tile byte then covers a run of bins, counted with
-// a difference array (a +1 / -1 pair per run, prefix-summed at the end), and
-// each higher tile byte changes at most a few times, counted once per run.
-// Only keys below the capacity are counted (they are the ones sorted).
-__global__ __launch_bounds__(256) void k_emit_keys(int P, const uint32_t* __restrict__ ntiles,
+// Depth keys of the primitives with their four byte histograms (per
+// workgroup in LDS, added to the global ones once).
+__global__ __launch_bounds__(256) void k_prim_keys(int P, const uint32_t* __restrict__ ntiles,
+                                                   const uint32_t* __restrict__ depth, uint32_t* __restrict__ keys,
+                                                   uint32_t* __restrict__ vals, uint32_t* __restrict__ hist) {
+    __shared__ uint32_t sh[4][256];
+    for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x) (&sh[0][0])[i] = 0u;
+    __syncthreads();
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
+        const uint32_t k = ntiles[p] ? depth[p] : 0xffffffffu;
+        keys[p] = k;
+        vals[p] = (uint32_t)p;
+#pragma unroll
+        for (int b = 0; b < 4; b++) atomicAdd(&sh[b][(k >> (8 * b)) & 255u], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x) {
+        const uint32_t c = (&sh[0][0])[i];
+        if (c) atomicAdd(&hist[i], c);
+    }
+}
+
+void launch_prim_keys(hipStream_t st, int P, const uint32_t* ntiles, const uint32_t* depth, uint32_t* keys,
+                      uint32_t* vals, uint32_t* hist) {
+    if (P <= 0) return;
+    const int blocks = (P + 255) / 256 < kEmitBlocks ? (P + 255) / 256 : kEmitBlocks;
+    hipLaunchKernelGGL(k_prim_keys, dim3(blocks), dim3(256), 0, st, P, ntiles, depth, keys, vals, hist);
+}
+
+// Key emission in depth order, fused with the digit histograms of the tile
+// bytes (hist[b][d]: kept keys whose tile byte b is d).  Along one row of a
+// primitive's tile rectangle the tile ids are consecutive: the low tile byte
+// then covers a run of bins, counted with a difference array (a +1 / -1 pair
+// per run, prefix-summed at the end), and each higher tile byte changes at
+// most a few times, counted once per run.  Only keys below the capacity are
+// counted (they are the ones sorted).
+__global__ __launch_bounds__(256) void k_emit_keys(int P, const uint32_t* __restrict__ order,
+                                                   const uint32_t* __restrict__ ntiles,
                                                    const uint32_t* __restrict__ offsets,
                                                    const uint64_t* __restrict__ prect,
                                                    const uint32_t* __restrict__ depth, int TX, uint32_t cap,
                                                    uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
                                                    uint32_t* __restrict__ hist, int passes, int* err) {
-    __shared__ uint32_t sh[8][256];
+    __shared__ uint32_t sh[3][256];  // tile bytes 1, 2 (byte 0 below)
     __shared__ int32_t s_diff[257];  // low tile byte: difference array over the bins
     __shared__ uint32_t s_all;       // low tile byte: runs of 256 or more add to every bin
     __shared__ uint32_t s_wsum[4];
-    for (int i = threadIdx.x; i < 8 * 256; i += blockDim.x) (&sh[0][0])[i] = 0u;
+    for (int i = threadIdx.x; i < 3 * 256; i += blockDim.x) (&sh[0][0])[i] = 0u;
     for (int i = threadIdx.x; i < 257; i += blockDim.x) s_diff[i] = 0;
     if (threadIdx.x == 0) s_all = 0u;
     __syncthreads();
-    // grid-stride over primitives: a capped grid, so each workgroup adds its
-    // histogram to the global one once
-    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
+    // grid-stride over the depth order: a capped grid, so each workgroup adds
+    // its histogram to the global one once
+    for (int i0 = blockIdx.x * blockDim.x + threadIdx.x; i0 < P; i0 += gridDim.x * blockDim.x) {
+        const uint32_t p = order[i0];
+        if (p >= (uint32_t)P) continue;  // a permutation of [0, P) unless a sort wait timed out
         const uint32_t nt = ntiles[p];
         if (nt) {
-            const uint32_t off = offsets[p];
+            const uint32_t off = offsets[i0];
             if ((uint64_t)off + nt > cap) atomicOr(err, 1 << kErrCapacity);
-            const uint32_t nkept = off >= cap ? 0u : (cap - off < nt ? cap - off : nt);
             const uint64_t r = prect[p];
             const uint32_t d = depth[p];
-            const int dp = passes < 4 ? passes : 4;
-            if (nkept)
-                for (int b = 0; b < dp; b++) atomicAdd(&sh[b][(d >> (8 * b)) & 255u], nkept);
             const int tx0 = rect_x0(r) / kTile, tx1 = rect_x1(r) / kTile;
             const int ty0 = rect_y0(r) / kTile, ty1 = rect_y1(r) / kTile;
             uint32_t i = off;
@@ -202,9 +234,9 @@ __global__ __launch_bounds__(256) void k_emit_keys(int P, const uint32_t* __rest
                 const uint32_t kept = cap - i < len ? cap - i : len;
                 for (uint32_t j = 0; j < kept; j++) {
                     keys[i + j] = ((uint64_t)(t0 + j) << 32) | d;
-                    vals[i + j] = (uint32_t)p;
+                    vals[i + j] = p;
                 }
-                if (passes > 4 && kept) {
+                if (kept) {
                     if (kept >= 256u) atomicAdd(&s_all, kept >> 8);
                     const uint32_t rem = kept & 255u, a = t0 & 255u;
                     if (rem) {
@@ -219,12 +251,12 @@ __global__ __launch_bounds__(256) void k_emit_keys(int P, const uint32_t* __rest
                     }
                 }
                 // higher tile bytes change rarely along a row: one count per run
-                for (int b = 5; b < passes; b++) {
-                    const int sh8 = 8 * (b - 4);
+                for (int b = 1; b < passes; b++) {
+                    const int sh8 = 8 * b;
                     for (uint32_t t = t0, te = t0 + kept; t < te;) {
                         const uint32_t run_end = ((t >> sh8) + 1u) << sh8;
                         const uint32_t stop = run_end < te ? run_end : te;
-                        atomicAdd(&sh[b][(t >> sh8) & 255u], stop - t);
+                        atomicAdd(&sh[b - 1][(t >> sh8) & 255u], stop - t);
                         t = stop;
                     }
                 }
@@ -233,7 +265,7 @@ __global__ __launch_bounds__(256) void k_emit_keys(int P, const uint32_t* __rest
         }
     }
     __syncthreads();
-    if (passes > 4) {
+    {
         // low tile byte: inclusive prefix sum of the difference array
         const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
         int32_t x = s_diff[tid];
@@ -245,23 +277,23 @@ __global__ __launch_bounds__(256) void k_emit_keys(int P, const uint32_t* __rest
         if (lane == 63) s_wsum[wave] = (uint32_t)x;
         __syncthreads();
         for (int w = 0; w < wave; w++) x += (int32_t)s_wsum[w];
-        sh[4][tid] = (uint32_t)x + s_all;
-        __syncthreads();
+        const uint32_t c = (uint32_t)x + s_all;
+        if (c) atomicAdd(&hist[tid], c);
     }
-    for (int b = 0; b < passes; b++)
+    for (int b = 1; b < passes; b++)
         for (int i = threadIdx.x; i < 256; i += blockDim.x) {
-            const uint32_t c = sh[b][i];
+            const uint32_t c = sh[b - 1][i];
             if (c) atomicAdd(&hist[b * 256 + i], c);
         }
 }
 
-void launch_emit_keys(hipStream_t st, int P, const uint32_t* ntiles, const uint32_t* offsets,
-                      const uint64_t* prect, const uint32_t* depth, int TX, uint32_t cap, uint64_t* keys,
-                      uint32_t* vals, uint32_t* hist, int passes, int* err) {
+void launch_emit_keys(hipStream_t st, int P, const uint32_t* order, const uint32_t* ntiles,
+                      const uint32_t* offsets, const uint64_t* prect, const uint32_t* depth, int TX, uint32_t cap,
+                      uint64_t* keys, uint32_t* vals, uint32_t* hist, int tile_passes, int* err) {
     if (P <= 0) return;
     const int blocks = (P + 255) / 256 < kEmitBlocks ? (P + 255) / 256 : kEmitBlocks;
-    hipLaunchKernelGGL(k_emit_keys, dim3(blocks), dim3(256), 0, st, P, ntiles, offsets, prect, depth, TX,
-                       cap, keys, vals, hist, passes, err);
+    hipLaunchKernelGGL(k_emit_keys, dim3(blocks), dim3(256), 0, st, P, order, ntiles, offsets, prect, depth, TX,
+                       cap, keys, vals, hist, tile_passes, err);
 }
 
 __global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t* __restrict__ keys,

@@ -1,4 +1,5 @@
-// Onesweep LSD radix sort of (u64 key, u32 value) pairs, 8-bit digits.
+// Onesweep LSD radix sort of (key, u32 value) pairs, 8-bit digits, for u32
+// and u64 keys and any run of digits [first_bit, first_bit + bits).
 //
 // One histogram sweep counts the digits of every pass; each pass is then a
 // single read and a single write of the data.  Within a pass, persistent
@@ -95,14 +96,16 @@ __device__ inline bool look_back(const uint64_t* status, size_t stride, int part
     return true;
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __restrict__ kin,
+// n_ptr (device) holds the item count, or is null for n = cap.
+template <class KeyT>
+__global__ __launch_bounds__(kSortThreads) void k_onesweep(const KeyT* __restrict__ kin,
                                                            const uint32_t* __restrict__ vin,
-                                                           uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                           KeyT* __restrict__ kout, uint32_t* __restrict__ vout,
                                                            const uint32_t* __restrict__ n_ptr, uint32_t cap,
                                                            int shift, const uint32_t* __restrict__ dcount,
                                                            uint64_t* status, const uint32_t* ep, uint32_t pass_tag,
                                                            uint32_t* ticket, int* err) {
-    __shared__ uint64_t s_key[kSortPart];
+    __shared__ KeyT s_key[kSortPart];
     __shared__ uint32_t s_val[kSortPart];
     __shared__ uint32_t s_cnt[kSortWaves][256];  // per-wave digit counts, then per-wave offsets
     __shared__ uint32_t s_lstart[256];            // start of each digit in the partition-local order
@@ -112,7 +115,7 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
     __shared__ uint32_t s_goff[256];  // global start of each digit: exclusive scan of the digit counts
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t epoch = epoch_tag(*ep, pass_tag);
-    uint32_t n = *n_ptr;
+    uint32_t n = n_ptr ? *n_ptr : cap;
     if (n > cap) n = cap;
     const uint32_t nparts = (n + kSortPart - 1) / kSortPart;
     {
@@ -138,7 +141,7 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
         if (part >= nparts) break;
         const uint32_t pbase = part * kSortPart;
         const uint32_t wbase = pbase + wave * (kSortItems * 64);
-        uint64_t k[kSortItems];
+        KeyT k[kSortItems];
         uint32_t v[kSortItems], rank[kSortItems];
 #pragma unroll
         for (int i = 0; i < kSortItems; i++) {
@@ -213,7 +216,7 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
         __syncthreads();
         const uint32_t cnt = n - pbase < (uint32_t)kSortPart ? n - pbase : (uint32_t)kSortPart;
         for (uint32_t i = tid; i < cnt; i += kSortThreads) {
-            const uint64_t kk = s_key[i];
+            const KeyT kk = s_key[i];
             const uint32_t pos = s_gbase[(uint32_t)(kk >> shift) & 255u] + i;
             if (pos < n) {  // always true unless a look-back wait timed out
                 kout[pos] = kk;
@@ -225,25 +228,40 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
     }
 }
 
+template <class KeyT>
+static bool radix_sort(hipStream_t st, KeyT* k0, uint32_t* v0, KeyT* k1, uint32_t* v1, const uint32_t* n_ptr,
+                       uint32_t cap, int first_bit, int bits, const SortScratch& s, const uint32_t* epoch,
+                       uint32_t tag0, int* err) {
+    const int passes = sort_passes(bits);
+    const size_t parts = max_parts(cap);
+    const unsigned grid = (unsigned)(parts < 1024 ? parts : 1024);
+    KeyT *ki = k0, *ko = k1;
+    uint32_t *vi = v0, *vo = v1;
+    for (int p = 0; p < passes; p++) {
+        hipLaunchKernelGGL(k_onesweep<KeyT>, dim3(grid), dim3(kSortThreads), 0, st, ki, vi, ko, vo, n_ptr, cap,
+                           first_bit + 8 * p, s.hist + p * 256, s.status, epoch, tag0 + (uint32_t)p, s.tickets + p,
+                           err);
+        KeyT* tk = ki; ki = ko; ko = tk;
+        uint32_t* tv = vi; vi = vo; vo = tv;
+    }
+    return (passes & 1) != 0;
+}
+
 bool launch_radix_sort(hipStream_t st, uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1,
                        const uint32_t* n_ptr, uint32_t cap, int bits, const SortScratch& s,
-                       const uint32_t* epoch, int* err, bool hist_ready) {
+                       const uint32_t* epoch, int* err, bool hist_ready, int first_bit, uint32_t tag0) {
     const int passes = sort_passes(bits);
     if (passes <= 0 || cap == 0) return false;
     if (!hist_ready)
         hipLaunchKernelGGL(k_radix_hist, dim3(kHistBlocks), dim3(kSortThreads), 0, st, k0, n_ptr, cap, passes,
                            s.hist);
-    const size_t parts = max_parts(cap);
-    const unsigned grid = (unsigned)(parts < 1024 ? parts : 1024);
-    uint64_t *ki = k0, *ko = k1;
-    uint32_t *vi = v0, *vo = v1;
-    for (int p = 0; p < passes; p++) {
-        hipLaunchKernelGGL(k_onesweep, dim3(grid), dim3(kSortThreads), 0, st, ki, vi, ko, vo, n_ptr, cap, 8 * p,
-                           s.hist + p * 256, s.status, epoch, (uint32_t)(1 + p), s.tickets + p, err);
-        uint64_t* tk = ki; ki = ko; ko = tk;
-        uint32_t* tv = vi; vi = vo; vo = tv;
-    }
-    return (passes & 1) != 0;
+    return radix_sort(st, k0, v0, k1, v1, n_ptr, cap, first_bit, bits, s, epoch, tag0, err);
+}
+
+bool launch_radix_sort32(hipStream_t st, uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t n,
+                         const SortScratch& s, const uint32_t* epoch, uint32_t tag0, int* err) {
+    if (n == 0) return false;
+    return radix_sort(st, k0, v0, k1, v1, nullptr, n, 0, 32, s, epoch, tag0, err);
 }
 
 }  // namespace dgs
