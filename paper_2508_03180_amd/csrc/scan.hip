@@ -14,7 +14,18 @@ namespace dgs {
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanPart = kScanThreads * kScanItems;
-constexpr int kEmitBlocks = 512;
+// Histogram-producing kernels run capped grids (grid-stride), each
+// workgroup adding its LDS histogram to the global one once: every global
+// bin then takes at most kHistBlocks atomics.  The key emission is bound by
+// its stores, so it keeps one primitive per thread up to the cap.
+constexpr int kHistBlocks = 512;
+constexpr int kPrimKeysPerBlock = 1024;
+constexpr int kEmitPrimsPerBlock = 256;
+
+static int hist_grid(int n, int per_block) {
+    const int b = (n + per_block - 1) / per_block;
+    return b < 1 ? 1 : (b > kHistBlocks ? kHistBlocks : b);
+}
 constexpr int kSpinLimit = 1 << 22;
 
 // status word: epoch << 34 | flag << 32 | value; flag 1 = partition total,
@@ -187,8 +198,7 @@ __global__ __launch_bounds__(256) void k_prim_keys(int P, const uint32_t* __rest
 void launch_prim_keys(hipStream_t st, int P, const uint32_t* ntiles, const uint32_t* depth, uint32_t* keys,
                       uint32_t* vals, uint32_t* hist) {
     if (P <= 0) return;
-    const int blocks = (P + 255) / 256 < kEmitBlocks ? (P + 255) / 256 : kEmitBlocks;
-    hipLaunchKernelGGL(k_prim_keys, dim3(blocks), dim3(256), 0, st, P, ntiles, depth, keys, vals, hist);
+    hipLaunchKernelGGL(k_prim_keys, dim3(hist_grid(P, kPrimKeysPerBlock)), dim3(256), 0, st, P, ntiles, depth, keys, vals, hist);
 }
 
 // Key emission in depth order, fused with the digit histograms of the tile
@@ -291,8 +301,7 @@ void launch_emit_keys(hipStream_t st, int P, const uint32_t* order, const uint32
                       const uint32_t* offsets, const uint64_t* prect, const uint32_t* depth, int TX, uint32_t cap,
                       uint64_t* keys, uint32_t* vals, uint32_t* hist, int tile_passes, int* err) {
     if (P <= 0) return;
-    const int blocks = (P + 255) / 256 < kEmitBlocks ? (P + 255) / 256 : kEmitBlocks;
-    hipLaunchKernelGGL(k_emit_keys, dim3(blocks), dim3(256), 0, st, P, order, ntiles, offsets, prect, depth, TX,
+    hipLaunchKernelGGL(k_emit_keys, dim3(hist_grid(P, kEmitPrimsPerBlock)), dim3(256), 0, st, P, order, ntiles, offsets, prect, depth, TX,
                        cap, keys, vals, hist, tile_passes, err);
 }
 

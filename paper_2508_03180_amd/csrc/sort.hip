@@ -18,8 +18,8 @@ namespace dgs {
 
 constexpr int kSortThreads = 256;
 constexpr int kSortWaves = kSortThreads / 64;
-constexpr int kSortItems = 16;
-constexpr int kSortPart = kSortThreads * kSortItems;  // 4096 keys per partition
+constexpr int kMinSortItems = 4;
+constexpr int kMinSortPart = kSortThreads * kMinSortItems;  // smallest partition: 1024 keys
 static_assert(kSortThreads == 256, "one thread per digit");
 constexpr int kHistBlocks = 128;
 constexpr int kSortSpinLimit = 1 << 22;
@@ -27,9 +27,13 @@ constexpr int kLookWindow = 4;
 
 int sort_passes(int bits) { return (bits + 7) / 8; }
 
-static size_t max_parts(int64_t cap) { return (size_t)((cap + kSortPart - 1) / kSortPart); }
+static size_t max_parts(int64_t cap, int part = kMinSortPart) { return (size_t)((cap + part - 1) / part); }
 
 size_t sort_status_words(int64_t cap) { return max_parts(cap) * 256; }
+
+// Keys per thread: partitions of 4096 keys, or of 1024 for sorts of fewer
+// than 2^19 keys, which would otherwise occupy only a few dozen CUs.
+static int sort_items(int64_t cap) { return cap >= ((int64_t)1 << 19) ? 16 : 4; }
 
 __global__ __launch_bounds__(256) void k_radix_hist(const uint64_t* __restrict__ keys,
                                                     const uint32_t* __restrict__ n_ptr, uint32_t cap, int passes,
@@ -97,7 +101,7 @@ __device__ inline bool look_back(const uint64_t* status, size_t stride, int part
 }
 
 // n_ptr (device) holds the item count, or is null for n = cap.
-template <class KeyT>
+template <class KeyT, int kSortItems>
 __global__ __launch_bounds__(kSortThreads) void k_onesweep(const KeyT* __restrict__ kin,
                                                            const uint32_t* __restrict__ vin,
                                                            KeyT* __restrict__ kout, uint32_t* __restrict__ vout,
@@ -105,6 +109,7 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const KeyT* __restric
                                                            int shift, const uint32_t* __restrict__ dcount,
                                                            uint64_t* status, const uint32_t* ep, uint32_t pass_tag,
                                                            uint32_t* ticket, int* err) {
+    constexpr int kSortPart = kSortThreads * kSortItems;
     __shared__ KeyT s_key[kSortPart];
     __shared__ uint32_t s_val[kSortPart];
     __shared__ uint32_t s_cnt[kSortWaves][256];  // per-wave digit counts, then per-wave offsets
@@ -228,21 +233,31 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const KeyT* __restric
     }
 }
 
+template <class KeyT, int ITEMS>
+static void sort_passes_launch(hipStream_t st, KeyT* k0, uint32_t* v0, KeyT* k1, uint32_t* v1,
+                               const uint32_t* n_ptr, uint32_t cap, int first_bit, int passes, const SortScratch& s,
+                               const uint32_t* epoch, uint32_t tag0, int* err) {
+    const size_t parts = max_parts(cap, kSortThreads * ITEMS);
+    const unsigned grid = (unsigned)(parts < 1024 ? parts : 1024);
+    KeyT *ki = k0, *ko = k1;
+    uint32_t *vi = v0, *vo = v1;
+    for (int p = 0; p < passes; p++) {
+        hipLaunchKernelGGL((k_onesweep<KeyT, ITEMS>), dim3(grid), dim3(kSortThreads), 0, st, ki, vi, ko, vo, n_ptr,
+                           cap, first_bit + 8 * p, s.hist + p * 256, s.status, epoch, tag0 + (uint32_t)p,
+                           s.tickets + p, err);
+        KeyT* tk = ki; ki = ko; ko = tk;
+        uint32_t* tv = vi; vi = vo; vo = tv;
+    }
+}
+
 template <class KeyT>
 static bool radix_sort(hipStream_t st, KeyT* k0, uint32_t* v0, KeyT* k1, uint32_t* v1, const uint32_t* n_ptr,
                        uint32_t cap, int first_bit, int bits, const SortScratch& s, const uint32_t* epoch,
                        uint32_t tag0, int* err) {
     const int passes = sort_passes(bits);
-    const size_t parts = max_parts(cap);
-    const unsigned grid = (unsigned)(parts < 1024 ? parts : 1024);
-    KeyT *ki = k0, *ko = k1;
-    uint32_t *vi = v0, *vo = v1;
-    for (int p = 0; p < passes; p++) {
-        hipLaunchKernelGGL(k_onesweep<KeyT>, dim3(grid), dim3(kSortThreads), 0, st, ki, vi, ko, vo, n_ptr, cap,
-                           first_bit + 8 * p, s.hist + p * 256, s.status, epoch, tag0 + (uint32_t)p, s.tickets + p,
-                           err);
-        KeyT* tk = ki; ki = ko; ko = tk;
-        uint32_t* tv = vi; vi = vo; vo = tv;
+    switch (sort_items(cap)) {
+        case 16: sort_passes_launch<KeyT, 16>(st, k0, v0, k1, v1, n_ptr, cap, first_bit, passes, s, epoch, tag0, err); break;
+        default: sort_passes_launch<KeyT, 4>(st, k0, v0, k1, v1, n_ptr, cap, first_bit, passes, s, epoch, tag0, err);
     }
     return (passes & 1) != 0;
 }

@@ -151,6 +151,48 @@ def test_gaussian_keys_bit_exact_alpha_mode(R):
     np.testing.assert_array_equal(ranges.cpu().numpy(), oranges)
 
 
+def _tie_scene():
+    """Cells and Gaussians on three planes of constant camera depth (an
+    axis-aligned camera makes their depth bits equal), the last third of
+    the cells exact copies of the first third in reverse order: the sorted
+    lists must break every depth tie by ascending id."""
+    s = scenes.make_tiny_scene(3, n_cells=3000)
+    rng = np.random.default_rng(3)
+    N = s["cell_pos"].shape[0]
+    s["cell_pos"][:, 2] = rng.choice(np.float32([-0.5, 0.0, 0.5]), N)
+    s["means"][:, 2] = rng.choice(np.float32([-0.25, 0.25]), s["means"].shape[0])
+    d = N // 3
+    for k in ("cell_pos", "cell_scale", "cell_rot", "cell_v_sh"):
+        s[k][N - d:] = s[k][:d][::-1]
+    view = np.eye(4, dtype=np.float32)
+    view[2, 3] = 3.0
+    return s, scenes.pinhole(view, 256, 256)
+
+
+def _count_ties(keys):
+    k = keys.cpu().numpy().view(np.uint64)
+    return int((k[1:] == k[:-1]).sum())
+
+
+def test_sorted_lists_break_depth_ties_by_id(R):
+    s, cam = _tie_scene()
+    n = _check_discrete(R, s, cam)
+    keys, _, _ = R.read_lists(256)
+    assert n > 1000 and _count_ties(keys) > 1000
+
+
+def test_sorted_gaussian_lists_break_depth_ties_by_id(R):
+    s, cam = _tie_scene()
+    ds = upload(s)
+    R.render(ds, cam, mode="alpha")
+    gd = oracle.gauss_discrete(s, cam)
+    keys, vals, ranges = R.read_lists(256)
+    ids, _, oranges = oracle.build_lists(gd["visible"], gd["depth_bits"], gd["rect"], 256, 256)
+    np.testing.assert_array_equal(vals.cpu().numpy(), ids)
+    np.testing.assert_array_equal(ranges.cpu().numpy(), oranges)
+    assert _count_ties(keys) > 1000
+
+
 # ------------------------------------------------------------------ images
 
 def test_tiny_scene_image_parity(R):
