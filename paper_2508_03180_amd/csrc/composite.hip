@@ -105,9 +105,18 @@ struct RecView {
     uint32_t wx, wy;
 };
 
-__device__ inline RecView read_rec(const GRec* lds, int i) {
-    const float4* p = reinterpret_cast<const float4*>(lds + i);
-    const float4 a = p[0], b = p[1], c = p[2];
+typedef float F4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) const F4 LdsF4;
+
+// The wavefront's record array as a 32-bit LDS address, held in a scalar
+// register: every lane reads the same record, so its address is uniform.
+__device__ inline uint32_t lds_base(const GRec* lds) {
+    return __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(const LdsF4*)lds);
+}
+
+__device__ inline RecView read_rec(uint32_t lb, int i) {
+    const LdsF4* p = (const LdsF4*)(uintptr_t)(lb + (uint32_t)i * (uint32_t)sizeof(GRec));
+    const F4 a = p[0], b = p[1], c = p[2];
     RecView e;
     e.ox = a.x; e.oy = a.y; e.ca = a.z; e.cb = a.w;
     e.cc = b.x; e.lo = b.y; e.r = b.z; e.g = b.w;
@@ -171,6 +180,7 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
     const int cpc = 64 / K;  // cells per chunk
     const uint32_t kmask = K == 32 ? 0xffffffffu : ((1u << K) - 1u);
     const float eps = f.eps, th = f.th, amax = f.amax;
+    const uint32_t lb = lds_base(lds);
 
     float T[NS], N0[NS], N1[NS], N2[NS], D[NS];
     int32_t last[NS];
@@ -221,27 +231,30 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
             for (int j = 0; j < NS; j++) { A0[j] = A1[j] = A2[j] = Bs[j] = 0.0f; P[j] = 1.0f; }
             for (uint32_t rem = any; rem; rem &= rem - 1) {
                 const int k = __builtin_ctz(rem);
-                const RecView e = read_rec(lds, base + k);
+                const RecView e = read_rec(lb, base + k);
                 const uint32_t rx = (uint32_t)(px - e.x0);
                 const bool inx = rx <= e.wx;
                 const float dx = (float)(int)rx + e.ox;
-                const float t0 = fmaf(e.ca * dx, dx, e.lo);
+                // outside the box's columns the power is -inf: the alpha_min
+                // test then rejects the pixel as the box test would
+                const float t0 = inx ? fmaf(e.ca * dx, dx, e.lo) : -INFINITY;
                 const float t1 = e.cb * dx;
                 const uint32_t ry0 = (uint32_t)(py0 - e.y0);
+                // every strip is evaluated (strips the member misses fail the
+                // row test in every lane): no scalar test per strip
 #pragma unroll
                 for (int j = 0; j < NS; j++) {
-                    if (!((mj[j] >> k) & 1u)) continue;  // scalar: member misses strip j
                     const uint32_t ry = ry0 + 4u * j;
                     const float dy = (float)(int)ry + e.oy;
                     const float pw = fmaf(dy, fmaf(e.cc, dy, t1), t0);
-                    const bool inbox = inx && ry <= e.wy;
-                    const bool hit = inbox && pw >= th;
+                    const bool iny = ry <= e.wy;
+                    const bool hit = iny & (pw >= th);
                     if (STATS) {
                         cn.val += hit;
                         cn.rend += hit && act[j];
-                        cn.box += inbox && act[j];
+                        cn.box += inx && iny && act[j];
                     }
-                    if (hit && act[j]) {
+                    if (hit & act[j]) {
                         const float al = fminf(amax, __builtin_amdgcn_exp2f(pw));
                         A0[j] = fmaf(al, e.r, A0[j]);
                         A1[j] = fmaf(al, e.g, A1[j]);
@@ -306,6 +319,7 @@ __device__ inline void alpha_tile(const CompositeArgs& a, const FrameView& f, in
         T[j] = 1.0f; C0[j] = C1[j] = C2[j] = 0.0f; last[j] = 0;
         act[j] = px < f.W && py0 + 4 * j < f.H;
     }
+    const uint32_t lb = lds_base(lds);
     Chunk q;
     if (start < end) load_chunk(a, start, (int)min(64u, end - start), 1, lane, false, q);
     bool alive = true;
@@ -333,27 +347,28 @@ __device__ inline void alpha_tile(const CompositeArgs& a, const FrameView& f, in
                     break;
                 }
             }
-            const RecView e = read_rec(lds, m);
+            const RecView e = read_rec(lb, m);
             const uint32_t rx = (uint32_t)(px - e.x0);
             const bool inx = rx <= e.wx;
             const float dx = (float)(int)rx + e.ox;
-            const float t0 = fmaf(e.ca * dx, dx, e.lo);
+            const float t0 = inx ? fmaf(e.ca * dx, dx, e.lo) : -INFINITY;  // as in the Duplex walk
             const float t1 = e.cb * dx;
             const uint32_t ry0 = (uint32_t)(py0 - e.y0);
 #pragma unroll
             for (int j = 0; j < NS; j++) {
-                if (!((B[j] >> m) & 1ull)) continue;
-                act[j] = act[j] && !(T[j] < eps);  // termination before each Gaussian
+                // termination before each Gaussian (T only changes on a hit,
+                // so testing it for strips the Gaussian misses changes nothing)
+                act[j] = act[j] && !(T[j] < eps);
                 const uint32_t ry = ry0 + 4u * j;
                 const float dy = (float)(int)ry + e.oy;
                 const float pw = fmaf(dy, fmaf(e.cc, dy, t1), t0);
-                const bool inbox = inx && ry <= e.wy;
-                const bool hit = inbox && pw >= th;
+                const bool iny = ry <= e.wy;
+                const bool hit = iny & (pw >= th);
                 if (STATS) {
                     cn.val += hit;
-                    cn.box += inbox && act[j];
+                    cn.box += inx && iny && act[j];
                 }
-                if (hit && act[j]) {
+                if (hit & act[j]) {
                     const float al = fminf(amax, __builtin_amdgcn_exp2f(pw));
                     const float w = al * T[j];
                     C0[j] = fmaf(w, e.r, C0[j]);
