@@ -183,12 +183,14 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
     const uint32_t lb = lds_base(lds);
 
     float T[NS], N0[NS], N1[NS], N2[NS], D[NS];
+    float thj[NS];  // alpha_min threshold of strip j's pixel, +inf once it has terminated
     int32_t last[NS];
     bool act[NS];
 #pragma unroll
     for (int j = 0; j < NS; j++) {
         T[j] = 1.0f; N0[j] = N1[j] = N2[j] = D[j] = 0.0f; last[j] = 0;
         act[j] = px < f.W && py0 + 4 * j < f.H;
+        thj[j] = act[j] ? th : INFINITY;
     }
 
     Chunk q;
@@ -218,6 +220,7 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
 #pragma unroll
                 for (int j = 0; j < NS; j++) {
                     act[j] = act[j] && !(T[j] < eps);  // cell-level termination
+                    thj[j] = act[j] ? th : INFINITY;
                     anyact = anyact || act[j];
                 }
                 if (!STATS && !__any(anyact)) {
@@ -248,13 +251,14 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
                     const float dy = (float)(int)ry + e.oy;
                     const float pw = fmaf(dy, fmaf(e.cc, dy, t1), t0);
                     const bool iny = ry <= e.wy;
-                    const bool hit = iny & (pw >= th);
+                    const bool hit = iny & (pw >= thj[j]);  // false once the pixel has terminated
                     if (STATS) {
-                        cn.val += hit;
-                        cn.rend += hit && act[j];
+                        const bool val = iny & (pw >= th);
+                        cn.val += val;
+                        cn.rend += val && act[j];
                         cn.box += inx && iny && act[j];
                     }
-                    if (hit & act[j]) {
+                    if (hit) {
                         const float al = fminf(amax, __builtin_amdgcn_exp2f(pw));
                         A0[j] = fmaf(al, e.r, A0[j]);
                         A1[j] = fmaf(al, e.g, A1[j]);
