@@ -84,15 +84,26 @@ struct BRec {
 
 // log2(sigma G') with exactly the forward's operations, so every gate
 // decision (box, alpha_min) and every alpha is reproduced bit for bit.
-__device__ inline float brec_power(const BRec& e, float dx, float dy) {
-    const float t0 = fmaf(e.ca * dx, dx, e.lo);
+// Outside the box's columns (inx false) the power is -inf, which the
+// alpha_min test rejects as the forward's box test does.
+__device__ inline float brec_power(const BRec& e, float dx, float dy, bool inx) {
+    const float t0 = inx ? fmaf(e.ca * dx, dx, e.lo) : -INFINITY;
     const float t1 = e.cb * dx;
     return fmaf(dy, fmaf(e.cc, dy, t1), t0);
 }
 
-__device__ inline BRec read_brec(const GRec* lds, int i) {
-    const float4* p = reinterpret_cast<const float4*>(lds + i);
-    const float4 a = p[0], b = p[1], c = p[2];
+typedef float F4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) const F4 LdsF4;
+
+// The wavefront's record array as a 32-bit LDS address in a scalar register
+// (every lane reads the same record).
+__device__ inline uint32_t lds_base(const GRec* lds) {
+    return __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(const LdsF4*)lds);
+}
+
+__device__ inline BRec read_brec(uint32_t lb, int i) {
+    const LdsF4* p = (const LdsF4*)(uintptr_t)(lb + (uint32_t)i * (uint32_t)sizeof(GRec));
+    const F4 a = p[0], b = p[1], c = p[2];
     BRec e;
     e.ox = a.x; e.oy = a.y;
     e.ca = a.z; e.cb = a.w; e.cc = b.x;
@@ -128,6 +139,7 @@ __device__ inline void duplex_tile_bwd(const BwdArgs& a, int tile, int s0, int l
     const uint32_t kmask = K == 32 ? 0xffffffffu : ((1u << K) - 1u);
     const float th = a.o.log2_alpha_min, amax = a.o.alpha_max;
     const size_t HW = (size_t)k.W * k.H;
+    const uint32_t lb = lds_base(lds);
 
     int32_t last[NS];
     float gN0[NS], gN1[NS], gN2[NS], gD[NS], T[NS], R[NS];
@@ -192,11 +204,13 @@ __device__ inline void duplex_tile_bwd(const BwdArgs& a, int tile, int s0, int l
             const int p = lo_c + c;  // list position (0-based) of this cell
             uint32_t mj[NS], mm = 0;
             bool act[NS], anyact = false;
+            float thj[NS];  // alpha_min threshold, +inf where the pixel does not reach this cell
 #pragma unroll
             for (int j = 0; j < NS; j++) {
                 mj[j] = (uint32_t)(Bm[j] >> base) & kmask;
                 mm |= mj[j];
                 act[j] = p < last[j];
+                thj[j] = act[j] ? th : INFINITY;
                 anyact = anyact || act[j];
             }
             if (!mm || !__any(anyact)) continue;  // no member touches the owned rows / no pixel reaches the cell
@@ -208,18 +222,17 @@ __device__ inline void duplex_tile_bwd(const BwdArgs& a, int tile, int s0, int l
             for (int j = 0; j < NS; j++) { A0[j] = A1[j] = A2[j] = Bs[j] = 0.0f; P[j] = 1.0f; }
             for (uint32_t rem = mm; rem; rem &= rem - 1) {
                 const int kk = __builtin_ctz(rem);
-                const BRec e = read_brec(lds, base + kk);
+                const BRec e = read_brec(lb, base + kk);
                 const uint32_t rx = (uint32_t)(px - e.x0);
                 const bool inx = rx <= e.wx;
                 const float dx = (float)(int)rx + e.ox;
                 const uint32_t ry0 = (uint32_t)(py0 - e.y0);
 #pragma unroll
                 for (int j = 0; j < NS; j++) {
-                    if (!((mj[j] >> kk) & 1u)) continue;
                     const uint32_t ry = ry0 + 4u * j;
                     const float dy = (float)(int)ry + e.oy;
-                    const float pw = brec_power(e, dx, dy);
-                    if (act[j] && inx && ry <= e.wy && pw >= th) {
+                    const float pw = brec_power(e, dx, dy, inx);
+                    if ((ry <= e.wy) & (pw >= thj[j])) {
                         const float al = fminf(amax, __builtin_amdgcn_exp2f(pw));
                         A0[j] = fmaf(al, e.r, A0[j]); A1[j] = fmaf(al, e.g, A1[j]); A2[j] = fmaf(al, e.b, A2[j]);
                         Bs[j] += al;
@@ -249,7 +262,7 @@ __device__ inline void duplex_tile_bwd(const BwdArgs& a, int tile, int s0, int l
             // pass 2: per-member gradients, summed over the lane's pixels, then the wave
             for (uint32_t rem = mm; rem; rem &= rem - 1) {
                 const int kk = __builtin_ctz(rem);
-                const BRec e = read_brec(lds, base + kk);
+                const BRec e = read_brec(lb, base + kk);
                 const uint32_t rx = (uint32_t)(px - e.x0);
                 const bool inx = rx <= e.wx;
                 const float dx = (float)(int)rx + e.ox;
@@ -259,11 +272,10 @@ __device__ inline void duplex_tile_bwd(const BwdArgs& a, int tile, int s0, int l
                 const float inv_sigma = __builtin_amdgcn_rcpf(e.sigma);
 #pragma unroll
                 for (int j = 0; j < NS; j++) {
-                    if (!((mj[j] >> kk) & 1u)) continue;
                     const uint32_t ry = ry0 + 4u * j;
                     const float dy = (float)(int)ry + e.oy;
-                    const float pw = brec_power(e, dx, dy);
-                    if (act[j] && inx && ry <= e.wy && pw >= th) {
+                    const float pw = brec_power(e, dx, dy, inx);
+                    if ((ry <= e.wy) & (pw >= thj[j])) {
                         anyhit = true;
                         const float sg = __builtin_amdgcn_exp2f(pw);  // sigma G'
                         const float al = fminf(amax, sg);
