@@ -115,8 +115,11 @@ typedef struct {
     int32_t* last;     /* [H][W] 1 + tile-list position of the last contributing entry (0 = none), nullable */
 } dgs_image;
 
-/* Gradients: caller-owned device buffers in the scene's planar layout.  The
- * library ADDS into them, so zero them first.  Cell scales and rotations only
+/* Gradients: caller-owned device buffers in the scene's planar layout.  With
+ * overwrite == 0 the library ADDS into them (zero them first, or accumulate
+ * over several frames); with overwrite != 0 it writes every entry of every
+ * buffer (zero where there is no gradient), so they need no clearing and are
+ * not read.  Cell scales and rotations only
  * decide which tiles a cell is listed in (a discrete choice), so they get no
  * gradient; cell positions get the gradient through the view direction of
  * v_n only. */
@@ -129,6 +132,7 @@ typedef struct {
     float* d_cell_v_sh; /* [Cv][N] */
     float* d_cell_pos;  /* [3][N] */
     float* d_mean2d;    /* [2][M] gradient of the projected means (densification statistics), nullable */
+    int32_t overwrite;  /* 0: add into the buffers; nonzero: write them */
 } dgs_grads;
 
 typedef struct {

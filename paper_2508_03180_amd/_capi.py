@@ -55,7 +55,7 @@ class dgs_image(C.Structure):
 class dgs_grads(C.Structure):
     _fields_ = [("d_means", C.c_void_p), ("d_scales", C.c_void_p), ("d_rots", C.c_void_p),
                 ("d_opacities", C.c_void_p), ("d_sh", C.c_void_p), ("d_cell_v_sh", C.c_void_p),
-                ("d_cell_pos", C.c_void_p), ("d_mean2d", C.c_void_p)]
+                ("d_cell_pos", C.c_void_p), ("d_mean2d", C.c_void_p), ("overwrite", C.c_int32)]
 
 
 class dgs_stats(C.Structure):

@@ -384,6 +384,14 @@ __device__ inline void dir_to_pos(const float* d, float len, const float* g, flo
     for (int i = 0; i < 3; i++) gp[i] += (g[i] - d[i] * dg) / len;
 }
 
+// dst = v (OW: the caller's buffer is written, not read) or dst += v.
+template <bool OW>
+__device__ inline void put(float* dst, float v) {
+    if constexpr (OW) *dst = v;
+    else *dst += v;
+}
+
+template <bool OW>
 __global__ __launch_bounds__(256) void k_gauss_project_bwd(BwdArgs a, ProjBwdArgs b) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= a.M) return;
@@ -396,7 +404,17 @@ __global__ __launch_bounds__(256) void k_gauss_project_bwd(BwdArgs a, ProjBwdArg
     bool any = false;
 #pragma unroll
     for (int i = 0; i < 9; i++) any = any || s9[i] != 0.0f;
-    if (!any) return;
+    if (!any) {
+        if constexpr (OW) {  // no gradient reaches this Gaussian: its entries are zero
+            for (int i = 0; i < 3; i++) b.d_means[(size_t)i * M + g] = b.d_scales[(size_t)i * M + g] = 0.0f;
+            for (int i = 0; i < 4; i++) b.d_rots[(size_t)i * M + g] = 0.0f;
+            b.d_opac[g] = 0.0f;
+            const int C3 = 3 * (b.sh_degree + 1) * (b.sh_degree + 1);
+            for (int i = 0; i < C3; i++) b.d_sh[(size_t)i * M + g] = 0.0f;
+            if (b.d_mean2d) b.d_mean2d[g] = b.d_mean2d[M + g] = 0.0f;
+        }
+        return;
+    }
     const CamK& k = a.k;
     const float m0 = b.means[g], m1 = b.means[M + g], m2 = b.means[2 * M + g];
     float t[3];
@@ -479,11 +497,11 @@ __global__ __launch_bounds__(256) void k_gauss_project_bwd(BwdArgs a, ProjBwdArg
     const float gz = 2.f * (-2.f * z * gR[0] - w * gR[1] + x * gR[2] + w * gR[3] - 2.f * z * gR[4] + y * gR[5] +
                             x * gR[6] + y * gR[7]);
     const float qd = w * gw + x * gx + y * gy + z * gz;
-    b.d_rots[g] += (gw - w * qd) / qn;
-    b.d_rots[M + g] += (gx - x * qd) / qn;
-    b.d_rots[2 * M + g] += (gy - y * qd) / qn;
-    b.d_rots[3 * M + g] += (gz - z * qd) / qn;
-    for (int j = 0; j < 3; j++) b.d_scales[(size_t)j * M + g] += gs[j];
+    put<OW>(&b.d_rots[g], (gw - w * qd) / qn);
+    put<OW>(&b.d_rots[M + g], (gx - x * qd) / qn);
+    put<OW>(&b.d_rots[2 * M + g], (gy - y * qd) / qn);
+    put<OW>(&b.d_rots[3 * M + g], (gz - z * qd) / qn);
+    for (int j = 0; j < 3; j++) put<OW>(&b.d_scales[(size_t)j * M + g], gs[j]);
     // Mx = J W: dL/dJ = dL/dMx W^T, then J (and the mean u) -> camera-space position
     const float gJ00 = gMx[0] * k.R[0] + gMx[1] * k.R[1] + gMx[2] * k.R[2];
     const float gJ02 = gMx[0] * k.R[6] + gMx[1] * k.R[7] + gMx[2] * k.R[8];
@@ -520,35 +538,49 @@ __global__ __launch_bounds__(256) void k_gauss_project_bwd(BwdArgs a, ProjBwdArg
     float gdir[3] = {0.f, 0.f, 0.f};
     for (int ch = 0; ch < 3; ch++) {
         const float gc = s9[6 + ch];
-        if (gc == 0.0f) continue;
-        float cval = 0.5f;
-        for (int j = 0; j < Cn; j++) cval += Y[j] * b.sh[((size_t)j * 3 + ch) * M + g];
-        if (cval < 0.0f) continue;  // clamped colour channel
+        bool live = gc != 0.0f;
+        if (live) {
+            float cval = 0.5f;
+            for (int j = 0; j < Cn; j++) cval += Y[j] * b.sh[((size_t)j * 3 + ch) * M + g];
+            live = !(cval < 0.0f);  // a clamped colour channel has no gradient
+        }
+        if (!live) {
+            if constexpr (OW)
+                for (int j = 0; j < Cn; j++) b.d_sh[((size_t)j * 3 + ch) * M + g] = 0.0f;
+            continue;
+        }
         for (int j = 0; j < Cn; j++) {
             const float c = b.sh[((size_t)j * 3 + ch) * M + g];
-            b.d_sh[((size_t)j * 3 + ch) * M + g] += gc * Y[j];
+            put<OW>(&b.d_sh[((size_t)j * 3 + ch) * M + g], gc * Y[j]);
             gdir[0] += gc * c * Yx[j];
             gdir[1] += gc * c * Yy[j];
             gdir[2] += gc * c * Yz[j];
         }
     }
     dir_to_pos(dd, len, gdir, gm);
-    for (int j = 0; j < 3; j++) b.d_means[(size_t)j * M + g] += gm[j];
-    b.d_opac[g] += s9[5];
+    for (int j = 0; j < 3; j++) put<OW>(&b.d_means[(size_t)j * M + g], gm[j]);
+    put<OW>(&b.d_opac[g], s9[5]);
     if (b.d_mean2d) {
-        b.d_mean2d[g] += gu0;
-        b.d_mean2d[M + g] += gu1;
+        put<OW>(&b.d_mean2d[g], gu0);
+        put<OW>(&b.d_mean2d[M + g], gu1);
     }
 }
 
+template <bool OW>
 __global__ __launch_bounds__(256) void k_cell_bwd(BwdArgs a, ProjBwdArgs b) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= b.N) return;
     a.k = a.fr->k;
     a.o = a.fr->o;
-    if (a.o.v_one) return;
-    const float gv = a.gv[n];
-    if (gv == 0.0f) return;
+    const float gv = a.o.v_one ? 0.0f : a.gv[n];  // v = 1: v's parameters have no gradient
+    if (gv == 0.0f) {
+        if constexpr (OW) {
+            const int Cv = (b.v_sh_degree + 1) * (b.v_sh_degree + 1);
+            for (int j = 0; j < Cv; j++) b.d_cell_v_sh[(size_t)j * b.N + n] = 0.0f;
+            for (int j = 0; j < 3; j++) b.d_cell_pos[(size_t)j * b.N + n] = 0.0f;
+        }
+        return;
+    }
     const CamK& k = a.k;
     const int N = b.N;
     const float p0 = b.cell_pos[n], p1 = b.cell_pos[N + n], p2 = b.cell_pos[2 * N + n];
@@ -565,14 +597,14 @@ __global__ __launch_bounds__(256) void k_cell_bwd(BwdArgs a, ProjBwdArgs b) {
     float gdir[3] = {0.f, 0.f, 0.f};
     for (int j = 0; j < Cn; j++) {
         const float c = b.cell_v_sh[(size_t)j * N + n];
-        b.d_cell_v_sh[(size_t)j * N + n] += gs * Y[j];
+        put<OW>(&b.d_cell_v_sh[(size_t)j * N + n], gs * Y[j]);
         gdir[0] += gs * c * Yx[j];
         gdir[1] += gs * c * Yy[j];
         gdir[2] += gs * c * Yz[j];
     }
     float gp[3] = {0.f, 0.f, 0.f};
     dir_to_pos(dd, len, gdir, gp);
-    for (int j = 0; j < 3; j++) b.d_cell_pos[(size_t)j * N + n] += gp[j];
+    for (int j = 0; j < 3; j++) put<OW>(&b.d_cell_pos[(size_t)j * N + n], gp[j]);
 }
 
 void launch_composite_bwd(hipStream_t st, const BwdArgs& a) {
@@ -582,10 +614,16 @@ void launch_composite_bwd(hipStream_t st, const BwdArgs& a) {
     hipLaunchKernelGGL(k_composite_bwd, dim3((waves + kBwdWaves - 1) / kBwdWaves), dim3(256), 0, st, a);
 }
 
-void launch_project_bwd(hipStream_t st, const BwdArgs& a, const ProjBwdArgs& b) {
+template <bool OW>
+static void project_bwd(hipStream_t st, const BwdArgs& a, const ProjBwdArgs& b) {
     if (a.M > 0)
-        hipLaunchKernelGGL(k_gauss_project_bwd, dim3((a.M + 255) / 256), dim3(256), 0, st, a, b);
-    if (b.N > 0) hipLaunchKernelGGL(k_cell_bwd, dim3((b.N + 255) / 256), dim3(256), 0, st, a, b);
+        hipLaunchKernelGGL(k_gauss_project_bwd<OW>, dim3((a.M + 255) / 256), dim3(256), 0, st, a, b);
+    if (b.N > 0) hipLaunchKernelGGL(k_cell_bwd<OW>, dim3((b.N + 255) / 256), dim3(256), 0, st, a, b);
+}
+
+void launch_project_bwd(hipStream_t st, const BwdArgs& a, const ProjBwdArgs& b) {
+    if (b.overwrite) project_bwd<true>(st, a, b);
+    else project_bwd<false>(st, a, b);
 }
 
 }  // namespace dgs

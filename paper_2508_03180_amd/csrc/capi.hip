@@ -626,6 +626,7 @@ dgs_status dgs_render_backward(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
         b.d_sh = gr->d_sh;
         b.d_cell_v_sh = gr->d_cell_v_sh;
         b.d_cell_pos = gr->d_cell_pos;
+        b.overwrite = gr->overwrite != 0;
         b.d_mean2d = gr->d_mean2d;
         launch_project_bwd(q, a, b);
     }

@@ -258,14 +258,15 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
                         cn.rend += val && act[j];
                         cn.box += inx && iny && act[j];
                     }
-                    if (hit) {
-                        const float al = fminf(amax, __builtin_amdgcn_exp2f(pw));
-                        A0[j] = fmaf(al, e.r, A0[j]);
-                        A1[j] = fmaf(al, e.g, A1[j]);
-                        A2[j] = fmaf(al, e.b, A2[j]);
-                        Bs[j] += al;
-                        if constexpr (!LC) P[j] = fmaf(-P[j], v * al, P[j]);
-                    }
+                    // no branch: a pixel that is not hit adds alpha = 0, which
+                    // leaves A, B and P exactly unchanged (the four strips then
+                    // interleave without exec-mask changes)
+                    const float al = hit ? fminf(amax, __builtin_amdgcn_exp2f(pw)) : 0.0f;
+                    A0[j] = fmaf(al, e.r, A0[j]);
+                    A1[j] = fmaf(al, e.g, A1[j]);
+                    A2[j] = fmaf(al, e.b, A2[j]);
+                    Bs[j] += al;
+                    if constexpr (!LC) P[j] = fmaf(-P[j], v * al, P[j]);
                 }
             }
 #pragma unroll

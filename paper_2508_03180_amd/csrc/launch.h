@@ -167,6 +167,7 @@ struct ProjBwdArgs {
     const float *cell_pos, *cell_v_sh;
     int v_sh_degree;
     float *d_means, *d_scales, *d_rots, *d_opac, *d_sh, *d_cell_v_sh, *d_cell_pos, *d_mean2d;
+    bool overwrite;  // write every entry instead of adding
 };
 void launch_composite_bwd(hipStream_t st, const BwdArgs& a);
 void launch_project_bwd(hipStream_t st, const BwdArgs& a, const ProjBwdArgs& b);

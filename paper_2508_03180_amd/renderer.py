@@ -183,22 +183,32 @@ class Renderer:
         self.frame_id += 1
         return capi.dgs_render(self.ctx, scene.struct(), camera_struct(cam), opts, img)
 
-    def render_backward(self, scene: DeviceScene, cam, out, grad_color, grad_D=None, mean2d=False, **kw):
+    def render_backward(self, scene: DeviceScene, cam, out, grad_color, grad_D=None, mean2d=False, into=None,
+                        **kw):
         """Gradients (planar, float32) of a loss whose gradient w.r.t. the
-        last render's colour is grad_color [3,H,W] (and w.r.t. D, grad_D)."""
+        last render's colour is grad_color [3,H,W] (and w.r.t. D, grad_D).
+        Without `into`, new buffers are returned, written whole by the
+        library; with `into` (a dict as returned here), the gradients are
+        added to its buffers and it is returned."""
         d = self.device
         M, N = scene.M, scene.N
-        g = dict(means=torch.zeros((3, M), device=d), scales=torch.zeros((3, M), device=d),
-                 rots=torch.zeros((4, M), device=d), opacities=torch.zeros((M,), device=d),
-                 sh=torch.zeros_like(scene.t["sh"]), cell_v_sh=torch.zeros_like(scene.t["cell_v_sh"]),
-                 cell_pos=torch.zeros((3, N), device=d))
-        if mean2d:
-            g["mean2d"] = torch.zeros((2, M), device=d)
+        if into is None:
+            g = dict(means=torch.empty((3, M), device=d), scales=torch.empty((3, M), device=d),
+                     rots=torch.empty((4, M), device=d), opacities=torch.empty((M,), device=d),
+                     sh=torch.empty_like(scene.t["sh"]), cell_v_sh=torch.empty_like(scene.t["cell_v_sh"]),
+                     cell_pos=torch.empty((3, N), device=d))
+            if mean2d:
+                g["mean2d"] = torch.empty((2, M), device=d)
+        else:
+            g = into
+            if mean2d and "mean2d" not in g:
+                raise ValueError("into has no mean2d buffer")
         gr = capi.dgs_grads()
+        gr.overwrite = 1 if into is None else 0
         gr.d_means, gr.d_scales, gr.d_rots = g["means"].data_ptr(), g["scales"].data_ptr(), g["rots"].data_ptr()
         gr.d_opacities, gr.d_sh = g["opacities"].data_ptr(), g["sh"].data_ptr()
         gr.d_cell_v_sh, gr.d_cell_pos = g["cell_v_sh"].data_ptr(), g["cell_pos"].data_ptr()
-        gr.d_mean2d = g["mean2d"].data_ptr() if mean2d else None
+        gr.d_mean2d = g["mean2d"].data_ptr() if "mean2d" in g and (mean2d or into is not None) else None
         img = capi.dgs_image()
         img.color, img.weight_sum = out["color"].data_ptr(), out["D"].data_ptr()
         img.final_T, img.last = out["T"].data_ptr(), out["last"].data_ptr()

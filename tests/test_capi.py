@@ -39,6 +39,7 @@ def test_struct_layouts_match_header_sizes():
     assert ctypes.sizeof(_capi.dgs_camera) == 16 * 4 + 4 * 4 + 2 * 4 + 4
     assert ctypes.sizeof(_capi.dgs_render_opts) == 4 + 4 + 5 * 4 + 3 * 4 + 4
     assert ctypes.sizeof(_capi.dgs_image) == 4 * 8
+    assert ctypes.sizeof(_capi.dgs_grads) == 8 * 8 + 8  # eight pointers, overwrite flag, padding
 
 
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):

@@ -162,3 +162,47 @@ def test_backward_rejects_alpha_mode_and_mismatch(R):
         R.render_backward(ds, cam, out, torch.zeros((3, 64, 64), device="cuda"), mode="alpha")
     with pytest.raises(_capi.DgsError, match="same scene"):
         R.render_backward(ds, cam, out, torch.zeros((3, 64, 64), device="cuda"))
+
+
+@pytest.mark.parametrize("v_one", [False, True])
+def test_overwrite_and_accumulate_modes_agree(R, v_one):
+    """Written gradients (buffers full of NaN beforehand, never read) equal
+    gradients added into zeroed buffers, and a second backward doubles
+    them; every entry is written, including Gaussians and cells that get no
+    gradient."""
+    from paper_2508_03180_amd import _capi
+    from paper_2508_03180_amd.renderer import DeviceScene, camera_struct, opts_struct
+    s = small_scene()
+    # a narrow view: cells outside it get no gradient
+    cam = scenes.pinhole(scenes.tiny_camera()["viewmat"], 64, 64, fov_x_deg=25.0)
+    ds = DeviceScene.from_numpy(s, "cuda:0")
+    opts = dict(v_one=True) if v_one else {}
+    out = R.render(ds, cam, **opts)
+    gC = torch.randn((3, 64, 64), device="cuda", generator=torch.Generator("cuda").manual_seed(5))
+    g = R.render_backward(ds, cam, out, gC, mean2d=True, **opts)
+    # overwrite into NaN-filled buffers through the C ABI
+    nan = {k: torch.full_like(v, float("nan")) for k, v in g.items()}
+    gr = _capi.dgs_grads()
+    gr.d_means, gr.d_scales, gr.d_rots = nan["means"].data_ptr(), nan["scales"].data_ptr(), nan["rots"].data_ptr()
+    gr.d_opacities, gr.d_sh = nan["opacities"].data_ptr(), nan["sh"].data_ptr()
+    gr.d_cell_v_sh, gr.d_cell_pos, gr.d_mean2d = (nan["cell_v_sh"].data_ptr(), nan["cell_pos"].data_ptr(),
+                                                  nan["mean2d"].data_ptr())
+    gr.overwrite = 1
+    img = _capi.dgs_image(out["color"].data_ptr(), out["D"].data_ptr(), out["T"].data_ptr(), out["last"].data_ptr())
+    _capi.check(_capi.dgs_render_backward(R.ctx, ds.struct(), camera_struct(cam), opts_struct(**opts), img,
+                                          gC.data_ptr(), None, gr), R.ctx)
+    acc = {k: torch.zeros_like(v) for k, v in g.items()}
+    R.render_backward(ds, cam, out, gC, into=acc, **opts)
+    torch.cuda.synchronize()
+    for k in g:
+        assert not torch.isnan(nan[k]).any(), k
+        torch.testing.assert_close(nan[k], g[k], rtol=1e-5, atol=1e-7, msg=k)
+        torch.testing.assert_close(acc[k], g[k], rtol=1e-5, atol=1e-7, msg=k)
+    R.render_backward(ds, cam, out, gC, into=acc, **opts)
+    torch.cuda.synchronize()
+    for k in g:
+        torch.testing.assert_close(acc[k], 2 * g[k], rtol=1e-5, atol=1e-7, msg=k)
+    # Gaussians and cells outside the view get no gradient: zeros
+    assert (g["means"].abs().sum(0) == 0).any() and (g["sh"].abs().sum((0, 1)) == 0).any()
+    if v_one:
+        assert (g["cell_v_sh"] == 0).all() and (g["cell_pos"] == 0).all()
