@@ -48,6 +48,12 @@ __device__ inline uint32_t wave_incl_scan(uint32_t v) {
     return v;
 }
 
+__device__ inline uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
 // Persistent blocks take partitions from a ticket counter in launch order, so
 // a partition only ever waits for partitions that are already running.
 __global__ __launch_bounds__(kScanThreads) void k_scan_excl(const uint32_t* __restrict__ in,
@@ -82,30 +88,49 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_excl(const uint32_t* __re
             if (w < wave) wprefix += s;
             btotal += s;
         }
-        if (tid == 0) {
+        if (wave == 0) {
+            // decoupled look-back by the whole wavefront: lane l reads the
+            // status of partition j - l, so one round trip covers 64
+            // predecessors; it stops at the nearest inclusive prefix
             const uint64_t tag = (uint64_t)epoch << 34;
             uint32_t excl = 0;
             if (part == 0) {
-                st_status(&status[0], tag | (2ull << 32) | btotal);
+                if (lane == 0) st_status(&status[0], tag | (2ull << 32) | btotal);
             } else {
-                st_status(&status[part], tag | (1ull << 32) | btotal);
+                if (lane == 0) st_status(&status[part], tag | (1ull << 32) | btotal);
                 int j = part - 1, spins = 0;
-                while (j >= 0) {
-                    const uint64_t s = ld_status(&status[j]);
-                    const uint32_t flag = (uint32_t)(s >> 32) & 3u;
-                    if ((uint32_t)(s >> 34) != epoch || flag == 0) {
-                        if (++spins > kSpinLimit) { atomicOr(err, 1 << kErrTimeout); break; }
-                        __builtin_amdgcn_s_sleep(1);
+                for (;;) {
+                    const int idx = j - lane;
+                    uint32_t flag = 2, val = 0;  // before partition 0: an inclusive prefix of 0
+                    if (idx >= 0) {
+                        const uint64_t st = ld_status(&status[idx]);
+                        flag = (uint32_t)(st >> 34) == epoch ? (uint32_t)(st >> 32) & 3u : 0u;
+                        val = (uint32_t)st;
+                    }
+                    const uint64_t notready = __ballot(flag == 0), inclusive = __ballot(flag == 2);
+                    const int fn = notready ? __builtin_ctzll(notready) : 64;
+                    const int li = inclusive ? __builtin_ctzll(inclusive) : 64;
+                    if (li < fn) {  // every partition down to the nearest inclusive prefix is published
+                        excl += wave_sum_u32(lane <= li ? val : 0u);
+                        break;
+                    }
+                    if (fn > 0) {  // totals of the published run [0, fn): take them and move on
+                        excl += wave_sum_u32(lane < fn ? val : 0u);
+                        j -= fn;
                         continue;
                     }
-                    excl += (uint32_t)s;
-                    if (flag == 2) break;
-                    j--;
+                    if (++spins > kSpinLimit) {
+                        if (lane == 0) atomicOr(err, 1 << kErrTimeout);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
                 }
-                st_status(&status[part], tag | (2ull << 32) | (excl + btotal));
+                if (lane == 0) st_status(&status[part], tag | (2ull << 32) | (excl + btotal));
             }
-            s_excl = excl;
-            if (part == nparts - 1) *total = excl + btotal;
+            if (lane == 0) {
+                s_excl = excl;
+                if (part == nparts - 1) *total = excl + btotal;
+            }
         }
         __syncthreads();
         uint32_t run = s_excl + wprefix + incl - sum;

@@ -120,6 +120,9 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const KeyT* __restric
     __shared__ uint32_t s_goff[256];  // global start of each digit: exclusive scan of the digit counts
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t epoch = epoch_tag(*ep, pass_tag);
+    // the first partition ticket is taken before the digit counts are read,
+    // so the two round trips overlap
+    if (tid == 0) s_part = atomicAdd(ticket, 1u);
     uint32_t n = n_ptr ? *n_ptr : cap;
     if (n > cap) n = cap;
     const uint32_t nparts = (n + kSortPart - 1) / kSortPart;
@@ -139,7 +142,6 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const KeyT* __restric
         __syncthreads();  // s_wsum is reused below
     }
     for (;;) {
-        if (tid == 0) s_part = atomicAdd(ticket, 1u);
         for (int d = tid; d < kSortWaves * 256; d += kSortThreads) (&s_cnt[0][0])[d] = 0;
         __syncthreads();
         const uint32_t part = s_part;
@@ -229,7 +231,8 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const KeyT* __restric
             }
         }
         if (gridDim.x >= nparts) break;  // the other partitions went to other workgroups
-        __syncthreads();  // LDS is reused by the next partition
+        __syncthreads();  // LDS (and s_part) are reused by the next partition
+        if (tid == 0) s_part = atomicAdd(ticket, 1u);
     }
 }
 
