@@ -229,9 +229,11 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
                 }
             }
             const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cv), base));
-            float A0[NS], A1[NS], A2[NS], Bs[NS], P[NS];
+            // the cell's weight is fixed before its members: w alpha c and
+            // w alpha go straight into N and D (no per-cell sums A, B)
+            float wj[NS], P[NS], Bs[NS];
 #pragma unroll
-            for (int j = 0; j < NS; j++) { A0[j] = A1[j] = A2[j] = Bs[j] = 0.0f; P[j] = 1.0f; }
+            for (int j = 0; j < NS; j++) { wj[j] = LC ? v : v * T[j]; P[j] = 1.0f; Bs[j] = 0.0f; }
             for (uint32_t rem = any; rem; rem &= rem - 1) {
                 const int k = __builtin_ctz(rem);
                 const RecView e = read_rec(lb, base + k);
@@ -262,25 +264,24 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
                     // leaves A, B and P exactly unchanged (the four strips then
                     // interleave without exec-mask changes)
                     const float al = hit ? fminf(amax, __builtin_amdgcn_exp2f(pw)) : 0.0f;
-                    A0[j] = fmaf(al, e.r, A0[j]);
-                    A1[j] = fmaf(al, e.g, A1[j]);
-                    A2[j] = fmaf(al, e.b, A2[j]);
-                    Bs[j] += al;
+                    const float wa = wj[j] * al;
+                    N0[j] = fmaf(wa, e.r, N0[j]);
+                    N1[j] = fmaf(wa, e.g, N1[j]);
+                    N2[j] = fmaf(wa, e.b, N2[j]);
+                    D[j] += wa;
                     if constexpr (!LC) P[j] = fmaf(-P[j], v * al, P[j]);
+                    else Bs[j] += al;
                 }
             }
 #pragma unroll
             for (int j = 0; j < NS; j++) {
                 if (!mj[j]) continue;  // scalar: nothing of this cell in strip j
                 if (act[j]) {
-                    const float w = LC ? v : v * T[j];
-                    N0[j] = fmaf(w, A0[j], N0[j]);
-                    N1[j] = fmaf(w, A1[j], N1[j]);
-                    N2[j] = fmaf(w, A2[j], N2[j]);
-                    D[j] = fmaf(w, Bs[j], D[j]);
                     if constexpr (!LC) T[j] *= P[j];
-                    if (Bs[j] > 0.0f) last[j] = (int32_t)(pos + c - start + 1);
-                    if (STATS) cn.cellhit += Bs[j] > 0.0f;
+                    // a hit lowers P by v alpha >= v / 255
+                    const bool hitc = LC ? Bs[j] > 0.0f : P[j] < 1.0f;
+                    if (hitc) last[j] = (int32_t)(pos + c - start + 1);
+                    if (STATS) cn.cellhit += hitc;
                 }
             }
         }
