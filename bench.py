@@ -458,6 +458,23 @@ def main():
         capi.check(capi.dgs_sync(r.ctx), r.ctx)
         return dt
 
+    def frame_times(mode, orbits=2):
+        """Per-frame GPU time (HIP events between consecutive frames on the
+        context stream) over the orbit: median, p99 and max in ms."""
+        op = opts_struct(mode=mode)
+        n = orbits * NF
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+        ev[0].record(r.stream)
+        for i in range(n):
+            st = L.dgs_render(r.ctx, sc, cam_structs[i % NF], op, im)
+            if st:
+                capi.check(st, r.ctx)
+            ev[i + 1].record(r.stream)
+        torch.cuda.synchronize()
+        ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(n)])
+        return {"frames": n, "median_ms": round(float(np.median(ms)), 4),
+                "p99_ms": round(float(np.percentile(ms, 99)), 4), "max_ms": round(float(ms.max()), 4)}
+
     def stage_times(mode):
         capi.dgs_set_timing(r.ctx, 1)
         frames(mode, NF)
@@ -484,6 +501,7 @@ def main():
     dt = timed("duplex", a.steps, a.warmup)
     fps = a.steps / dt
     st_dup = stage_times("duplex")
+    fr_dup = frame_times("duplex")
     cnt = counters("duplex", range(0, NF, 6))
 
     alpha = None
@@ -491,10 +509,11 @@ def main():
         keys_alpha = size_all("alpha")
         dta = timed("alpha", a.steps, a.warmup)
         st_alpha = stage_times("alpha")
+        fr_alpha = frame_times("alpha")
         cnt_a = counters("alpha", range(0, NF, 6))
         comp_a = st_alpha["composite"]
         flops_a = FLOP_BOX * cnt_a["n_box"] + FLOP_ALPHA_HIT * cnt_a["n_rendered"]
-        alpha = {"fps": round(a.steps / dta, 2), "ms_per_step": round(1e3 * dta / a.steps, 4),
+        alpha = {"fps": round(a.steps / dta, 2), "ms_per_step": round(1e3 * dta / a.steps, 4), "frame_ms": fr_alpha,
                  "stages_ms": {k: round(v, 4) for k, v in st_alpha.items()},
                  "keys_mean": float(np.mean(keys_alpha)),
                  "composite_tflops": round(flops_a / (comp_a * 1e-3) / 1e12, 3),
@@ -545,6 +564,7 @@ def main():
                    "width": W, "height": H, "frames": NF},
         "alpha_baseline": alpha,
         "speedup_vs_alpha": None if alpha is None else round(fps / alpha["fps"], 3),
+        "frame_ms": fr_dup,
         "stages_ms": {k: round(v, 4) for k, v in st_dup.items()},
         "keys_mean": float(np.mean(keys_dup)),
         "key_reduction_vs_alpha": None if alpha is None else round(1 - np.mean(keys_dup) / alpha["keys_mean"], 4),
