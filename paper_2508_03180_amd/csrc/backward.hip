@@ -391,7 +391,9 @@ __device__ inline void put(float* dst, float v) {
     else *dst += v;
 }
 
-template <bool OW>
+// DEG: the scene's SH degree (0..3) as a constant, so that every loop over
+// the coefficients unrolls and their loads issue together.
+template <bool OW, int DEG>
 __global__ __launch_bounds__(256) void k_gauss_project_bwd(BwdArgs a, ProjBwdArgs b) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= a.M) return;
@@ -409,7 +411,8 @@ __global__ __launch_bounds__(256) void k_gauss_project_bwd(BwdArgs a, ProjBwdArg
             for (int i = 0; i < 3; i++) b.d_means[(size_t)i * M + g] = b.d_scales[(size_t)i * M + g] = 0.0f;
             for (int i = 0; i < 4; i++) b.d_rots[(size_t)i * M + g] = 0.0f;
             b.d_opac[g] = 0.0f;
-            const int C3 = 3 * (b.sh_degree + 1) * (b.sh_degree + 1);
+            constexpr int C3 = 3 * (DEG + 1) * (DEG + 1);
+#pragma unroll
             for (int i = 0; i < C3; i++) b.d_sh[(size_t)i * M + g] = 0.0f;
             if (b.d_mean2d) b.d_mean2d[g] = b.d_mean2d[M + g] = 0.0f;
         }
@@ -532,29 +535,33 @@ __global__ __launch_bounds__(256) void k_gauss_project_bwd(BwdArgs a, ProjBwdArg
     float dd[3] = {m0 - k.o[0], m1 - k.o[1], m2 - k.o[2]};
     const float len = sqrtf(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
     for (int i = 0; i < 3; i++) dd[i] /= len;
+    constexpr int Cn = (DEG + 1) * (DEG + 1);
     float Y[16], Yx[16], Yy[16], Yz[16];
-    const int deg = b.sh_degree, Cn = (deg + 1) * (deg + 1);
-    sh_basis_grad(deg, dd[0], dd[1], dd[2], Y, Yx, Yy, Yz);
+    sh_basis_grad(DEG, dd[0], dd[1], dd[2], Y, Yx, Yy, Yz);
     float gdir[3] = {0.f, 0.f, 0.f};
+#pragma unroll
     for (int ch = 0; ch < 3; ch++) {
         const float gc = s9[6 + ch];
-        bool live = gc != 0.0f;
-        if (live) {
-            float cval = 0.5f;
-            for (int j = 0; j < Cn; j++) cval += Y[j] * b.sh[((size_t)j * 3 + ch) * M + g];
-            live = !(cval < 0.0f);  // a clamped colour channel has no gradient
+        float c[Cn];
+        float cval = 0.5f;
+#pragma unroll
+        for (int j = 0; j < Cn; j++) {
+            c[j] = b.sh[((size_t)j * 3 + ch) * M + g];
+            cval += Y[j] * c[j];
         }
-        if (!live) {
-            if constexpr (OW)
+        if (gc == 0.0f || cval < 0.0f) {  // no gradient, or a clamped colour channel
+            if constexpr (OW) {
+#pragma unroll
                 for (int j = 0; j < Cn; j++) b.d_sh[((size_t)j * 3 + ch) * M + g] = 0.0f;
+            }
             continue;
         }
+#pragma unroll
         for (int j = 0; j < Cn; j++) {
-            const float c = b.sh[((size_t)j * 3 + ch) * M + g];
             put<OW>(&b.d_sh[((size_t)j * 3 + ch) * M + g], gc * Y[j]);
-            gdir[0] += gc * c * Yx[j];
-            gdir[1] += gc * c * Yy[j];
-            gdir[2] += gc * c * Yz[j];
+            gdir[0] += gc * c[j] * Yx[j];
+            gdir[1] += gc * c[j] * Yy[j];
+            gdir[2] += gc * c[j] * Yz[j];
         }
     }
     dir_to_pos(dd, len, gdir, gm);
@@ -566,7 +573,7 @@ __global__ __launch_bounds__(256) void k_gauss_project_bwd(BwdArgs a, ProjBwdArg
     }
 }
 
-template <bool OW>
+template <bool OW, int VDEG>
 __global__ __launch_bounds__(256) void k_cell_bwd(BwdArgs a, ProjBwdArgs b) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= b.N) return;
@@ -575,7 +582,8 @@ __global__ __launch_bounds__(256) void k_cell_bwd(BwdArgs a, ProjBwdArgs b) {
     const float gv = a.o.v_one ? 0.0f : a.gv[n];  // v = 1: v's parameters have no gradient
     if (gv == 0.0f) {
         if constexpr (OW) {
-            const int Cv = (b.v_sh_degree + 1) * (b.v_sh_degree + 1);
+            constexpr int Cv = (VDEG + 1) * (VDEG + 1);
+#pragma unroll
             for (int j = 0; j < Cv; j++) b.d_cell_v_sh[(size_t)j * b.N + n] = 0.0f;
             for (int j = 0; j < 3; j++) b.d_cell_pos[(size_t)j * b.N + n] = 0.0f;
         }
@@ -587,20 +595,24 @@ __global__ __launch_bounds__(256) void k_cell_bwd(BwdArgs a, ProjBwdArgs b) {
     float dd[3] = {p0 - k.o[0], p1 - k.o[1], p2 - k.o[2]};
     const float len = sqrtf(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
     for (int i = 0; i < 3; i++) dd[i] /= len;
+    constexpr int Cn = (VDEG + 1) * (VDEG + 1);
     float Y[16], Yx[16], Yy[16], Yz[16];
-    const int deg = b.v_sh_degree, Cn = (deg + 1) * (deg + 1);
-    sh_basis_grad(deg, dd[0], dd[1], dd[2], Y, Yx, Yy, Yz);
-    float sv = 0.f;
-    for (int j = 0; j < Cn; j++) sv += Y[j] * b.cell_v_sh[(size_t)j * N + n];
+    sh_basis_grad(VDEG, dd[0], dd[1], dd[2], Y, Yx, Yy, Yz);
+    float c[Cn], sv = 0.f;
+#pragma unroll
+    for (int j = 0; j < Cn; j++) {
+        c[j] = b.cell_v_sh[(size_t)j * N + n];
+        sv += Y[j] * c[j];
+    }
     const float v = 1.0f / (1.0f + __expf(-sv));
     const float gs = gv * v * (1.0f - v);
     float gdir[3] = {0.f, 0.f, 0.f};
+#pragma unroll
     for (int j = 0; j < Cn; j++) {
-        const float c = b.cell_v_sh[(size_t)j * N + n];
         put<OW>(&b.d_cell_v_sh[(size_t)j * N + n], gs * Y[j]);
-        gdir[0] += gs * c * Yx[j];
-        gdir[1] += gs * c * Yy[j];
-        gdir[2] += gs * c * Yz[j];
+        gdir[0] += gs * c[j] * Yx[j];
+        gdir[1] += gs * c[j] * Yy[j];
+        gdir[2] += gs * c[j] * Yz[j];
     }
     float gp[3] = {0.f, 0.f, 0.f};
     dir_to_pos(dd, len, gdir, gp);
@@ -614,11 +626,35 @@ void launch_composite_bwd(hipStream_t st, const BwdArgs& a) {
     hipLaunchKernelGGL(k_composite_bwd, dim3((waves + kBwdWaves - 1) / kBwdWaves), dim3(256), 0, st, a);
 }
 
+template <bool OW, int DEG>
+static void gauss_bwd(hipStream_t st, const BwdArgs& a, const ProjBwdArgs& b) {
+    hipLaunchKernelGGL((k_gauss_project_bwd<OW, DEG>), dim3((a.M + 255) / 256), dim3(256), 0, st, a, b);
+}
+
+template <bool OW, int VDEG>
+static void cell_bwd(hipStream_t st, const BwdArgs& a, const ProjBwdArgs& b) {
+    hipLaunchKernelGGL((k_cell_bwd<OW, VDEG>), dim3((b.N + 255) / 256), dim3(256), 0, st, a, b);
+}
+
+// Degrees were checked against 0..3 when the frame was rendered.
 template <bool OW>
 static void project_bwd(hipStream_t st, const BwdArgs& a, const ProjBwdArgs& b) {
-    if (a.M > 0)
-        hipLaunchKernelGGL(k_gauss_project_bwd<OW>, dim3((a.M + 255) / 256), dim3(256), 0, st, a, b);
-    if (b.N > 0) hipLaunchKernelGGL(k_cell_bwd<OW>, dim3((b.N + 255) / 256), dim3(256), 0, st, a, b);
+    if (a.M > 0) {
+        switch (b.sh_degree) {
+            case 0: gauss_bwd<OW, 0>(st, a, b); break;
+            case 1: gauss_bwd<OW, 1>(st, a, b); break;
+            case 2: gauss_bwd<OW, 2>(st, a, b); break;
+            default: gauss_bwd<OW, 3>(st, a, b);
+        }
+    }
+    if (b.N > 0) {
+        switch (b.v_sh_degree) {
+            case 0: cell_bwd<OW, 0>(st, a, b); break;
+            case 1: cell_bwd<OW, 1>(st, a, b); break;
+            case 2: cell_bwd<OW, 2>(st, a, b); break;
+            default: cell_bwd<OW, 3>(st, a, b);
+        }
+    }
 }
 
 void launch_project_bwd(hipStream_t st, const BwdArgs& a, const ProjBwdArgs& b) {

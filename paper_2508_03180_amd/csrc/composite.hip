@@ -261,7 +261,7 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
                         cn.box += inx && iny && act[j];
                     }
                     // no branch: a pixel that is not hit adds alpha = 0, which
-                    // leaves A, B and P exactly unchanged (the four strips then
+                    // leaves N, D and P exactly unchanged (the four strips then
                     // interleave without exec-mask changes)
                     const float al = hit ? fminf(amax, __builtin_amdgcn_exp2f(pw)) : 0.0f;
                     const float wa = wj[j] * al;
