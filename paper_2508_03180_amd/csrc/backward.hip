@@ -267,9 +267,12 @@ __device__ inline void duplex_tile_bwd(const BwdArgs& a, int tile, int s0, int l
                 const bool inx = rx <= e.wx;
                 const float dx = (float)(int)rx + e.ox;
                 const uint32_t ry0 = (uint32_t)(py0 - e.y0);
-                float gu0 = 0.f, gu1 = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, gs = 0.f, gr = 0.f, gg = 0.f, gb = 0.f;
+                // dL/dp per pixel (gp) enters the mean, conic and sigma
+                // gradients only through gp, gp dy and gp dy^2 (dx is the
+                // lane's constant for this member), so the lane sums those
+                // three and forms the seven quantities once per member
+                float S0 = 0.f, S1 = 0.f, S2 = 0.f, gr = 0.f, gg = 0.f, gb = 0.f;
                 bool anyhit = false;
-                const float inv_sigma = __builtin_amdgcn_rcpf(e.sigma);
 #pragma unroll
                 for (int j = 0; j < NS; j++) {
                     const uint32_t ry = ry0 + 4u * j;
@@ -284,19 +287,20 @@ __device__ inline void duplex_tile_bwd(const BwdArgs& a, int tile, int s0, int l
                         dv -= Pom * al;
                         const float dLda = dLdA0[j] * e.r + dLdA1[j] * e.g + dLdA2[j] * e.b + dLdB[j] - Pom * v;
                         gr += dLdA0[j] * al; gg += dLdA1[j] * al; gb += dLdA2[j] * al;
-                        if (sg < amax) {
-                            // alpha = sigma exp(p): dalpha/dp = alpha, dalpha/dsigma = alpha / sigma
-                            const float gp = dLda * al;
-                            gs += gp * inv_sigma;
-                            const float y0 = e.A * dx + e.B * dy, y1 = e.B * dx + e.C * dy;
-                            gu0 += gp * y0;  // p depends on the mean through dx = px + 0.5 - u
-                            gu1 += gp * y1;
-                            gA += -0.5f * gp * dx * dx;
-                            gB += -gp * dx * dy;
-                            gC += -0.5f * gp * dy * dy;
-                        }
+                        // alpha = sigma exp(p) below the clamp: dalpha/dp = alpha
+                        const float gp = sg < amax ? dLda * al : 0.0f;
+                        S0 += gp;
+                        S1 = fmaf(gp, dy, S1);
+                        S2 = fmaf(gp * dy, dy, S2);
                     }
                 }
+                // p = lo + ca dx^2 + cb dx dy + cc dy^2 with dx = px + 0.5 - u
+                // (and dy likewise): dp/du = (A dx + B dy, B dx + C dy) for
+                // the natural conic (A, B, C); dp/dA = -dx^2/2, dp/dB = -dx dy,
+                // dp/dC = -dy^2/2; dalpha/dsigma = alpha / sigma
+                const float gu0 = e.A * dx * S0 + e.B * S1, gu1 = e.B * dx * S0 + e.C * S1;
+                const float gA = -0.5f * dx * dx * S0, gB = -dx * S1, gC = -0.5f * S2;
+                const float gs = S0 * __builtin_amdgcn_rcpf(e.sigma);
                 if (__any(anyhit)) {
                     // quantities 0..7 by one transposed reduction (group q of
                     // eight lanes holds quantity q), quantity 8 by a plain one;
