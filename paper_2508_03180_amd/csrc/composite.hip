@@ -168,8 +168,16 @@ struct Counters {
     uint32_t val = 0, rend = 0, box = 0, cellhit = 0;
 };
 
+// The hybrid renderer over one tile (NS = 4) or one strip s0 (NS = 1)
+// (Sec. V-A, eq. hybrid_renderer with w_n = v_n T_n and eq. dulpex_T; Sec. V-B
+// termination; Sec. VI-A box gate): cells front to back; a pixel whose
+// transmittance in front of a cell is below eps stops there; inside a cell
+// every member that passes the box and alpha_min gates adds w alpha c to N
+// and w alpha to D with the cell's weight w = v T (the cell's alpha sums A,
+// B of the equation times w, accumulated member by member), and
+// P = prod (1 - v alpha) updates T after the cell; C = N / D at the end.
 // LC: the "w/o T^cell" weights -- cell_v holds w_n = v_n max(0, 1 - d_n / tau),
-// N += w A, D += w B, no transmittance and no termination.
+// no transmittance and no termination.
 template <bool STATS, int NS, bool LC>
 __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, int tile, int s0, int lane, GRec* lds,
                                  Counters& cn) {
