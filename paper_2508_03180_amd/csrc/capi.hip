@@ -336,6 +336,12 @@ dgs_status dgs_create(int device, void* hip_stream, dgs_ctx* out) {
         dgs_destroy(c);
         return DGS_ERR_OOM;
     }
+    if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+        dgs_destroy(c);
+        return DGS_ERR_DEVICE;
+    }
     hipMemsetAsync(c->misc, 0, 16 * sizeof(uint32_t), c->stream);
     hipMemsetAsync(c->dev_err, 0, sizeof(int), c->stream);
     hipMemsetAsync(c->counters, 0, 4 * sizeof(unsigned long long), c->stream);
@@ -348,10 +354,17 @@ dgs_status dgs_destroy(dgs_ctx c) {
     if (!c) return DGS_ERR_INVALID_ARG;
     hipSetDevice(c->device);
     hipStreamSynchronize(c->stream);
+    if (c->aux) {
+        hipStreamSynchronize(c->aux);
+        hipStreamDestroy(c->aux);
+    }
+    if (c->ev_fork) hipEventDestroy(c->ev_fork);
+    if (c->ev_join) hipEventDestroy(c->ev_join);
     for (auto& a : c->events)
         for (auto& e : a) hipEventDestroy(e);
     void* ptrs[] = {c->p_depth, c->p_ntiles, c->p_offsets, c->p_rect, c->cell_v, c->recs, c->grect,
                     c->keys0, c->keys1, c->vals0, c->vals1, c->ranges, c->tile_order, c->scan_status, c->sort_status, c->g2d, c->gv, c->dec,
+                    c->pk0, c->pk1, c->pv0, c->pv1, c->psort_status,
                     c->hist, c->misc, c->dev_err, c->counters, c->frame};
     for (void* p : ptrs)
         if (p) hipFree(p);
@@ -476,13 +489,24 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
         launch_clear(q, cl, write_frame ? &f : nullptr, c->frame);
     }
     sm.mark(0);
+    // Duplex / LC-WSR: the cell sort needs only the cell preprocess, so the
+    // (decode and) projection of the members runs on the second stream
+    // meanwhile; with stage timing on, everything stays on one stream
+    const bool overlap = cells && !c->timing;
     if (cells) {
         launch_cell_preprocess(q, N, s->cell_pos, s->cell_scale, s->cell_rot, s->cell_v_sh, s->v_sh_degree,
                                c->frame, c->p_depth, c->p_rect, c->p_ntiles, c->cell_v);
-        if (nn) launch_decode(q, decode_args(c, *nn, c->p_ntiles));
+        hipStream_t pq = q;
+        if (overlap) {
+            hipEventRecord(c->ev_fork, q);
+            hipStreamWaitEvent(c->aux, c->ev_fork, 0);
+            pq = c->aux;
+        }
+        if (nn) launch_decode(pq, decode_args(c, *nn, c->p_ntiles));
         sm.mark(1);
-        launch_gauss_project(q, M, K, s->means, s->scales, s->rots, s->opacities, s->sh, s->sh_degree, c->frame,
-                             c->p_ntiles, c->recs, c->grect, nullptr, nullptr);
+        launch_gauss_project(pq, M, K, s->means, s->scales, s->rots, s->opacities, s->sh, s->sh_degree, c->frame,
+                             c->p_ntiles, c->recs, c->grect, nullptr, nullptr, overlap);
+        if (overlap) hipEventRecord(c->ev_join, c->aux);
     } else {
         if (nn) launch_decode(q, decode_args(c, *nn, nullptr));
         sm.mark(1);
@@ -529,6 +553,7 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     a.order = c->tile_order;
     a.queue = c->misc + 11;
     launch_tile_order(q, c->ranges, tiles, kSplitLen, c->tile_order, c->misc + 11);
+    if (overlap) hipStreamWaitEvent(q, c->ev_join, 0);  // the projected members
     sm.mark(6);
     if (mode == DGS_MODE_DUPLEX)
         launch_composite_duplex(q, a);

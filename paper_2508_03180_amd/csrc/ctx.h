@@ -14,6 +14,11 @@ struct dgs_ctx_s {
     hipStream_t stream = nullptr;
     std::string err;
 
+    // second stream of the frame: the Gaussian projection runs on it while
+    // the cell sort runs on `stream` (fork after the cell preprocess, join
+    // before the compositor)
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int64_t cap_prims = 0, cap_gauss = 0, cap_keys = 0, cap_tiles = 0;
     uint64_t generation = 0;  // bumped whenever a workspace buffer moves (captured graphs go stale)
     uint32_t *p_depth = nullptr, *p_ntiles = nullptr, *p_offsets = nullptr;

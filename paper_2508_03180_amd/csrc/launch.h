@@ -32,7 +32,7 @@ void launch_cell_preprocess(hipStream_t st, int N, const float* pos, const float
 void launch_gauss_project(hipStream_t st, int M, int K, const float* means, const float* scales,
                           const float* rots, const float* opac, const float* sh, int sh_deg, const FrameK* fr,
                           const uint32_t* cell_ntiles, GRec* recs, uint64_t* grect, uint32_t* gdepth,
-                          uint32_t* gntiles);
+                          uint32_t* gntiles, bool overlapped = false);
 
 // Exclusive scan of n u32 values (in[i], or in[idx[i]] when idx is set);
 // *total receives the sum.  status needs scan_status_words(n) 64-bit words;

@@ -178,18 +178,16 @@ __global__ __launch_bounds__(256) void k_cell_preprocess(int N, const float* __r
     v_out[n] = v;
 }
 
-// a2: one thread per Gaussian.  In Duplex mode only members of cells that
-// survived a1 are projected (cell_ntiles != null); every Gaussian gets its
-// packed pixel rectangle (kEmptyRect when culled), projected ones a GRec.
-// In alpha mode (cell_ntiles == null) it also writes the depth key bits and
-// tile count used for per-Gaussian keys.
-__global__ __launch_bounds__(256) void k_gauss_project(
-    int M, int K, const float* __restrict__ means, const float* __restrict__ scales,
+// a2 for Gaussian g.  In Duplex mode only members of cells that survived a1
+// are projected (cell_ntiles != null); every Gaussian gets its packed pixel
+// rectangle (kEmptyRect when culled), projected ones a GRec.  In alpha mode
+// (cell_ntiles == null) it also writes the depth key bits and tile count
+// used for per-Gaussian keys.
+__device__ inline void gauss_project_one(
+    int g, int M, int K, const float* __restrict__ means, const float* __restrict__ scales,
     const float* __restrict__ rots, const float* __restrict__ opac, const float* __restrict__ sh, int sh_deg,
     const FrameK* __restrict__ fr, const uint32_t* __restrict__ cell_ntiles, GRec* __restrict__ recs,
     uint64_t* __restrict__ grect, uint32_t* __restrict__ gdepth, uint32_t* __restrict__ gntiles) {
-    int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= M) return;
     const CamK k = fr->k;
     const OptK o = fr->o;
     if (cell_ntiles && cell_ntiles[g / K] == 0) {
@@ -269,6 +267,20 @@ __global__ __launch_bounds__(256) void k_gauss_project(
     recs[g] = e;
 }
 
+// Grid-stride over the Gaussians.  When the projection runs beside the cell
+// sort (on a second stream) its grid is capped, so that the sort's small
+// latency-bound grids still find free CUs.
+constexpr int kOverlapProjectBlocks = 1024;
+
+__global__ __launch_bounds__(256) void k_gauss_project(
+    int M, int K, const float* __restrict__ means, const float* __restrict__ scales,
+    const float* __restrict__ rots, const float* __restrict__ opac, const float* __restrict__ sh, int sh_deg,
+    const FrameK* __restrict__ fr, const uint32_t* __restrict__ cell_ntiles, GRec* __restrict__ recs,
+    uint64_t* __restrict__ grect, uint32_t* __restrict__ gdepth, uint32_t* __restrict__ gntiles) {
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < M; g += gridDim.x * blockDim.x)
+        gauss_project_one(g, M, K, means, scales, rots, opac, sh, sh_deg, fr, cell_ntiles, recs, grect, gdepth, gntiles);
+}
+
 void launch_cell_preprocess(hipStream_t st, int N, const float* pos, const float* scale, const float* rot,
                             const float* vsh, int vdeg, const FrameK* fr, uint32_t* depth_bits,
                             uint64_t* prect, uint32_t* ntiles, float* v) {
@@ -280,9 +292,10 @@ void launch_cell_preprocess(hipStream_t st, int N, const float* pos, const float
 void launch_gauss_project(hipStream_t st, int M, int K, const float* means, const float* scales,
                           const float* rots, const float* opac, const float* sh, int sh_deg, const FrameK* fr,
                           const uint32_t* cell_ntiles, GRec* recs, uint64_t* grect, uint32_t* gdepth,
-                          uint32_t* gntiles) {
+                          uint32_t* gntiles, bool overlapped) {
     if (M <= 0) return;
-    hipLaunchKernelGGL(k_gauss_project, dim3((M + 255) / 256), dim3(256), 0, st, M, K, means, scales, rots, opac,
+    const int blocks = (M + 255) / 256, cap = overlapped ? kOverlapProjectBlocks : blocks;
+    hipLaunchKernelGGL(k_gauss_project, dim3(blocks < cap ? blocks : cap), dim3(256), 0, st, M, K, means, scales, rots, opac,
                        sh, sh_deg, fr, cell_ntiles, recs, grect, gdepth, gntiles);
 }
 
