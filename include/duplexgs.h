@@ -25,7 +25,12 @@
  *     context, its workspace and its streams' work.  Nothing is retained past
  *     a call except what the context documents (the last frame's state).
  *   - Every call enqueues work on the context's stream and returns without a
- *     host synchronisation, unless its comment says it synchronises.
+ *     host synchronisation, unless its comment says it synchronises.  A
+ *     Duplex frame also runs part of its work (the projection of the cells'
+ *     Gaussians) on a second stream the context owns: it starts after the
+ *     frame's first kernels on the context's stream and is joined back
+ *     before the frame's last kernel there, so the frame is ordered on the
+ *     context's stream like a single-stream one (also under graph capture).
  *   - Errors that the host can see return at once and enqueue nothing.
  *     Errors only the device can see (key capacity overflow, a look-back wait
  *     that timed out) set a device flag that dgs_sync / dgs_get_stats report.
@@ -266,7 +271,8 @@ dgs_status dgs_render_neural(dgs_ctx ctx, const dgs_neural_scene* scene, const d
 dgs_status dgs_read_decoded(dgs_ctx ctx, float* means, float* scales, float* rots, float* opacities, float* colors);
 
 /* Stage timing.  While enabled, every render records HIP events on the
- * context stream at the boundaries of its stages:
+ * context stream at the boundaries of its stages (and runs all of a frame on
+ * that stream, so the stages do not overlap):
  *   0 cell preprocess (or nothing in alpha mode), 1 Gaussian projection,
  *   2 depth sort of the primitives, 3 scan + key emission, 4 radix sort of
  *   the keys on their tile bits, 5 tile ranges + compositor work queue,
