@@ -397,6 +397,25 @@ def test_render_is_deterministic(R, c1):
     assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("mode", ["duplex", "lcwsr", "alpha"])
+def test_one_stream_and_two_stream_frames_are_identical(R, c1, mode):
+    """With stage timing on a frame runs on one stream; off, the member
+    projection runs on a second stream beside the cell sort.  Both must give
+    the same bits in every output, frame after frame."""
+    from paper_2508_03180_amd import _capi
+    cams = scenes.orbit_cameras(60, 1920, 1080)
+    ds = upload(c1)
+    opts = dict(mode=mode, tau=8.0) if mode == "lcwsr" else dict(mode=mode)
+    for i in (3, 29):
+        _capi.dgs_set_timing(R.ctx, 1)
+        a = {k: v.clone() for k, v in R.render(ds, cams[i], **opts).items()}
+        _capi.dgs_set_timing(R.ctx, 0)
+        b = R.render(ds, cams[i], **opts)
+        for k in ("color", "D", "T", "last"):
+            assert torch.equal(a[k], b[k]), (mode, i, k)
+    _capi.dgs_get_timing(R.ctx)
+
+
 def test_stats_counters_match_oracle(R):
     s = scenes.make_tiny_scene(0)
     cam = scenes.tiny_camera()
