@@ -116,6 +116,7 @@ public:
             }
             s.hinfo[0] = s.hinfo[1] = 0;
             dgs_status st = dgs_create(device_, s.stream, &s.ctx);
+            if (st == DGS_OK) s.ctx->two_streams = false;  // the slots overlap whole frames
             if (st != DGS_OK) {
                 err = "context creation failed";
                 return st;
