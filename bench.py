@@ -50,12 +50,12 @@ BYTES_PROJECT_SH3 = 12 + 12 + 16 + 4 + 192 + 48 + 8
 
 # HBM traffic of one Duplex compositor launch on this workload, from two
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) scaled by a 1 GiB copy
-# kernel's reading (profiles/composite_traffic_1080p_1M_pmc.md): 205.74 MB
-# read + 51.53 MB written.  Valid for the compositor source it was taken
+# kernel's reading (profiles/composite_traffic_1080p_1M_pmc.md): 214.77 MB
+# read + 51.44 MB written.  Valid for the compositor source it was taken
 # on; reported as null once that source changes.
-COMPOSITE_TRAFFIC_BYTES = 205.735e6 + 51.527e6
+COMPOSITE_TRAFFIC_BYTES = 214.773e6 + 51.443e6
 COMPOSITE_TRAFFIC_SOURCES = {
-    "paper_2508_03180_amd/csrc/composite.hip": "1a8065b268c3faa2db59e45b89b313ef71b3d5e03fa42b139da7a24943392603",
+    "paper_2508_03180_amd/csrc/composite.hip": "8c05922bec5a5943a255d3d2c3de01fbdc98313fc4707da848d210410ccb2e92",
     "paper_2508_03180_amd/csrc/common.h": "fbc33ccd81363d9fc045c47e1ff3c270d76a413fd2ab6e00ca8ba68037eed22f",
 }
 
