@@ -336,6 +336,14 @@ dgs_status dgs_create(int device, void* hip_stream, dgs_ctx* out) {
         dgs_destroy(c);
         return DGS_ERR_OOM;
     }
+    // the frame's second stream, created here so that no frame (a captured
+    // one included) has to create it
+    if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+        dgs_destroy(c);
+        return DGS_ERR_DEVICE;
+    }
     hipMemsetAsync(c->misc, 0, 16 * sizeof(uint32_t), c->stream);
     hipMemsetAsync(c->dev_err, 0, sizeof(int), c->stream);
     hipMemsetAsync(c->counters, 0, 4 * sizeof(unsigned long long), c->stream);
@@ -469,21 +477,6 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     const uint32_t cap = (uint32_t)c->cap_keys;
     hipStream_t q = c->stream;
     const bool overlap = cells && !c->timing && c->two_streams;
-    if (overlap && !c->aux) {  // first two-stream frame: its stream and events, all or none
-        hipStream_t st2 = nullptr;
-        hipEvent_t e1 = nullptr, e2 = nullptr;
-        if (hipStreamCreateWithFlags(&st2, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&e1, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&e2, hipEventDisableTiming) != hipSuccess) {
-            if (st2) hipStreamDestroy(st2);
-            if (e1) hipEventDestroy(e1);
-            if (e2) hipEventDestroy(e2);
-            return fail(c, DGS_ERR_DEVICE, "second stream or its events could not be created");
-        }
-        c->aux = st2;
-        c->ev_fork = e1;
-        c->ev_join = e2;
-    }
 
     StageMarks sm(c);
     {

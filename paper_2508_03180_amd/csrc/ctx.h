@@ -16,8 +16,8 @@ struct dgs_ctx_s {
 
     // second stream of the frame: the Gaussian projection runs on it while
     // the cell sort runs on `stream` (fork after the cell preprocess, join
-    // before the compositor); created at the first frame that uses it.  The
-    // server turns it off: its slots already overlap whole frames.
+    // before the compositor).  The server turns it off: its slots already
+    // overlap whole frames.
     bool two_streams = true;
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
