@@ -43,6 +43,16 @@ FLOP_DUPLEX_MEMBER = 11
 FLOP_DUPLEX_CELL = 10
 FLOP_ALPHA_HIT = 9
 
+def sort_traffic(prims, keys, tiles):
+    """Algorithmic bytes of the two-stage sort: depth keys written (key and
+    value, 8 B per primitive), four 8-bit passes over them (16 B read and
+    written per primitive and pass), and the passes over the (tile, depth)
+    keys on their tile bits (u64 key + u32 value read and written: 24 B per
+    key and pass)."""
+    tile_passes = (max(1, (tiles - 1).bit_length()) + 7) // 8
+    return prims * (8 + 4 * 16) + keys * 24 * tile_passes
+
+
 # algorithmic bytes of the Gaussian projection, per projected Gaussian:
 # reads mean 12, scales 12, quaternion 16, opacity 4, SH (deg 3) 192,
 # writes the 48-byte record and the 8-byte packed rectangle
@@ -422,6 +432,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     W, H, NF = 1920, 1080, 60
+    TILES = ((W + 15) // 16) * ((H + 15) // 16)
     scene = scenes.make_mid_scene(1)
     cams = scenes.orbit_cameras(NF, W, H)
     r = Renderer(0)
@@ -518,7 +529,10 @@ def main():
                  "keys_mean": float(np.mean(keys_alpha)),
                  "composite_tflops": round(flops_a / (comp_a * 1e-3) / 1e12, 3),
                  "sort_ms": round(st_alpha["depth_sort"] + st_alpha["tile_sort"], 4),
-                 "sort_keys_per_s": round(cnt_a["keys"] / ((st_alpha["depth_sort"] + st_alpha["tile_sort"]) * 1e-3), 1)}
+                 "sort_keys_per_s": round(cnt_a["keys"] / ((st_alpha["depth_sort"] + st_alpha["tile_sort"]) * 1e-3), 1),
+                 "sort_hbm_frac": round(sort_traffic(ds.M, cnt_a["keys"], TILES)
+                                        / ((st_alpha["depth_sort"] + st_alpha["tile_sort"]) * 1e-3)
+                                        / (PEAK_HBM_GBS * 1e9), 4)}
 
     # roofline of the dominant kernel, the Duplex compositor (plain FP32 ALU)
     comp_ms = st_dup["composite"]
@@ -570,6 +584,8 @@ def main():
         "key_reduction_vs_alpha": None if alpha is None else round(1 - np.mean(keys_dup) / alpha["keys_mean"], 4),
         "sort_ms": round(st_dup["depth_sort"] + st_dup["tile_sort"], 4),
         "sort_keys_per_s": round(cnt["keys"] / ((st_dup["depth_sort"] + st_dup["tile_sort"]) * 1e-3), 1),
+        "sort_hbm_frac": round(sort_traffic(ds.N, cnt["keys"], TILES) / ((st_dup["depth_sort"] + st_dup["tile_sort"]) * 1e-3)
+                               / (PEAK_HBM_GBS * 1e9), 4),
         "projection_hbm_gbs": round(proj_gbs, 1),
         "projection_hbm_frac": round(proj_gbs / PEAK_HBM_GBS, 4),
         "termination_ratio": round(1 - cnt["n_rendered"] / max(cnt["n_val"], 1), 4),
