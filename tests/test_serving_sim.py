@@ -41,16 +41,18 @@ def sim_server(slots=4, graphs=True, budget=0, fixed=0.0, per_mpx=0.01, keys_per
 
 def bytes_for(prims, gauss, keys, tiles):
     """Workspace bytes of a context at these capacities (the library's
-    accounting: 24 B per primitive + 8 B per 2048-primitive scan partition,
-    56 B per Gaussian, 24 B per key + 256 x 8 B per 4096-key partition,
-    24 B per tile)."""
+    accounting: 40 B per primitive (depth, rectangle, tile count, offset, v,
+    and the depth sort's keys and values twice) + 8 B per 2048-primitive scan
+    partition (+ 8) + 256 x 8 B per 1024-primitive sort partition, 56 B per
+    Gaussian, 24 B per key + 256 x 8 B per 1024-key sort partition, 24 B per
+    tile)."""
     b = 0
     if prims:
-        b += prims * 24 + ((prims + 2047) // 2048 + 1) * 8
+        b += prims * 40 + ((prims + 2047) // 2048 + 1) * 8 + ((prims + 1023) // 1024) * 256 * 8
     if gauss:
         b += gauss * 56
     if keys:
-        b += keys * 24 + ((keys + 4095) // 4096) * 256 * 8
+        b += keys * 24 + ((keys + 1023) // 1024) * 256 * 8
     if tiles:
         b += tiles * 24
     return b
