@@ -612,8 +612,9 @@ dgs_status dgs_render_backward(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
         hipStream_t q = c->stream;
         launch_fill_u32(q, (uint32_t*)c->g2d, 0u, kG2dRow * (size_t)M);
         launch_fill_u32(q, (uint32_t*)c->gv, 0u, (size_t)N);
-        launch_fill_u32(q, c->misc + 11, 0u, 2);
-        launch_tile_order(q, c->ranges, tiles, kSplitLen, c->tile_order, c->misc + 11);
+        // the forward's work queue (same ranges, same split) is still in
+        // tile_order with its item count in misc[12]: rewind its head only
+        launch_fill_u32(q, c->misc + 11, 0u, 1);
         launch_set_frame(q, FrameK{k, o, fwd->color, fwd->weight_sum, fwd->final_T, fwd->last}, c->frame);
         BwdArgs a;
         a.ranges = c->ranges;
