@@ -272,6 +272,28 @@ def test_ragged_image_and_opaque_scene(R):
     assert (ref["T"] < 1e-4).mean() > 0.05
 
 
+@pytest.mark.parametrize("size", [(16, 16), (13, 9), (1, 1), (17, 16)])
+@pytest.mark.parametrize("mode", ["duplex", "alpha"])
+def test_single_tile_and_tiny_images(R, size, mode):
+    """One tile (no tile bits: the key sort has no pass and the lists stay
+    where the emission put them, in depth order), a single pixel, and two
+    tiles: lists bit-exact and pixels against the oracle."""
+    w, h = size
+    s = scenes.make_tiny_scene(1, n_cells=400, K=4)
+    base = scenes.tiny_camera()
+    cam = scenes.pinhole(base["viewmat"], w, h, fov_x_deg=12.0)
+    out = R.render(upload(s), cam, mode=mode)
+    ref = oracle.render(s, cam, mode=mode)
+    check_image(out, ref)
+    tiles = ((w + 15) // 16) * ((h + 15) // 16)
+    keys, vals, ranges = R.read_lists(tiles)
+    d = oracle.cells_discrete(s, cam) if mode == "duplex" else oracle.gauss_discrete(s, cam)
+    ids, _, oranges = oracle.build_lists(d["visible"], d["depth_bits"], d["rect"], w, h)
+    assert len(ids) > 0
+    np.testing.assert_array_equal(vals.cpu().numpy(), ids)
+    np.testing.assert_array_equal(ranges.cpu().numpy(), oranges)
+
+
 def test_k1_duplex_equals_alpha_blending_on_gpu(R):
     """K = 1, proxy = its Gaussian, kappa = 3, v = 1: C D (Duplex) equals the
     alpha-blended colour on black and D = 1 - T."""
