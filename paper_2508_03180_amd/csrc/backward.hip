@@ -82,12 +82,16 @@ struct BRec {
     uint32_t wx, wy;
 };
 
-// log2(sigma G') with exactly the forward's operations, so every gate
-// decision (box, alpha_min) and every alpha is reproduced bit for bit.
+// lo + ca dx^2 + cb dx dy + cc dy^2 in the forward compositor's operations.
+// With lo = log2 sigma + log2 v (the forward's staged record) this is the
+// forward's gate power log2(v sigma G'), reproduced bit for bit with its
+// alpha_min threshold log2 alpha_min + log2 v, so every gate decision (box,
+// alpha_min) is the forward's; minus log2 v it is log2(sigma G') for the
+// gradients (continuous: the extra rounding does not matter there).
 // Outside the box's columns (inx false) the power is -inf, which the
 // alpha_min test rejects as the forward's box test does.
-__device__ inline float brec_power(const BRec& e, float dx, float dy, bool inx) {
-    const float t0 = inx ? fmaf(e.ca * dx, dx, e.lo) : -INFINITY;
+__device__ inline float brec_power(const BRec& e, float lo, float dx, float dy, bool inx) {
+    const float t0 = inx ? fmaf(e.ca * dx, dx, lo) : -INFINITY;
     const float t1 = e.cb * dx;
     return fmaf(dy, fmaf(e.cc, dy, t1), t0);
 }
@@ -204,17 +208,19 @@ __device__ inline void duplex_tile_bwd(const BwdArgs& a, int tile, int s0, int l
             const int p = lo_c + c;  // list position (0-based) of this cell
             uint32_t mj[NS], mm = 0;
             bool act[NS], anyact = false;
-            float thj[NS];  // alpha_min threshold, +inf where the pixel does not reach this cell
+            float thj[NS];  // gate threshold, +inf where the pixel does not reach this cell
+            const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v_lane), base));
+            const float lv = fold_log2_weight(v);  // as the forward stages it
+            const float thc = th + lv;
 #pragma unroll
             for (int j = 0; j < NS; j++) {
                 mj[j] = (uint32_t)(Bm[j] >> base) & kmask;
                 mm |= mj[j];
                 act[j] = p < last[j];
-                thj[j] = act[j] ? th : INFINITY;
+                thj[j] = act[j] ? thc : INFINITY;
                 anyact = anyact || act[j];
             }
             if (!mm || !__any(anyact)) continue;  // no member touches the owned rows / no pixel reaches the cell
-            const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v_lane), base));
             const uint32_t cell = a.vals[start + p];
             // pass 1: cell totals at each pixel (same decisions as the forward)
             float A0[NS], A1[NS], A2[NS], Bs[NS], P[NS];
@@ -226,14 +232,16 @@ __device__ inline void duplex_tile_bwd(const BwdArgs& a, int tile, int s0, int l
                 const uint32_t rx = (uint32_t)(px - e.x0);
                 const bool inx = rx <= e.wx;
                 const float dx = (float)(int)rx + e.ox;
+                const float lof = e.lo + lv;
                 const uint32_t ry0 = (uint32_t)(py0 - e.y0);
+                const float dy0 = (float)(int)ry0 + e.oy;
 #pragma unroll
                 for (int j = 0; j < NS; j++) {
                     const uint32_t ry = ry0 + 4u * j;
-                    const float dy = (float)(int)ry + e.oy;
-                    const float pw = brec_power(e, dx, dy, inx);
-                    if ((ry <= e.wy) & (pw >= thj[j])) {
-                        const float al = fminf(amax, __builtin_amdgcn_exp2f(pw));
+                    const float dy = j ? dy0 + 4.0f * j : dy0;  // as the forward forms it
+                    const float pwv = brec_power(e, lof, dx, dy, inx);  // log2(v sigma G')
+                    if ((ry <= e.wy) & (pwv >= thj[j])) {
+                        const float al = fminf(amax, __builtin_amdgcn_exp2f(pwv - lv));
                         A0[j] = fmaf(al, e.r, A0[j]); A1[j] = fmaf(al, e.g, A1[j]); A2[j] = fmaf(al, e.b, A2[j]);
                         Bs[j] += al;
                         P[j] = fmaf(-P[j], v * al, P[j]);
@@ -266,7 +274,9 @@ __device__ inline void duplex_tile_bwd(const BwdArgs& a, int tile, int s0, int l
                 const uint32_t rx = (uint32_t)(px - e.x0);
                 const bool inx = rx <= e.wx;
                 const float dx = (float)(int)rx + e.ox;
+                const float lof = e.lo + lv;
                 const uint32_t ry0 = (uint32_t)(py0 - e.y0);
+                const float dy0 = (float)(int)ry0 + e.oy;
                 // dL/dp per pixel (gp) enters the mean, conic and sigma
                 // gradients only through gp, gp dy and gp dy^2 (dx is the
                 // lane's constant for this member), so the lane sums those
@@ -276,11 +286,11 @@ __device__ inline void duplex_tile_bwd(const BwdArgs& a, int tile, int s0, int l
 #pragma unroll
                 for (int j = 0; j < NS; j++) {
                     const uint32_t ry = ry0 + 4u * j;
-                    const float dy = (float)(int)ry + e.oy;
-                    const float pw = brec_power(e, dx, dy, inx);
-                    if ((ry <= e.wy) & (pw >= thj[j])) {
+                    const float dy = j ? dy0 + 4.0f * j : dy0;
+                    const float pwv = brec_power(e, lof, dx, dy, inx);
+                    if ((ry <= e.wy) & (pwv >= thj[j])) {
                         anyhit = true;
-                        const float sg = __builtin_amdgcn_exp2f(pw);  // sigma G'
+                        const float sg = __builtin_amdgcn_exp2f(pwv - lv);  // sigma G'
                         const float al = fminf(amax, sg);
                         const float om = 1.0f - v * al;
                         const float Pom = dLdP[j] * P[j] * __builtin_amdgcn_rcpf(om);  // dL/dP * P / (1 - v al)

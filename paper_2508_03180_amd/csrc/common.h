@@ -63,6 +63,11 @@ struct __align__(16) GRec {
 };
 static_assert(sizeof(GRec) == 48, "GRec layout");
 
+// log2 of a cell weight v in [0, 1] as the Duplex compositor folds it into
+// its members' log2 sigma (forward and backward alike), floored at -126 so
+// that v = 0 stays finite: a weight that small contributes nothing.
+__device__ inline float fold_log2_weight(float v) { return fmaxf(__builtin_amdgcn_logf(v), -126.0f); }
+
 // Look-back status words carry a 30-bit epoch (never 0) derived from a
 // device-side frame counter (bumped by the per-frame clear kernel) and the
 // pass index j < 16, so status buffers are zeroed once at allocation and

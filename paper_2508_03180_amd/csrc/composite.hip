@@ -34,7 +34,7 @@ constexpr int kWaves = 4;  // tiles per workgroup
 
 struct Chunk {
     float4 r0, r1, r2;  // this lane's record
-    float v;            // v of the cell whose first member is this lane
+    float v;            // v of this lane's cell (Duplex walks)
     bool ok;
 };
 
@@ -51,7 +51,7 @@ __device__ inline void load_chunk(const CompositeArgs& a, uint32_t pos, int nrec
         const int c = lane / K, k = lane - c * K;
         const uint32_t cell = a.vals[pos + c];
         g = cell * K + k;
-        q.v = k == 0 ? a.cell_v[cell] : 0.0f;
+        q.v = a.cell_v[cell];
     } else {
         g = a.vals[pos + lane];
         q.v = 0.0f;
@@ -206,6 +206,9 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
     bool alive = true;
     for (uint32_t pos = start; pos < end && (alive || STATS);) {
         const int nch = (int)min((uint32_t)cpc, end - pos);
+        // Duplex: log2 v goes into the record's log2 sigma, so that the
+        // walk computes v alpha directly (the alpha_min test moves by log2 v)
+        if (!LC) q.r1.y += fold_log2_weight(q.v);
         store_chunk(lds, lane, q);
         uint64_t B4[4];
         strip_ballots(q, tx0, ty0, B4);
@@ -223,12 +226,18 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
                 any |= mj[j];
             }
             if (!any) continue;  // no member of this cell touches the owned strips
+            const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cv), base));
+            // Duplex: every record of this cell holds log2 sigma + log2 v, so
+            // its power pw is log2(v sigma G'); alpha >= alpha_min becomes
+            // pw >= th + log2 v and min(alpha_max, .) becomes min(v alpha_max, .)
+            const float thc = LC ? th : th + fold_log2_weight(v);
+            const float vmax = LC ? amax : v * amax;
             if constexpr (!LC) {
                 bool anyact = false;
 #pragma unroll
                 for (int j = 0; j < NS; j++) {
                     act[j] = act[j] && !(T[j] < eps);  // cell-level termination
-                    thj[j] = act[j] ? th : INFINITY;
+                    thj[j] = act[j] ? thc : INFINITY;
                     anyact = anyact || act[j];
                 }
                 if (!STATS && !__any(anyact)) {
@@ -236,12 +245,12 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
                     break;
                 }
             }
-            const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cv), base));
             // the cell's weight is fixed before its members: w alpha c and
-            // w alpha go straight into N and D (no per-cell sums A, B)
+            // w alpha go straight into N and D (no per-cell sums A, B); in the
+            // Duplex walk al below is v alpha and w alpha = T (v alpha)
             float wj[NS], P[NS], Bs[NS];
 #pragma unroll
-            for (int j = 0; j < NS; j++) { wj[j] = LC ? v : v * T[j]; P[j] = 1.0f; Bs[j] = 0.0f; }
+            for (int j = 0; j < NS; j++) { wj[j] = LC ? v : T[j]; P[j] = 1.0f; Bs[j] = 0.0f; }
             for (uint32_t rem = any; rem; rem &= rem - 1) {
                 const int k = __builtin_ctz(rem);
                 const RecView e = read_rec(lb, base + k);
@@ -253,17 +262,18 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
                 const float t0 = inx ? fmaf(e.ca * dx, dx, e.lo) : -INFINITY;
                 const float t1 = e.cb * dx;
                 const uint32_t ry0 = (uint32_t)(py0 - e.y0);
+                const float dy0 = (float)(int)ry0 + e.oy;
                 // every strip is evaluated (strips the member misses fail the
                 // row test in every lane): no scalar test per strip
 #pragma unroll
                 for (int j = 0; j < NS; j++) {
                     const uint32_t ry = ry0 + 4u * j;
-                    const float dy = (float)(int)ry + e.oy;
+                    const float dy = j ? dy0 + 4.0f * j : dy0;  // the row 4j below, without a conversion
                     const float pw = fmaf(dy, fmaf(e.cc, dy, t1), t0);
                     const bool iny = ry <= e.wy;
                     const bool hit = iny & (pw >= thj[j]);  // false once the pixel has terminated
                     if (STATS) {
-                        const bool val = iny & (pw >= th);
+                        const bool val = iny & (pw >= thc);
                         cn.val += val;
                         cn.rend += val && act[j];
                         cn.box += inx && iny && act[j];
@@ -271,13 +281,14 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
                     // no branch: a pixel that is not hit adds alpha = 0, which
                     // leaves N, D and P exactly unchanged (the four strips then
                     // interleave without exec-mask changes)
-                    const float al = hit ? fminf(amax, __builtin_amdgcn_exp2f(pw)) : 0.0f;
+                    // min(vmax, 2^pw) as a clamp to [0, vmax] (2^pw >= 0)
+                    const float al = hit ? __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(pw), 0.0f, vmax) : 0.0f;
                     const float wa = wj[j] * al;
                     N0[j] = fmaf(wa, e.r, N0[j]);
                     N1[j] = fmaf(wa, e.g, N1[j]);
                     N2[j] = fmaf(wa, e.b, N2[j]);
                     D[j] += wa;
-                    if constexpr (!LC) P[j] = fmaf(-P[j], v * al, P[j]);
+                    if constexpr (!LC) P[j] = fmaf(-P[j], al, P[j]);
                     else Bs[j] += al;
                 }
             }
@@ -368,13 +379,14 @@ __device__ inline void alpha_tile(const CompositeArgs& a, const FrameView& f, in
             const float t0 = inx ? fmaf(e.ca * dx, dx, e.lo) : -INFINITY;  // as in the Duplex walk
             const float t1 = e.cb * dx;
             const uint32_t ry0 = (uint32_t)(py0 - e.y0);
+            const float dy0 = (float)(int)ry0 + e.oy;
 #pragma unroll
             for (int j = 0; j < NS; j++) {
                 // termination before each Gaussian (T only changes on a hit,
                 // so testing it for strips the Gaussian misses changes nothing)
                 act[j] = act[j] && !(T[j] < eps);
                 const uint32_t ry = ry0 + 4u * j;
-                const float dy = (float)(int)ry + e.oy;
+                const float dy = j ? dy0 + 4.0f * j : dy0;
                 const float pw = fmaf(dy, fmaf(e.cc, dy, t1), t0);
                 const bool iny = ry <= e.wy;
                 const bool hit = iny & (pw >= th);

@@ -112,6 +112,32 @@ def test_backward_opaque_scene_with_termination(R):
     check(run_case(R, s, cam, np.ones((64, 64)), seed=2))
 
 
+def test_zero_weight_cells_forward_and_backward(R):
+    """Cells whose weight v underflows to 0 in binary32 (logit -282) add
+    nothing and leave the gates of every other cell unchanged; the forward
+    and the backward stay finite.  Pixels whose weight sum D the oracle puts
+    below 1e-3 are left out of the comparison: where only such cells
+    contribute, C = N / D divides binary64 weights of ~1e-123 (the oracle's
+    colour) while binary32 has D = 0 (the background)."""
+    import oracle
+    from paper_2508_03180_amd.renderer import DeviceScene
+    s = small_scene()
+    v = s["cell_v_sh"].copy()
+    v[::3, 0] = -1000.0
+    s["cell_v_sh"] = v
+    cam = scenes.tiny_camera(64, 64)
+    out = R.render(DeviceScene.from_numpy(s, "cuda:0"), cam)
+    col = out["color"].permute(1, 2, 0).reshape(-1, 3).double().cpu().numpy()
+    assert np.isfinite(col).all()
+    ref = oracle.render(s, cam)
+    keep = ref["D"] >= 1e-3
+    assert keep.mean() > 0.3
+    err = oracle.admissible_max_err(col, ref)[keep]
+    assert np.isfinite(err).mean() >= 0.999
+    assert np.nanmax(err) <= 2e-4
+    check(run_case(R, s, cam, keep.reshape(64, 64).astype(np.float64), seed=5))
+
+
 def test_backward_1080p_window(R):
     """Full-size 1M-Gaussian scene at 1920x1080 (the benchmark's launch
     configuration); the oracle takes the loss on a 48x48 window."""
