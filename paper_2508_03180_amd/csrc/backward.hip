@@ -174,6 +174,7 @@ __device__ inline void duplex_tile_bwd(const BwdArgs& a, int tile, int s0, int l
     // the wave walks from its largest `last` down to the first cell
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) maxlast = max(maxlast, __shfl_xor(maxlast, o, 64));
+    maxlast = __builtin_amdgcn_readfirstlane(maxlast);  // uniform: scalar loop control
     for (int hi = maxlast; hi > 0;) {
         // chunk of cells [lo_c, hi) (list positions relative to start)
         const int nch = hi < cpc ? hi : cpc;
@@ -342,7 +343,9 @@ __global__ __launch_bounds__(256) void k_composite_bwd(BwdArgs a) {
     for (;;) {
         uint32_t t = 0;
         if (lane == 0) t = atomicAdd(a.queue, 1u);
-        t = (uint32_t)__shfl((int)t, 0, 64);
+        // lane 0's ticket in a scalar register: the item, its tile and its
+        // strip are then wavefront-uniform, and so is all loop control below
+        t = __builtin_amdgcn_readfirstlane(t);
         if (t >= nitems) break;
         const uint32_t item = a.order[t];
         const int tile = (int)(item >> 3), mode = (int)(item & 7u);

@@ -62,8 +62,12 @@ __device__ inline void load_chunk(const CompositeArgs& a, uint32_t pos, int nrec
     q.r2 = p[2];
 }
 
-// Ballots of the strips (bit j: rows 4j..4j+3 of the tile) each lane's record touches.
-__device__ inline void strip_ballots(const Chunk& q, int tx0, int ty0, uint64_t* B) {
+// Ballots of the owned strips each lane's record touches: B[j] for strip j
+// (rows 4j..4j+3 of the tile) when the wavefront owns the whole tile
+// (NS = 4), B[0] for strip s0 alone when it owns one strip (NS = 1; s0 is
+// wavefront-uniform, so the ballot stays in scalar registers).
+template <int NS>
+__device__ inline void strip_ballots(const Chunk& q, int tx0, int ty0, int s0, uint64_t* B) {
     uint32_t sm = 0;
     if (q.ok) {
         const int x0 = __float_as_int(q.r2.y), y0 = __float_as_int(q.r2.z);
@@ -71,24 +75,14 @@ __device__ inline void strip_ballots(const Chunk& q, int tx0, int ty0, uint64_t*
         const int x1 = x0 + (int)(wxy & 0xffffu), y1 = y0 + (int)(wxy >> 16);
         if (x0 <= tx0 + 15 && x1 >= tx0) {
 #pragma unroll
-            for (int j = 0; j < 4; j++)
-                if (y0 <= ty0 + 4 * j + 3 && y1 >= ty0 + 4 * j) sm |= 1u << j;
+            for (int j = 0; j < NS; j++) {
+                const int r0 = ty0 + 4 * (NS == 4 ? j : s0);
+                if (y0 <= r0 + 3 && y1 >= r0) sm |= 1u << j;
+            }
         }
     }
 #pragma unroll
-    for (int j = 0; j < 4; j++) B[j] = __ballot((sm >> j) & 1u);
-}
-
-// The owned strips' ballots: all four, or strip s0 (wave-uniform) selected
-// without indexing a register array at run time (which would spill it).
-template <int NS>
-__device__ inline void pick_strips(const uint64_t* B4, int s0, uint64_t* B) {
-    if (NS == 4) {
-#pragma unroll
-        for (int j = 0; j < 4; j++) B[j] = B4[j];
-    } else {
-        B[0] = (s0 & 2) ? ((s0 & 1) ? B4[3] : B4[2]) : ((s0 & 1) ? B4[1] : B4[0]);
-    }
+    for (int j = 0; j < NS; j++) B[j] = __ballot((sm >> j) & 1u);
 }
 
 __device__ inline void store_chunk(GRec* lds, int lane, const Chunk& q) {
@@ -210,10 +204,8 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
         // walk computes v alpha directly (the alpha_min test moves by log2 v)
         if (!LC) q.r1.y += fold_log2_weight(q.v);
         store_chunk(lds, lane, q);
-        uint64_t B4[4];
-        strip_ballots(q, tx0, ty0, B4);
         uint64_t B[NS];
-        pick_strips<NS>(B4, s0, B);
+        strip_ballots<NS>(q, tx0, ty0, s0, B);
         const float cv = q.v;
         const uint32_t next = pos + nch;
         if (next < end) load_chunk(a, next, (int)min((uint32_t)cpc, end - next) * K, K, lane, true, q);
@@ -351,10 +343,8 @@ __device__ inline void alpha_tile(const CompositeArgs& a, const FrameView& f, in
     for (uint32_t pos = start; pos < end && (alive || STATS);) {
         const int n = (int)min(64u, end - pos);
         store_chunk(lds, lane, q);
-        uint64_t B4[4];
-        strip_ballots(q, tx0, ty0, B4);
         uint64_t B[NS], any = 0;
-        pick_strips<NS>(B4, s0, B);
+        strip_ballots<NS>(q, tx0, ty0, s0, B);
 #pragma unroll
         for (int j = 0; j < NS; j++) any |= B[j];
         const uint32_t next = pos + n;
@@ -441,7 +431,9 @@ __global__ __launch_bounds__(256) void k_composite(CompositeArgs a) {
     for (;;) {
         uint32_t t = 0;
         if (lane == 0) t = atomicAdd(a.queue, 1u);
-        t = (uint32_t)__shfl((int)t, 0, 64);
+        // lane 0's ticket in a scalar register: the item, its tile and its
+        // strip are then wavefront-uniform, and so is all loop control below
+        t = __builtin_amdgcn_readfirstlane(t);
         if (t >= nitems) break;
         const uint32_t item = a.order[t];
         const int tile = (int)(item >> 3), mode = (int)(item & 7u);
