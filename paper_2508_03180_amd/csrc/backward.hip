@@ -127,8 +127,9 @@ __device__ inline BRec read_brec(uint32_t lb, int i) {
 }
 
 // Backward of a whole 16x16 tile (NS = 4: lane l holds pixel (l & 15,
-// 4 j + (l >> 4)) of strip j) or of one 16x4 strip s0 (NS = 1), in the
-// forward compositor's layout and with its exact gate arithmetic.  Each
+// 4 j + (l >> 4)) of strip j) or of one 16x8 half (NS = 2, strips s0 and
+// s0 + 1), in the forward compositor's layout and with its exact gate
+// arithmetic.  Each
 // pixel walks back from its own last contributing entry; per member, the
 // lane first sums its pixels' contributions, then the wavefront reduces
 // them once for the tile.
@@ -344,7 +345,7 @@ __global__ __launch_bounds__(256) void k_composite_bwd(BwdArgs a) {
         uint32_t t = 0;
         if (lane == 0) t = atomicAdd(a.queue, 1u);
         // lane 0's ticket in a scalar register: the item, its tile and its
-        // strip are then wavefront-uniform, and so is all loop control below
+        // half are then wavefront-uniform, and so is all loop control below
         t = __builtin_amdgcn_readfirstlane(t);
         if (t >= nitems) break;
         const uint32_t item = a.order[t];
@@ -352,7 +353,7 @@ __global__ __launch_bounds__(256) void k_composite_bwd(BwdArgs a) {
         if (mode == 0)
             duplex_tile_bwd<4>(a, tile, 0, lane, lds);
         else
-            duplex_tile_bwd<1>(a, tile, mode - 4, lane, lds);
+            duplex_tile_bwd<2>(a, tile, 2 * (mode - 2), lane, lds);
     }
 }
 

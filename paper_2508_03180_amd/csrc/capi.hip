@@ -554,7 +554,7 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     a.counters = o.stats ? c->counters : nullptr;
     a.order = c->tile_order;
     a.queue = c->misc + 11;
-    launch_tile_order(q, c->ranges, tiles, kSplitLen, c->tile_order, c->misc + 11);
+    launch_tile_order(q, c->ranges, tiles, cells ? kSplitLenCells : kSplitLenGauss, c->tile_order, c->misc + 11);
     if (overlap) hipStreamWaitEvent(q, c->ev_join, 0);  // the projected members
     sm.mark(6);
     if (mode == DGS_MODE_DUPLEX)

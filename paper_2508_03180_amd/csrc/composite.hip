@@ -15,9 +15,9 @@
 // depth-sorted Gaussians with C += T alpha c, T *= 1 - alpha, plus T bg.
 //
 // Mapping: a wavefront runs without workgroup barriers and owns either a
-// whole 16x16 tile or, for tiles with long lists, one 16x4 strip of it
-// (strip j = rows 4j..4j+3; lane l holds pixel (l & 15, 4j + (l >> 4)) of
-// every strip it owns).  Work items are taken from a queue that lists them
+// whole 16x16 tile or, for tiles with long lists, one 16x8 half of it
+// (strips 2h and 2h + 1, strip j = rows 4j..4j+3; lane l holds pixel
+// (l & 15, 4j + (l >> 4)) of every strip it owns).  Work items are taken from a queue that lists them
 // heaviest first.  The tile list is consumed in
 // chunks of up to 64 Gaussian records (whole cells): each lane loads one
 // record, the wave ballots which strips every record's box touches, and the
@@ -62,10 +62,10 @@ __device__ inline void load_chunk(const CompositeArgs& a, uint32_t pos, int nrec
     q.r2 = p[2];
 }
 
-// Ballots of the owned strips each lane's record touches: B[j] for strip j
-// (rows 4j..4j+3 of the tile) when the wavefront owns the whole tile
-// (NS = 4), B[0] for strip s0 alone when it owns one strip (NS = 1; s0 is
-// wavefront-uniform, so the ballot stays in scalar registers).
+// Ballots of the owned strips each lane's record touches: B[j] for strip
+// s0 + j (rows 4(s0 + j)..4(s0 + j) + 3 of the tile), j < NS; s0 = 0 for a
+// whole tile (NS = 4), 2h for half h (NS = 2).  s0 is wavefront-uniform, so
+// the ballots stay in scalar registers.
 template <int NS>
 __device__ inline void strip_ballots(const Chunk& q, int tx0, int ty0, int s0, uint64_t* B) {
     uint32_t sm = 0;
@@ -76,7 +76,7 @@ __device__ inline void strip_ballots(const Chunk& q, int tx0, int ty0, int s0, u
         if (x0 <= tx0 + 15 && x1 >= tx0) {
 #pragma unroll
             for (int j = 0; j < NS; j++) {
-                const int r0 = ty0 + 4 * (NS == 4 ? j : s0);
+                const int r0 = ty0 + 4 * (s0 + j);
                 if (y0 <= r0 + 3 && y1 >= r0) sm |= 1u << j;
             }
         }
@@ -153,7 +153,8 @@ __device__ inline FrameView frame_view(const FrameK* fr) {
     return f;
 }
 
-// Work item: tile << 3 | mode; mode 0 = all four strips, mode 4 + j = strip j.
+// Work item: tile << 3 | mode; mode 0 = the whole tile (all four strips),
+// mode 2 + h = half h (strips 2h and 2h + 1).
 
 // Statistics counters (STATS only): n_val, n_rendered (the termination ratio
 // 1 - n_rendered / n_val), in-box member evaluations and (pixel, entry) pairs
@@ -162,7 +163,8 @@ struct Counters {
     uint32_t val = 0, rend = 0, box = 0, cellhit = 0;
 };
 
-// The hybrid renderer over one tile (NS = 4) or one strip s0 (NS = 1)
+// The hybrid renderer over one tile (NS = 4) or one half (NS = 2, strips s0
+// and s0 + 1)
 // (Sec. V-A, eq. hybrid_renderer with w_n = v_n T_n and eq. dulpex_T; Sec. V-B
 // termination; Sec. VI-A box gate): cells front to back; a pixel whose
 // transmittance in front of a cell is below eps stops there; inside a cell
@@ -432,7 +434,7 @@ __global__ __launch_bounds__(256) void k_composite(CompositeArgs a) {
         uint32_t t = 0;
         if (lane == 0) t = atomicAdd(a.queue, 1u);
         // lane 0's ticket in a scalar register: the item, its tile and its
-        // strip are then wavefront-uniform, and so is all loop control below
+        // half are then wavefront-uniform, and so is all loop control below
         t = __builtin_amdgcn_readfirstlane(t);
         if (t >= nitems) break;
         const uint32_t item = a.order[t];
@@ -441,13 +443,13 @@ __global__ __launch_bounds__(256) void k_composite(CompositeArgs a) {
             if (mode == 0)
                 alpha_tile<STATS, 4>(a, f, tile, 0, lane, lds, cn);
             else
-                alpha_tile<STATS, 1>(a, f, tile, mode - 4, lane, lds, cn);
+                alpha_tile<STATS, 2>(a, f, tile, 2 * (mode - 2), lane, lds, cn);
         } else {
             constexpr bool LC = MODE == kModeLcwsr;
             if (mode == 0)
                 duplex_tile<STATS, 4, LC>(a, f, tile, 0, lane, lds, cn);
             else
-                duplex_tile<STATS, 1, LC>(a, f, tile, mode - 4, lane, lds, cn);
+                duplex_tile<STATS, 2, LC>(a, f, tile, 2 * (mode - 2), lane, lds, cn);
         }
     }
     if (STATS) {
@@ -458,7 +460,7 @@ __global__ __launch_bounds__(256) void k_composite(CompositeArgs a) {
     }
 }
 
-// Builds the work queue: one item per tile, or one per strip for tiles whose
+// Builds the work queue: one item per tile, or one per half for tiles whose
 // list has at least split_len entries; items are bucketed by
 // floor(log2(estimated cost)) and laid out from costly to cheap (order inside
 // a bucket is arbitrary: it only affects scheduling, never results).
@@ -473,7 +475,7 @@ __global__ __launch_bounds__(1024) void k_tile_order(const uint32_t* __restrict_
     for (int t = tid; t < ntiles; t += blockDim.x) {
         const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
         if (len >= split_len)
-            atomicAdd(&s_cnt[32 - __clz(len / 2)], 4u);  // four strips, each about half a tile's cost
+            atomicAdd(&s_cnt[32 - __clz(len)], 2u);  // two halves, each walking the whole list
         else
             atomicAdd(&s_cnt[32 - __clz(len)], 1u);
     }
@@ -491,8 +493,8 @@ __global__ __launch_bounds__(1024) void k_tile_order(const uint32_t* __restrict_
     for (int t = tid; t < ntiles; t += blockDim.x) {
         const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
         if (len >= split_len) {
-            const uint32_t o = atomicAdd(&s_off[32 - __clz(len / 2)], 4u);
-            for (uint32_t j = 0; j < 4; j++) order[o + j] = ((uint32_t)t << 3) | (4u + j);
+            const uint32_t o = atomicAdd(&s_off[32 - __clz(len)], 2u);
+            for (uint32_t h = 0; h < 2; h++) order[o + h] = ((uint32_t)t << 3) | (2u + h);
         } else {
             order[atomicAdd(&s_off[32 - __clz(len)], 1u)] = (uint32_t)t << 3;
         }

@@ -123,12 +123,15 @@ struct CompositeArgs {
     uint32_t* order;               // [4 * tiles] scratch: heaviest-first work items
     uint32_t* queue;               // [2] scratch: work-queue head, item count
 };
-// Work queue of the compositor (heaviest-first tile / strip items); must
+// Work queue of the compositor (heaviest-first tile / half-tile items); must
 // precede launch_composite_*.  Tiles with at least split_len entries become
-// four strip items (split_len 0: every tile is split).
+// two half-tile items (split_len 0: every tile is split).
 void launch_tile_order(hipStream_t st, const uint32_t* ranges, int tiles, uint32_t split_len, uint32_t* order,
                        uint32_t* queue);
-constexpr uint32_t kSplitLen = 64;
+// Split lengths, measured: lists of cells (each entry K members) and lists
+// of Gaussians.
+constexpr uint32_t kSplitLenCells = 32;
+constexpr uint32_t kSplitLenGauss = 64;
 void launch_composite_duplex(hipStream_t st, const CompositeArgs& a);
 void launch_composite_alpha(hipStream_t st, const CompositeArgs& a);
 // The Duplex walk with LC-WSR cell weights (cell_v holds the weights).
