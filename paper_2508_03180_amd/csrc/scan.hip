@@ -68,7 +68,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_excl(const uint32_t* __re
     for (;;) {
         if (tid == 0) s_part = atomicAdd(ticket, 1u);
         __syncthreads();
-        const int part = (int)s_part;
+        const int part = (int)__builtin_amdgcn_readfirstlane(s_part);  // uniform: scalar loop control
         if (part >= nparts) break;
         const int64_t base = (int64_t)part * kScanPart + (int64_t)tid * kScanItems;
         uint32_t x[kScanItems], sum = 0;

@@ -144,7 +144,7 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const KeyT* __restric
     for (;;) {
         for (int d = tid; d < kSortWaves * 256; d += kSortThreads) (&s_cnt[0][0])[d] = 0;
         __syncthreads();
-        const uint32_t part = s_part;
+        const uint32_t part = __builtin_amdgcn_readfirstlane(s_part);  // uniform: scalar loop control
         if (part >= nparts) break;
         const uint32_t pbase = part * kSortPart;
         const uint32_t wbase = pbase + wave * (kSortItems * 64);
