@@ -60,13 +60,13 @@ BYTES_PROJECT_SH3 = 12 + 12 + 16 + 4 + 192 + 48 + 8
 
 # HBM traffic of one Duplex compositor launch on this workload, from two
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) scaled by a 1 GiB copy
-# kernel's reading (profiles/composite_traffic_1080p_1M_pmc.md): 214.77 MB
-# read + 51.44 MB written.  Valid for the compositor source it was taken
+# kernel's reading (profiles/composite_traffic_1080p_1M_pmc.md): 194.91 MB
+# read + 51.33 MB written.  Valid for the compositor source it was taken
 # on; reported as null once that source changes.
-COMPOSITE_TRAFFIC_BYTES = 214.773e6 + 51.443e6
+COMPOSITE_TRAFFIC_BYTES = 194.914e6 + 51.325e6
 COMPOSITE_TRAFFIC_SOURCES = {
-    "paper_2508_03180_amd/csrc/composite.hip": "8c05922bec5a5943a255d3d2c3de01fbdc98313fc4707da848d210410ccb2e92",
-    "paper_2508_03180_amd/csrc/common.h": "fbc33ccd81363d9fc045c47e1ff3c270d76a413fd2ab6e00ca8ba68037eed22f",
+    "paper_2508_03180_amd/csrc/composite.hip": "e531f61f53757bcbcbaf936880b22cde7dd72e8ced87b380d92bce1e22bc3378",
+    "paper_2508_03180_amd/csrc/common.h": "ee695b63ce970c9d44d9e67504a2b2d021f63d98aa82a96452b6930557202274",
 }
 
 
