@@ -65,7 +65,7 @@ BYTES_PROJECT_SH3 = 12 + 12 + 16 + 4 + 192 + 48 + 8
 # on; reported as null once that source changes.
 COMPOSITE_TRAFFIC_BYTES = 194.914e6 + 51.325e6
 COMPOSITE_TRAFFIC_SOURCES = {
-    "paper_2508_03180_amd/csrc/composite.hip": "e531f61f53757bcbcbaf936880b22cde7dd72e8ced87b380d92bce1e22bc3378",
+    "paper_2508_03180_amd/csrc/composite.hip": "6081cc1731f746f488fa0c7c7efefd4dbc014fc15ad990e8539ba785627aca66",
     "paper_2508_03180_amd/csrc/common.h": "ee695b63ce970c9d44d9e67504a2b2d021f63d98aa82a96452b6930557202274",
 }
 

@@ -17,8 +17,8 @@
 // Mapping: a wavefront runs without workgroup barriers and owns either a
 // whole 16x16 tile or, for tiles with long lists, one 16x8 half of it
 // (strips 2h and 2h + 1, strip j = rows 4j..4j+3; lane l holds pixel
-// (l & 15, 4j + (l >> 4)) of every strip it owns).  Work items are taken from a queue that lists them
-// heaviest first.  The tile list is consumed in
+// (l & 15, 4j + (l >> 4)) of every strip it owns).  Work items are taken
+// from a queue that lists them heaviest first.  The tile list is consumed in
 // chunks of up to 64 Gaussian records (whole cells): each lane loads one
 // record, the wave ballots which strips every record's box touches, and the
 // records go to the wave's private LDS slot, from which they are read as
@@ -187,7 +187,7 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
     const uint32_t lb = lds_base(lds);
 
     float T[NS], N0[NS], N1[NS], N2[NS], D[NS];
-    float thj[NS];  // alpha_min threshold of strip j's pixel, +inf once it has terminated
+    float thj[NS];  // gate threshold of strip j's pixel for the current cell, +inf once it has terminated
     int32_t last[NS];
     bool act[NS];
 #pragma unroll
@@ -273,7 +273,7 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
                         cn.box += inx && iny && act[j];
                     }
                     // no branch: a pixel that is not hit adds alpha = 0, which
-                    // leaves N, D and P exactly unchanged (the four strips then
+                    // leaves N, D and P exactly unchanged (the owned strips then
                     // interleave without exec-mask changes)
                     // min(vmax, 2^pw) as a clamp to [0, vmax] (2^pw >= 0)
                     const float al = hit ? __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(pw), 0.0f, vmax) : 0.0f;
