@@ -138,6 +138,27 @@ def test_zero_weight_cells_forward_and_backward(R):
     check(run_case(R, s, cam, keep.reshape(64, 64).astype(np.float64), seed=5))
 
 
+@pytest.mark.parametrize("seed", [1, 2])
+def test_backward_tiles_at_the_split_length(R, seed):
+    """Gradients of the pixels of tiles whose cell lists are one short of,
+    exactly at and one past the length at which the compositor splits a
+    tile into two half-tile items (32 cells); the backward replays the
+    forward's items."""
+    import oracle
+    s = scenes.make_tiny_scene(seed)
+    cam = scenes.tiny_camera()
+    d = oracle.cells_discrete(s, cam)
+    _, _, ranges = oracle.build_lists(d["visible"], d["depth_bits"], d["rect"], 256, 256)
+    lens = ranges[:, 1] - ranges[:, 0]
+    tiles = np.nonzero((lens >= 31) & (lens <= 33))[0]
+    assert len(tiles) > 0
+    m = np.zeros((256, 256))
+    for t in tiles:
+        ty, tx = divmod(int(t), 16)
+        m[16 * ty:16 * ty + 16, 16 * tx:16 * tx + 16] = 1
+    check(run_case(R, s, cam, m, seed=6))
+
+
 def test_backward_1080p_window(R):
     """Full-size 1M-Gaussian scene at 1920x1080 (the benchmark's launch
     configuration); the oracle takes the loss on a 48x48 window."""

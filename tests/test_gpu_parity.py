@@ -210,6 +210,52 @@ def test_tiny_scene_image_parity(R):
     assert (last[exact] == ref["last"][exact]).mean() > 0.999
 
 
+# The compositor splits a tile whose list has at least 32 cells (64 Gaussians
+# in the per-Gaussian mode) into two half-tile work items.  Tiny scenes 1 and
+# 2 hold tiles whose cell lists are one short of, exactly at and one past 32,
+# and scene 2 tiles with 63 and 64 Gaussians; their pixels, lists and ranges
+# are checked here.
+SPLIT_LEN = {"duplex": 32, "alpha": 64}
+
+
+def split_boundary_pixels(s, cam, mode):
+    if mode == "duplex":
+        d = oracle.cells_discrete(s, cam)
+    else:
+        d = oracle.gauss_discrete(s, cam)
+    W, H = cam["width"], cam["height"]
+    _, _, ranges = oracle.build_lists(d["visible"], d["depth_bits"], d["rect"], W, H)
+    lens = ranges[:, 1] - ranges[:, 0]
+    L = SPLIT_LEN[mode]
+    tiles = np.nonzero((lens >= L - 1) & (lens <= L + 1))[0]
+    TX = (W + 15) // 16
+    mask = np.zeros((H, W), bool)
+    for t in tiles:
+        ty, tx = divmod(int(t), TX)
+        mask[16 * ty:16 * ty + 16, 16 * tx:16 * tx + 16] = True
+    return tiles, lens[tiles], mask.reshape(-1)
+
+
+@pytest.mark.parametrize("seed,mode", [(1, "duplex"), (2, "duplex"), (2, "alpha")])
+def test_tiles_at_the_split_length(R, seed, mode):
+    s = scenes.make_tiny_scene(seed)
+    cam = scenes.tiny_camera()
+    tiles, lens, mask = split_boundary_pixels(s, cam, mode)
+    L = SPLIT_LEN[mode]
+    assert len(tiles) > 0 and lens.min() < L <= lens.max()
+    out = R.render(upload(s), cam, mode=mode)
+    keys, vals, ranges = R.read_lists(256)
+    d = oracle.cells_discrete(s, cam) if mode == "duplex" else oracle.gauss_discrete(s, cam)
+    ids, _, oranges = oracle.build_lists(d["visible"], d["depth_bits"], d["rect"], 256, 256)
+    assert keys.numel() == len(ids)
+    np.testing.assert_array_equal(vals.cpu().numpy(), ids)
+    np.testing.assert_array_equal(ranges.cpu().numpy(), oranges)
+    ref = oracle.render(s, cam, mode=mode)
+    err = oracle.admissible_max_err(flat(out["color"]), ref)[mask]
+    assert np.isfinite(err).mean() >= 0.999
+    assert np.nanmax(err) <= TOL
+
+
 @pytest.mark.parametrize("flags", [dict(v_one=True), dict(no_et=True), dict(bg=(0.2, 0.4, 0.6)),
                                    dict(kappa=3.0), dict(eps=1e-2)])
 def test_tiny_scene_option_parity(R, flags):
