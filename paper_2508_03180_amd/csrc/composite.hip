@@ -189,12 +189,12 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
     float T[NS], N0[NS], N1[NS], N2[NS], D[NS];
     float thj[NS];  // gate threshold of strip j's pixel for the current cell, +inf once it has terminated
     int32_t last[NS];
-    bool act[NS];
+    bool inb[NS];  // the pixel lies in the image
 #pragma unroll
     for (int j = 0; j < NS; j++) {
         T[j] = 1.0f; N0[j] = N1[j] = N2[j] = D[j] = 0.0f; last[j] = 0;
-        act[j] = px < f.W && py0 + 4 * j < f.H;
-        thj[j] = act[j] ? th : INFINITY;
+        inb[j] = px < f.W && py0 + 4 * j < f.H;
+        thj[j] = inb[j] ? th : INFINITY;
     }
 
     Chunk q;
@@ -204,7 +204,15 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
         const int nch = (int)min((uint32_t)cpc, end - pos);
         // Duplex: log2 v goes into the record's log2 sigma, so that the
         // walk computes v alpha directly (the alpha_min test moves by log2 v)
-        if (!LC) q.r1.y += fold_log2_weight(q.v);
+        // per record lane, its cell's gate threshold and weight clamp (read
+        // by the cell loop from the cell's first lane)
+        float cthc = th, cvmax = amax;
+        if (!LC) {
+            const float lv = fold_log2_weight(q.v);
+            q.r1.y += lv;
+            cthc = th + lv;
+            cvmax = q.v * amax;
+        }
         store_chunk(lds, lane, q);
         uint64_t B[NS];
         strip_ballots<NS>(q, tx0, ty0, s0, B);
@@ -224,13 +232,17 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
             // Duplex: every record of this cell holds log2 sigma + log2 v, so
             // its power pw is log2(v sigma G'); alpha >= alpha_min becomes
             // pw >= th + log2 v and min(alpha_max, .) becomes min(v alpha_max, .)
-            const float thc = LC ? th : th + fold_log2_weight(v);
-            const float vmax = LC ? amax : v * amax;
+            const float thc = LC ? th : __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cthc), base));
+            const float vmax = LC ? amax : __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cvmax), base));
+            // a pixel still blends while T >= eps (T never rises, so once
+            // below eps it stays below: no state is carried across cells)
+            bool act[NS];
+#pragma unroll
+            for (int j = 0; j < NS; j++) act[j] = LC ? inb[j] : inb[j] && !(T[j] < eps);
             if constexpr (!LC) {
                 bool anyact = false;
 #pragma unroll
                 for (int j = 0; j < NS; j++) {
-                    act[j] = act[j] && !(T[j] < eps);  // cell-level termination
                     thj[j] = act[j] ? thc : INFINITY;
                     anyact = anyact || act[j];
                 }
@@ -332,11 +344,11 @@ __device__ inline void alpha_tile(const CompositeArgs& a, const FrameView& f, in
 
     float T[NS], C0[NS], C1[NS], C2[NS];
     int32_t last[NS];
-    bool act[NS];
+    bool inb[NS];  // the pixel lies in the image
 #pragma unroll
     for (int j = 0; j < NS; j++) {
         T[j] = 1.0f; C0[j] = C1[j] = C2[j] = 0.0f; last[j] = 0;
-        act[j] = px < f.W && py0 + 4 * j < f.H;
+        inb[j] = px < f.W && py0 + 4 * j < f.H;
     }
     const uint32_t lb = lds_base(lds);
     Chunk q;
@@ -358,7 +370,7 @@ __device__ inline void alpha_tile(const CompositeArgs& a, const FrameView& f, in
                 since_check = 0;
                 bool anyact = false;
 #pragma unroll
-                for (int j = 0; j < NS; j++) anyact = anyact || act[j];
+                for (int j = 0; j < NS; j++) anyact = anyact || (inb[j] && !(T[j] < eps));
                 if (!__any(anyact)) {
                     alive = false;
                     break;
@@ -374,9 +386,9 @@ __device__ inline void alpha_tile(const CompositeArgs& a, const FrameView& f, in
             const float dy0 = (float)(int)ry0 + e.oy;
 #pragma unroll
             for (int j = 0; j < NS; j++) {
-                // termination before each Gaussian (T only changes on a hit,
-                // so testing it for strips the Gaussian misses changes nothing)
-                act[j] = act[j] && !(T[j] < eps);
+                // termination before each Gaussian (T only changes on a hit
+                // and never rises, so no state is carried across Gaussians)
+                const bool act = inb[j] && !(T[j] < eps);
                 const uint32_t ry = ry0 + 4u * j;
                 const float dy = j ? dy0 + 4.0f * j : dy0;
                 const float pw = fmaf(dy, fmaf(e.cc, dy, t1), t0);
@@ -384,9 +396,9 @@ __device__ inline void alpha_tile(const CompositeArgs& a, const FrameView& f, in
                 const bool hit = iny & (pw >= th);
                 if (STATS) {
                     cn.val += hit;
-                    cn.box += inx && iny && act[j];
+                    cn.box += inx && iny && act;
                 }
-                if (hit & act[j]) {
+                if (hit & act) {
                     const float al = fminf(amax, __builtin_amdgcn_exp2f(pw));
                     const float w = al * T[j];
                     C0[j] = fmaf(w, e.r, C0[j]);
