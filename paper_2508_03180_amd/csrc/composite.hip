@@ -298,16 +298,16 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
                     else Bs[j] += al;
                 }
             }
+            // no branch: a pixel that no longer blends had threshold +inf in
+            // this cell, so P = 1 and Bs = 0 there (T and last unchanged)
 #pragma unroll
             for (int j = 0; j < NS; j++) {
                 if (!mj[j]) continue;  // scalar: nothing of this cell in strip j
-                if (act[j]) {
-                    if constexpr (!LC) T[j] *= P[j];
-                    // a hit lowers P by v alpha >= v / 255
-                    const bool hitc = LC ? Bs[j] > 0.0f : P[j] < 1.0f;
-                    if (hitc) last[j] = (int32_t)(pos + c - start + 1);
-                    if (STATS) cn.cellhit += hitc;
-                }
+                if constexpr (!LC) T[j] *= P[j];
+                // a hit lowers P by v alpha >= v / 255
+                const bool hitc = LC ? Bs[j] > 0.0f : P[j] < 1.0f;
+                last[j] = hitc ? (int32_t)(pos + c - start + 1) : last[j];
+                if (STATS) cn.cellhit += hitc;
             }
         }
         pos = next;
