@@ -60,12 +60,12 @@ BYTES_PROJECT_SH3 = 12 + 12 + 16 + 4 + 192 + 48 + 8
 
 # HBM traffic of one Duplex compositor launch on this workload, from two
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) scaled by a 1 GiB copy
-# kernel's reading (profiles/composite_traffic_1080p_1M_pmc.md): 194.91 MB
-# read + 51.33 MB written.  Valid for the compositor source it was taken
+# kernel's reading (profiles/composite_traffic_1080p_1M_pmc.md): 189.62 MB
+# read + 51.43 MB written.  Valid for the compositor source it was taken
 # on; reported as null once that source changes.
-COMPOSITE_TRAFFIC_BYTES = 194.914e6 + 51.325e6
+COMPOSITE_TRAFFIC_BYTES = 189.620e6 + 51.430e6
 COMPOSITE_TRAFFIC_SOURCES = {
-    "paper_2508_03180_amd/csrc/composite.hip": "6081cc1731f746f488fa0c7c7efefd4dbc014fc15ad990e8539ba785627aca66",
+    "paper_2508_03180_amd/csrc/composite.hip": "b372bef70e558bbdfce0827c0a6d7cce2f6a73ac08edf467b79874462ec05dcd",
     "paper_2508_03180_amd/csrc/common.h": "ee695b63ce970c9d44d9e67504a2b2d021f63d98aa82a96452b6930557202274",
 }
 
