@@ -136,11 +136,13 @@ def ssim_loss(C, T):
 
 
 def differentiation(r, scene, cam, steps):
-    """Forward + loss + backward time through the autograd Function."""
+    """Forward + loss + backward through the planar autograd Function (the
+    parameters are planar leaf tensors used in place), with the render, the
+    loss and the backward timed apart by HIP events on the torch stream."""
     import numpy as np
     import torch
 
-    from paper_2508_03180_amd.renderer import DeviceScene, DuplexRender
+    from paper_2508_03180_amd.renderer import DeviceScene, DuplexRenderPlanar
 
     rng = np.random.default_rng(3)
     pert = dict(scene)
@@ -149,40 +151,57 @@ def differentiation(r, scene, cam, steps):
     pert["opacities"] = (1 / (1 + np.exp(-(logit + rng.normal(0, 0.3, logit.shape))))).astype(np.float32)
     target = r.render(DeviceScene.from_numpy(pert, "cuda:0"), cam)["color"].clone()
     keys = ("cell_pos", "cell_scale", "cell_rot", "cell_v_sh", "means", "scales", "rots", "opacities", "sh")
-    t = {k: torch.tensor(scene[k], device="cuda", requires_grad=k not in ("cell_scale", "cell_rot")) for k in keys}
+    ds = DeviceScene.from_numpy(scene, "cuda:0")
+    pl = {k: ds.t[k].clone().requires_grad_(k not in ("cell_scale", "cell_rot")) for k in keys}
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
 
-    def step():
-        for v in t.values():
+    def step(timed):
+        for v in pl.values():
             v.grad = None
-        C, _ = DuplexRender.apply(r, cam, {}, *[t[k] for k in keys])
+        if timed:
+            ev[0].record()
+        C, _ = DuplexRenderPlanar.apply(r, cam, {}, *[pl[k] for k in keys])
+        if timed:
+            ev[1].record()
         loss = 0.8 * (C - target).abs().mean() + 0.2 * ssim_loss(C, target)
+        if timed:
+            ev[2].record()
         loss.backward()
+        if timed:
+            ev[3].record()
         return loss
 
     for _ in range(3):
-        step()
+        step(False)
     torch.cuda.synchronize()
+    parts = np.zeros(3)
     t0 = time.perf_counter()
     for _ in range(steps):
-        loss = step()
-    torch.cuda.synchronize()
+        loss = step(True)
+        torch.cuda.synchronize()
+        parts += [ev[i].elapsed_time(ev[i + 1]) for i in range(3)]
     dt = (time.perf_counter() - t0) / steps
-    # the backward kernels alone
+    parts /= steps
+    # the library's backward alone (composite and projection backward kernels)
     from paper_2508_03180_amd import _capi as capi
-    ds = DeviceScene.from_numpy(scene, "cuda:0")
-    out = r.render(ds, cam)
+    out = r.render(ds, cam, save=True)
     gC = torch.randn_like(out["color"])
-    r.render_backward(ds, cam, out, gC)
+    r.render_backward(ds, out["frame"], gC)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
     for _ in range(steps):
-        r.render_backward(ds, cam, out, gC)
+        r.render_backward(ds, out["frame"], gC)
+    e1.record()
     torch.cuda.synchronize()
-    bt = (time.perf_counter() - t1) / steps
+    bt = e0.elapsed_time(e1) / steps
+    out.pop("frame").release()
     capi.check(capi.dgs_sync(r.ctx), r.ctx)
     return {"loss": "0.8 L1 + 0.2 (1 - SSIM 11x11) vs perturbed-scene target", "width": 1920, "height": 1080,
-            "fwd_loss_bwd_ms": round(dt * 1e3, 3), "backward_ms": round(bt * 1e3, 3),
-            "final_loss": round(float(loss.detach()), 5)}
+            "params": "planar leaf tensors (no layout copies)",
+            "fwd_loss_bwd_ms": round(dt * 1e3, 3), "render_ms": round(float(parts[0]), 3),
+            "loss_ms": round(float(parts[1]), 3), "loss_and_render_backward_ms": round(float(parts[2]), 3),
+            "backward_ms": round(bt, 3), "final_loss": round(float(loss.detach()), 5)}
 
 
 # LC-WSR weights of the "w/o T^cell" variant on the mid scene: the farthest
@@ -448,7 +467,7 @@ def main():
     def frames(mode, n):
         op = opts_struct(mode=mode)
         for i in range(n):
-            st = L.dgs_render(r.ctx, sc, cam_structs[i % NF], op, im)
+            st = L.dgs_render(r.ctx, sc, cam_structs[i % NF], op, im, None)
             if st:
                 capi.check(st, r.ctx)
 
@@ -477,7 +496,7 @@ def main():
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
         ev[0].record(r.stream)
         for i in range(n):
-            st = L.dgs_render(r.ctx, sc, cam_structs[i % NF], op, im)
+            st = L.dgs_render(r.ctx, sc, cam_structs[i % NF], op, im, None)
             if st:
                 capi.check(st, r.ctx)
             ev[i + 1].record(r.stream)

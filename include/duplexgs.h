@@ -47,6 +47,9 @@ extern "C" {
 #endif
 
 typedef struct dgs_ctx_s* dgs_ctx;
+/* Saved forward state of one Duplex frame, for its backward (library-owned,
+ * belongs to the context that rendered it). */
+typedef struct dgs_frame_s* dgs_frame;
 
 typedef enum {
     DGS_OK = 0,
@@ -105,7 +108,7 @@ typedef struct {
     uint32_t flags;        /* DGS_FLAG_* */
     float eps_T;           /* termination threshold on the transmittance in front of a cell (1e-4) */
     float alpha_min;       /* alpha below this is skipped (1/255) */
-    float alpha_max;       /* alpha clamp (0.99) */
+    float alpha_max;       /* alpha clamp (0.99); must lie in (0, 1), so every factor 1 - v alpha > 0 */
     float cov2d_dilation;  /* screen-space variance added to every Gaussian, px^2 (0.3) */
     float proxy_kappa;     /* cell footprint = kappa-sigma box of the projected proxy (1.0) */
     float bg[3];           /* colour of pixels no Gaussian reaches (0, 0, 0) */
@@ -117,7 +120,9 @@ typedef struct {
     float* color;      /* [3][H][W] */
     float* weight_sum; /* [H][W] D = sum_n w_n sum_k alpha (Duplex) or 1 - T (alpha), nullable */
     float* final_T;    /* [H][W] transmittance behind the last blended cell, nullable */
-    int32_t* last;     /* [H][W] 1 + tile-list position of the last contributing entry (0 = none), nullable */
+    int32_t* last;     /* [H][W] 1 + tile-list position of the last contributing entry (0 = none): the
+                          last cell (Gaussian in alpha mode) with a member that passed the box and
+                          alpha_min gates at the pixel, whatever its weight v_n; nullable */
 } dgs_image;
 
 /* Gradients: caller-owned device buffers in the scene's planar layout.  With
@@ -172,25 +177,45 @@ dgs_status dgs_reserve(dgs_ctx ctx, int64_t max_keys, int64_t max_prims, int64_t
 
 /* Renders one frame: all of Sec. IV-B, V-A, V-B and VI-A for DGS_MODE_DUPLEX,
  * per-Gaussian alpha blending for DGS_MODE_ALPHA.  opts may be NULL
- * (defaults).  The context keeps this frame's sorted lists, projected
- * Gaussians and per-pixel state until its next render (used by
- * dgs_render_backward and the dgs_read_* calls). */
+ * (defaults).  The context keeps this frame's sorted lists and discrete
+ * results until its next render (the dgs_read_* calls).
+ *
+ * saved (nullable): for a frame that will be differentiated.  When non-NULL
+ * (DGS_MODE_DUPLEX only, else DGS_ERR_UNSUPPORTED), *saved receives a frame
+ * handle holding everything dgs_render_backward replays -- the per-tile cell
+ * lists, the projected Gaussians, v_n, and per pixel the colour, D and the
+ * transmittance at the replay start -- in buffers of its own: later renders,
+ * dgs_reserve and dgs_sort_pairs on the context leave it intact, so several
+ * frames can await their backward on one context.  It stays valid until
+ * dgs_frame_release or dgs_destroy.  A saved render may allocate device
+ * memory (not for graph capture). */
 dgs_status dgs_render(dgs_ctx ctx, const dgs_scene* scene, const dgs_camera* cam, const dgs_render_opts* opts,
-                      const dgs_image* out);
+                      const dgs_image* out, dgs_frame* saved);
 
 /* Backward of the hybrid renderer (Sec. V-A eqs. hybrid_renderer and
  * dulpex_T, with w_n = v_n T_n): given dL/dC (grad_color, [3][H][W]) and
  * optionally dL/dD (grad_weight_sum, [H][W], nullable), adds dL/d(parameters)
- * into *grads.  It replays the per-tile cell lists, projected Gaussians and
- * v_n kept by the context from its most recent dgs_render, which must have
- * rendered the same scene, camera and options in DGS_MODE_DUPLEX into `fwd`
- * with weight_sum, final_T and last all non-NULL (they are read here).
- * Returns DGS_ERR_UNSUPPORTED for DGS_MODE_ALPHA and DGS_ERR_INVALID_ARG when
- * the sizes do not match the last render.  Gradients are summed with float
- * atomics, so their last bits may differ between runs. */
+ * into *grads (or writes them, see dgs_grads.overwrite).  It replays the
+ * saved frame `saved`, which must come from dgs_render on this context with
+ * the same scene arrays (same sizes; their values must not have changed since).
+ * cam and opts may be NULL (the frame's own); when given they must equal the
+ * frame's, else DGS_ERR_INVALID_ARG.  The transmittance in front of each cell
+ * is recovered back to front from the one stored at the replay start, so no
+ * division meets a vanishing factor; cells whose front transmittance is below
+ * 2^-64 (reachable only with termination off or eps below that) get no
+ * gradient.  Gradients are summed with float atomics, so their last bits may
+ * differ between runs.  The frame stays valid (a second backward of it is
+ * allowed). */
 dgs_status dgs_render_backward(dgs_ctx ctx, const dgs_scene* scene, const dgs_camera* cam,
-                               const dgs_render_opts* opts, const dgs_image* fwd, const float* grad_color,
+                               const dgs_render_opts* opts, dgs_frame saved, const float* grad_color,
                                const float* grad_weight_sum, const dgs_grads* grads);
+
+/* Gives a saved frame back to its context (stream-ordered: work already
+ * enqueued on the context's stream that reads it still sees it).  The
+ * handle is invalid afterwards. */
+dgs_status dgs_frame_release(dgs_ctx ctx, dgs_frame saved);
+
+
 
 /* Waits for the context's stream; returns the first device-side error since
  * the previous dgs_sync (DGS_ERR_CAPACITY, DGS_ERR_TIMEOUT) or DGS_OK. */
@@ -198,6 +223,11 @@ dgs_status dgs_sync(dgs_ctx ctx);
 
 /* Synchronises and reports the counters of the last render. */
 dgs_status dgs_get_stats(dgs_ctx ctx, dgs_stats* out);
+
+/* Synchronises and reports the counters of a saved frame's render
+ * (num_keys, key_capacity and, for DGS_FLAG_STATS renders, n_val, n_rendered,
+ * n_box and n_cell_hits; the termination ratio is 1 - n_rendered / n_val). */
+dgs_status dgs_frame_stats(dgs_ctx ctx, dgs_frame saved, dgs_stats* out);
 
 /* Message of the last host-side error of this context (never NULL). */
 const char* dgs_last_error(dgs_ctx ctx);

@@ -129,7 +129,7 @@ def build_lists(visible, depth_bits, rect, width, height):
 
 
 DEFAULTS = dict(eps=1e-4, alpha_min=1.0 / 255.0, alpha_max=0.99, delta=0.3, kappa=1.0,
-                bg=(0.0, 0.0, 0.0), v_one=False, no_et=False, band_alpha=1e-4, band_T=1e-4, tau=0.0)
+                bg=(0.0, 0.0, 0.0), v_one=False, no_et=False, band_alpha=1e-5, band_T=1e-4, tau=0.0)
 
 MODES = {"duplex": 0, "alpha": 1, "lcwsr": 2}
 

@@ -98,6 +98,7 @@ class dgs_server_stats(C.Structure):
 DGS_REQ_QUEUED, DGS_REQ_RUNNING, DGS_REQ_DONE, DGS_REQ_FAILED, DGS_REQ_CANCELLED = range(5)
 
 dgs_ctx = C.c_void_p
+dgs_frame = C.c_void_p
 dgs_server = C.c_void_p
 
 # name -> (restype, argtypes)
@@ -108,10 +109,12 @@ _SIGS = {
     "dgs_set_stream": (C.c_int, [dgs_ctx, C.c_void_p]),
     "dgs_reserve": (C.c_int, [dgs_ctx, C.c_int64, C.c_int64, C.c_int64]),
     "dgs_render": (C.c_int, [dgs_ctx, C.POINTER(dgs_scene), C.POINTER(dgs_camera), C.POINTER(dgs_render_opts),
-                             C.POINTER(dgs_image)]),
+                             C.POINTER(dgs_image), C.POINTER(dgs_frame)]),
     "dgs_render_backward": (C.c_int, [dgs_ctx, C.POINTER(dgs_scene), C.POINTER(dgs_camera),
-                                      C.POINTER(dgs_render_opts), C.POINTER(dgs_image), C.c_void_p, C.c_void_p,
+                                      C.POINTER(dgs_render_opts), dgs_frame, C.c_void_p, C.c_void_p,
                                       C.POINTER(dgs_grads)]),
+    "dgs_frame_release": (C.c_int, [dgs_ctx, dgs_frame]),
+    "dgs_frame_stats": (C.c_int, [dgs_ctx, dgs_frame, C.POINTER(dgs_stats)]),
     "dgs_render_neural": (C.c_int, [dgs_ctx, C.POINTER(dgs_neural_scene), C.POINTER(dgs_decoder),
                                     C.POINTER(dgs_camera), C.POINTER(dgs_render_opts), C.POINTER(dgs_image)]),
     "dgs_read_decoded": (C.c_int, [dgs_ctx, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -203,13 +206,27 @@ def dgs_reserve(ctx, max_keys, max_prims, max_tiles):
     return check(lib().dgs_reserve(ctx, int(max_keys), int(max_prims), int(max_tiles)), ctx)
 
 
-def dgs_render(ctx, scene, cam, opts, image):
-    return lib().dgs_render(ctx, C.byref(scene), C.byref(cam), C.byref(opts), C.byref(image))
+def dgs_render(ctx, scene, cam, opts, image, saved=None):
+    """saved: None, or a dgs_frame() that receives the saved-frame handle."""
+    return lib().dgs_render(ctx, C.byref(scene), C.byref(cam), C.byref(opts), C.byref(image),
+                            C.byref(saved) if saved is not None else None)
 
 
-def dgs_render_backward(ctx, scene, cam, opts, image, grad_color_ptr, grad_weight_sum_ptr, grads):
-    return lib().dgs_render_backward(ctx, C.byref(scene), C.byref(cam), C.byref(opts), C.byref(image),
+def dgs_render_backward(ctx, scene, cam, opts, frame, grad_color_ptr, grad_weight_sum_ptr, grads):
+    """cam / opts may be None (the frame's own)."""
+    return lib().dgs_render_backward(ctx, C.byref(scene), C.byref(cam) if cam is not None else None,
+                                     C.byref(opts) if opts is not None else None, frame,
                                      C.c_void_p(grad_color_ptr), C.c_void_p(grad_weight_sum_ptr), C.byref(grads))
+
+
+def dgs_frame_release(ctx, frame):
+    return lib().dgs_frame_release(ctx, frame)
+
+
+def dgs_frame_stats(ctx, frame):
+    s = dgs_stats()
+    check(lib().dgs_frame_stats(ctx, frame, C.byref(s)), ctx)
+    return s
 
 
 def dgs_render_neural(ctx, scene, decoder, cam, opts, image):

@@ -11,8 +11,11 @@
 //     dL/dP_n = T_n dL/dT_{n+1},   dP_n/da_k = -v_n P_n / (1 - v_n a_k),
 //     dL/dv_n = T_n (g_N . A_n + g_D B_n) - dL/dP_n sum_k a_k P_n / (1 - v_n a_k).
 // The walk replays the forward's per-tile cell lists back to front from the
-// last contributing cell, recovering T_n = T_{n+1} / P_n (every factor
-// 1 - v a >= 1 - alpha_max > 0).  Per-Gaussian screen-space gradients
+// replay start the forward saved (the last contributing cell whose
+// transmittance in front is at least kMinReplayT, together with that
+// transmittance), recovering T_n = T_{n+1} / P_n for the cells in front of
+// it: there T_{n+1} >= kMinReplayT, so P_n >= kMinReplayT and the quotient
+// is finite however many opaque members a cell holds.  Per-Gaussian screen-space gradients
 // (mean, conic, sigma, colour) and per-cell dL/dv are reduced over each
 // wavefront and added atomically; a second kernel carries them through the
 // projection (EWA covariance, quaternion, scales, SH colour and its view
@@ -166,7 +169,7 @@ __device__ inline void duplex_tile_bwd(const BwdArgs& a, int tile, int s0, int l
                 gN0[j] = g0 * invD; gN1[j] = g1 * invD; gN2[j] = g2 * invD;
                 gD[j] = -(g0 * a.color[pi] + g1 * a.color[HW + pi] + g2 * a.color[2 * HW + pi]) * invD;
                 if (a.grad_D) gD[j] += a.grad_D[pi];
-                T[j] = a.T[pi];
+                T[j] = a.T[pi];  // transmittance in front of the replay start
                 last[j] = l;
             }
         }
@@ -256,9 +259,11 @@ __device__ inline void duplex_tile_bwd(const BwdArgs& a, int tile, int s0, int l
             for (int j = 0; j < NS; j++) {
                 dLdA0[j] = dLdA1[j] = dLdA2[j] = dLdB[j] = dLdP[j] = 0.0f;
                 if (act[j]) {
-                    // transmittance in front of this cell (gradients are continuous:
-                    // the hardware reciprocal, not a correctly rounded division)
-                    const float Tn = T[j] * __builtin_amdgcn_rcpf(P[j]);
+                    // transmittance in front of this cell: stored for the replay
+                    // start, else recovered from the one behind it (gradients
+                    // are continuous: the hardware reciprocal, not a correctly
+                    // rounded division)
+                    const float Tn = p == last[j] - 1 ? T[j] : T[j] * __builtin_amdgcn_rcpf(P[j]);
                     const float w = v * Tn;
                     dLdA0[j] = w * gN0[j]; dLdA1[j] = w * gN1[j]; dLdA2[j] = w * gN2[j];
                     dLdB[j] = w * gD[j];

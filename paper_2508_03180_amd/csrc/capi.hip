@@ -2,6 +2,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <array>
 #include <string>
 #include <vector>
@@ -82,6 +83,11 @@ dgs_status ensure(dgs_ctx c, int64_t prims, int64_t gauss, int64_t keys, int64_t
         if ((e = grow(c->tile_order, 4 * nc.tiles, c->stream)) != hipSuccess) goto oom;
         c->cap_tiles = nc.tiles;
     }
+    if (nc.prims != cur.prims || nc.gauss != cur.gauss || nc.keys != cur.keys || nc.tiles != cur.tiles) {
+        // the last render's lists and discrete results are gone (saved frames keep their own)
+        c->last_mode = -1;
+        c->cur_ranges = nullptr;
+    }
     return DGS_OK;
 oom:
     // a partial growth leaves the buffers of the failed group unusable: drop them all
@@ -127,7 +133,7 @@ dgs_status make_opts(dgs_ctx c, const dgs_render_opts* in, OptK& o, int& mode) {
         return fail(c, DGS_ERR_INVALID_ARG, "unknown mode");
     if (p.mode == DGS_MODE_LCWSR && !(p.lcwsr_tau > 0 && finite_f(p.lcwsr_tau)))
         return fail(c, DGS_ERR_INVALID_ARG, "DGS_MODE_LCWSR needs a finite lcwsr_tau > 0");
-    if (!(p.alpha_min > 0) || !(p.alpha_max > 0) || !(p.alpha_max <= 1.0f) || !(p.eps_T >= 0) ||
+    if (!(p.alpha_min > 0) || !(p.alpha_max > 0) || !(p.alpha_max < 1.0f) || !(p.eps_T >= 0) ||
         !(p.cov2d_dilation >= 0) || !(p.proxy_kappa > 0))
         return fail(c, DGS_ERR_INVALID_ARG, "render options out of range");
     mode = p.mode;
@@ -238,6 +244,68 @@ DecodeArgs decode_args(dgs_ctx c, const NeuralSrc& nn, const uint32_t* cell_ntil
     return a;
 }
 
+void free_frame(dgs_frame_s* f) {
+    void* ptrs[] = {f->recs, f->cell_v, f->vals, f->ranges, f->order, f->pix, f->info};
+    for (void* p : ptrs)
+        if (p) hipFree(p);
+    delete f;
+}
+
+// A released frame of the context (or a new one) with room for a render of
+// N cells, M Gaussians, `keys` keys, `tiles` tiles and `pixels` pixels.
+dgs_status acquire_frame(dgs_ctx c, int64_t N, int64_t M, int64_t keys, int64_t tiles, int64_t pixels,
+                         dgs_frame_s** out) {
+    dgs_frame_s* f = nullptr;
+    for (dgs_frame_s* x : c->frames)
+        if (!x->live && (!f || x->cap_recs > f->cap_recs)) f = x;
+    if (!f) {
+        f = new dgs_frame_s();
+        f->owner = c;
+        c->frames.push_back(f);
+    }
+    hipError_t e = hipSuccess;
+    if (!f->info && (e = hipMalloc((void**)&f->info, 16 * sizeof(uint32_t))) != hipSuccess) goto oom;
+    if (M > f->cap_recs) {
+        if ((e = grow(f->recs, M, c->stream)) != hipSuccess) goto oom;
+        f->cap_recs = M;
+    }
+    if (N > f->cap_cells) {
+        if ((e = grow(f->cell_v, N, c->stream)) != hipSuccess) goto oom;
+        f->cap_cells = N;
+    }
+    if (keys > f->cap_vals) {
+        if ((e = grow(f->vals, keys, c->stream)) != hipSuccess) goto oom;
+        f->cap_vals = keys;
+    }
+    if (tiles > f->cap_tiles) {
+        if ((e = grow(f->ranges, 2 * tiles, c->stream)) != hipSuccess) goto oom;
+        if ((e = grow(f->order, 4 * tiles, c->stream)) != hipSuccess) goto oom;
+        f->cap_tiles = tiles;
+    }
+    if (6 * pixels > f->cap_pix) {
+        if ((e = grow(f->pix, 6 * pixels, c->stream)) != hipSuccess) goto oom;
+        f->cap_pix = 6 * pixels;
+    }
+    *out = f;
+    return DGS_OK;
+oom:
+    // drop the half-grown frame: its capacities no longer describe its buffers
+    c->frames.erase(std::find(c->frames.begin(), c->frames.end(), f));
+    free_frame(f);
+    return fail(c, DGS_ERR_OOM, std::string("hipMalloc failed for a saved frame: ") + hipGetErrorString(e));
+}
+
+bool own_live_frame(dgs_ctx c, dgs_frame f) {
+    return f && f->owner == c && f->live && std::find(c->frames.begin(), c->frames.end(), f) != c->frames.end();
+}
+
+// Copies the render's key total and statistics counters into a saved frame.
+__global__ void k_frame_info(const uint32_t* misc, const unsigned long long* counters, uint32_t* info) {
+    const int i = threadIdx.x;
+    if (i == 0) info[2] = misc[0];
+    if (i < 4) reinterpret_cast<unsigned long long*>(info + 4)[i] = counters[i];
+}
+
 }  // namespace
 
 WorkspaceCaps dgs_internal_plan(const WorkspaceCaps& cur, const WorkspaceCaps& want) {
@@ -276,6 +344,7 @@ void dgs_internal_release(dgs_ctx c) {
     c->cap_prims = c->cap_gauss = c->cap_keys = c->cap_tiles = 0;
     c->scan_status_cap = c->sort_status_cap = 0;
     c->last_mode = -1;
+    c->cur_ranges = nullptr;
     c->generation++;
 }
 
@@ -289,6 +358,8 @@ dgs_status dgs_internal_frame(dgs_ctx c, const dgs_camera* cam, const dgs_render
     f->D = out->weight_sum;
     f->T = out->final_T;
     f->last = out->last;
+    f->sv_color = f->sv_D = f->sv_T = nullptr;
+    f->sv_last = nullptr;
     return DGS_OK;
 }
 
@@ -364,6 +435,8 @@ dgs_status dgs_destroy(dgs_ctx c) {
     if (c->ev_join) hipEventDestroy(c->ev_join);
     for (auto& a : c->events)
         for (auto& e : a) hipEventDestroy(e);
+    for (dgs_frame_s* f : c->frames) free_frame(f);
+    c->frames.clear();
     void* ptrs[] = {c->p_depth, c->p_ntiles, c->p_offsets, c->p_rect, c->cell_v, c->recs, c->grect,
                     c->keys0, c->keys1, c->vals0, c->vals1, c->ranges, c->tile_order, c->scan_status, c->sort_status, c->g2d, c->gv, c->dec,
                     c->pk0, c->pk1, c->pv0, c->pv1, c->psort_status,
@@ -388,8 +461,35 @@ dgs_status dgs_reserve(dgs_ctx c, int64_t max_keys, int64_t max_prims, int64_t m
 }
 
 dgs_status dgs_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* cam, const dgs_render_opts* opts,
-                      const dgs_image* out) {
-    return dgs_internal_render(c, s, cam, opts, out, true);
+                      const dgs_image* out, dgs_frame* saved) {
+    if (!saved) return dgs_internal_render(c, s, cam, opts, out, true);
+    if (!c) return DGS_ERR_INVALID_ARG;
+    *saved = nullptr;
+    CamK k;
+    OptK o;
+    int mode = 0;
+    dgs_status st;
+    if ((st = make_cam(c, cam, k)) != DGS_OK) return st;
+    if ((st = make_opts(c, opts, o, mode)) != DGS_OK) return st;
+    if (mode != DGS_MODE_DUPLEX) return fail(c, DGS_ERR_UNSUPPORTED, "only DGS_MODE_DUPLEX frames can be saved");
+    if ((st = check_scene(c, s, mode)) != DGS_OK) return st;
+    hipSetDevice(c->device);
+    const int64_t N = s->num_cells, M = N * s->gaussians_per_cell;
+    const int64_t tiles = (int64_t)k.TX * k.TY, pixels = (int64_t)k.W * k.H;
+    const int64_t keys = c->cap_keys ? c->cap_keys : dgs_internal_default_keys(N);
+    dgs_frame_s* f = nullptr;
+    if ((st = acquire_frame(c, N, M, keys, tiles, pixels, &f)) != DGS_OK) return st;
+    st = dgs_internal_render(c, s, cam, opts, out, true, nullptr, f);
+    if (st != DGS_OK) return st;
+    f->live = true;
+    f->k = k;
+    f->o = o;
+    f->N = (int)N;
+    f->K = s->gaussians_per_cell;
+    f->M = M;
+    f->tiles = (int)tiles;
+    *saved = f;
+    return DGS_OK;
 }
 
 dgs_status dgs_render_neural(dgs_ctx c, const dgs_neural_scene* ns, const dgs_decoder* dec, const dgs_camera* cam,
@@ -455,7 +555,7 @@ dgs_status dgs_read_decoded(dgs_ctx c, float* means, float* scales, float* rots,
 // written to the context's device FrameK by the first kernel; without it the
 // caller has put them there (a captured graph replayed for a new camera).
 dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* cam, const dgs_render_opts* opts,
-                               const dgs_image* out, bool write_frame, const NeuralSrc* nn) {
+                               const dgs_image* out, bool write_frame, const NeuralSrc* nn, dgs_frame_s* save) {
     if (!c) return DGS_ERR_INVALID_ARG;
     CamK k;
     OptK o;
@@ -477,6 +577,12 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     const uint32_t cap = (uint32_t)c->cap_keys;
     hipStream_t q = c->stream;
     const bool overlap = cells && !c->timing && c->two_streams;
+    // buffers the backward replays: a saved frame's own, else the context's
+    float* cell_v = save ? save->cell_v : c->cell_v;
+    GRec* recs = save ? save->recs : c->recs;
+    uint32_t* ranges = save ? save->ranges : c->ranges;
+    uint32_t* torder = save ? save->order : c->tile_order;
+    uint32_t* queue = save ? save->info : c->misc + 11;
 
     StageMarks sm(c);
     {
@@ -485,10 +591,17 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
         ClearList cl;
         cl.add(c->hist, 8 * 256);
         cl.add(c->misc + 1, 12);
-        cl.add(c->ranges, 2 * (size_t)tiles);
-        if (o.stats) cl.add((uint32_t*)c->counters, 8);
+        cl.add(ranges, 2 * (size_t)tiles);
+        if (o.stats || save) cl.add((uint32_t*)c->counters, 8);
         cl.bump = c->misc + 13;
-        const FrameK f{k, o, out->color, out->weight_sum, out->final_T, out->last};
+        FrameK f{k, o, out->color, out->weight_sum, out->final_T, out->last, nullptr, nullptr, nullptr, nullptr};
+        if (save) {
+            const size_t HW = (size_t)k.W * k.H;
+            f.sv_color = save->pix;
+            f.sv_D = save->pix + 3 * HW;
+            f.sv_T = save->pix + 4 * HW;
+            f.sv_last = reinterpret_cast<int32_t*>(save->pix + 5 * HW);
+        }
         launch_clear(q, cl, write_frame ? &f : nullptr, c->frame);
     }
     sm.mark(0);
@@ -497,7 +610,7 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     // meanwhile; with stage timing on, everything stays on one stream
     if (cells) {
         launch_cell_preprocess(q, N, s->cell_pos, s->cell_scale, s->cell_rot, s->cell_v_sh, s->v_sh_degree,
-                               c->frame, c->p_depth, c->p_rect, c->p_ntiles, c->cell_v);
+                               c->frame, c->p_depth, c->p_rect, c->p_ntiles, cell_v);
         hipStream_t pq = q;
         if (overlap) {
             hipEventRecord(c->ev_fork, q);
@@ -507,13 +620,13 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
         if (nn) launch_decode(pq, decode_args(c, *nn, c->p_ntiles));
         sm.mark(1);
         launch_gauss_project(pq, M, K, s->means, s->scales, s->rots, s->opacities, s->sh, s->sh_degree, c->frame,
-                             c->p_ntiles, c->recs, c->grect, nullptr, nullptr, overlap);
+                             c->p_ntiles, recs, c->grect, nullptr, nullptr, overlap);
         if (overlap) hipEventRecord(c->ev_join, c->aux);
     } else {
         if (nn) launch_decode(q, decode_args(c, *nn, nullptr));
         sm.mark(1);
         launch_gauss_project(q, M, K, s->means, s->scales, s->rots, s->opacities, s->sh, s->sh_degree, c->frame,
-                             nullptr, c->recs, c->grect, c->p_depth, c->p_ntiles);
+                             nullptr, recs, c->grect, c->p_depth, c->p_ntiles);
     }
     sm.mark(2);
     const uint64_t* prect = cells ? c->p_rect : c->grect;
@@ -537,12 +650,12 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     const uint64_t* skeys = in1 ? c->keys1 : c->keys0;
     const uint32_t* svals = in1 ? c->vals1 : c->vals0;
     sm.mark(5);
-    launch_tile_ranges(q, skeys, c->misc + 0, cap, c->ranges);
+    launch_tile_ranges(q, skeys, c->misc + 0, cap, ranges, svals, save ? save->vals : nullptr);
     CompositeArgs a;
-    a.ranges = c->ranges;
+    a.ranges = ranges;
     a.vals = svals;
-    a.recs = c->recs;
-    a.cell_v = c->cell_v;
+    a.recs = recs;
+    a.cell_v = cell_v;
     a.K = K;
     a.fr = c->frame;
     a.k = k;  // host copy: grid sizes only
@@ -552,9 +665,10 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     a.T = out->final_T;
     a.last = out->last;
     a.counters = o.stats ? c->counters : nullptr;
-    a.order = c->tile_order;
-    a.queue = c->misc + 11;
-    launch_tile_order(q, c->ranges, tiles, cells ? kSplitLenCells : kSplitLenGauss, c->tile_order, c->misc + 11);
+    a.order = torder;
+    a.queue = queue;
+    a.save = save != nullptr;
+    launch_tile_order(q, ranges, tiles, cells ? kSplitLenCells : kSplitLenGauss, torder, queue);
     if (overlap) hipStreamWaitEvent(q, c->ev_join, 0);  // the projected members
     sm.mark(6);
     if (mode == DGS_MODE_DUPLEX)
@@ -564,6 +678,8 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     else
         launch_composite_alpha(q, a);
     sm.mark(7);
+    if (save) hipLaunchKernelGGL(k_frame_info, dim3(1), dim3(64), 0, q, c->misc, c->counters, save->info);
+    c->cur_ranges = ranges;
     c->last_mode = mode;
     c->last_neural = nn != nullptr;
     c->last_passes = (P > 0 ? sort_passes(32) : 0) + sort_passes(tbits);
@@ -577,26 +693,34 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
 extern "C" {
 
 dgs_status dgs_render_backward(dgs_ctx c, const dgs_scene* s, const dgs_camera* cam, const dgs_render_opts* opts,
-                               const dgs_image* fwd, const float* grad_color, const float* grad_weight_sum,
+                               dgs_frame f, const float* grad_color, const float* grad_weight_sum,
                                const dgs_grads* gr) {
     if (!c) return DGS_ERR_INVALID_ARG;
-    CamK k;
-    OptK o;
-    int mode = 0;
+    if (!own_live_frame(c, f)) return fail(c, DGS_ERR_INVALID_ARG, "not a live saved frame of this context");
     dgs_status st;
-    if ((st = make_cam(c, cam, k)) != DGS_OK) return st;
-    if ((st = make_opts(c, opts, o, mode)) != DGS_OK) return st;
-    if ((st = check_scene(c, s, mode)) != DGS_OK) return st;
-    if (mode != DGS_MODE_DUPLEX) return fail(c, DGS_ERR_UNSUPPORTED, "backward is implemented for DGS_MODE_DUPLEX");
-    if (!fwd || !fwd->color || !fwd->weight_sum || !fwd->final_T || !fwd->last || !grad_color || !gr)
-        return fail(c, DGS_ERR_INVALID_ARG, "backward needs the forward color, weight_sum, final_T, last and grad_color");
+    if (cam) {
+        CamK k;
+        memset(&k, 0, sizeof k);
+        if ((st = make_cam(c, cam, k)) != DGS_OK) return st;
+        if (memcmp(&k, &f->k, sizeof k) != 0) return fail(c, DGS_ERR_INVALID_ARG, "camera differs from the saved frame's");
+    }
+    if (opts) {
+        OptK o;
+        int mode = 0;
+        memset(&o, 0, sizeof o);
+        if ((st = make_opts(c, opts, o, mode)) != DGS_OK) return st;
+        if (mode != DGS_MODE_DUPLEX) return fail(c, DGS_ERR_UNSUPPORTED, "backward is implemented for DGS_MODE_DUPLEX");
+        o.stats = f->o.stats;  // counting does not change the frame
+        if (memcmp(&o, &f->o, sizeof o) != 0)
+            return fail(c, DGS_ERR_INVALID_ARG, "render options differ from the saved frame's");
+    }
+    if ((st = check_scene(c, s, DGS_MODE_DUPLEX)) != DGS_OK) return st;
+    if (!grad_color || !gr) return fail(c, DGS_ERR_INVALID_ARG, "grad_color and grads must not be NULL");
     if (!gr->d_means || !gr->d_scales || !gr->d_rots || !gr->d_opacities || !gr->d_sh || !gr->d_cell_v_sh ||
         !gr->d_cell_pos)
         return fail(c, DGS_ERR_INVALID_ARG, "gradient buffers must not be NULL (only d_mean2d is optional)");
-    const int N = s->num_cells, K = s->gaussians_per_cell, M = N * K, tiles = k.TX * k.TY;
-    if (c->last_neural) return fail(c, DGS_ERR_UNSUPPORTED, "no backward for neural renders");
-    if (c->last_mode != DGS_MODE_DUPLEX || c->last_prims != N || c->last_gauss != M || c->last_tiles != tiles)
-        return fail(c, DGS_ERR_INVALID_ARG, "backward must follow a Duplex render of the same scene and camera");
+    const int N = s->num_cells, K = s->gaussians_per_cell, M = N * K;
+    if (N != f->N || K != f->K) return fail(c, DGS_ERR_INVALID_ARG, "scene sizes differ from the saved frame's");
     if (M == 0) return DGS_OK;
     hipSetDevice(c->device);
     hipError_t e = hipSuccess;
@@ -610,32 +734,37 @@ dgs_status dgs_render_backward(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     }
     {
         hipStream_t q = c->stream;
+        const size_t HW = (size_t)f->k.W * f->k.H;
+        float* color = f->pix;
+        float* D = f->pix + 3 * HW;
+        float* T = f->pix + 4 * HW;
+        int32_t* last = reinterpret_cast<int32_t*>(f->pix + 5 * HW);
         launch_fill_u32(q, (uint32_t*)c->g2d, 0u, kG2dRow * (size_t)M);
         launch_fill_u32(q, (uint32_t*)c->gv, 0u, (size_t)N);
-        // the forward's work queue (same ranges, same split) is still in
-        // tile_order with its item count in misc[12]: rewind its head only
-        launch_fill_u32(q, c->misc + 11, 0u, 1);
-        launch_set_frame(q, FrameK{k, o, fwd->color, fwd->weight_sum, fwd->final_T, fwd->last}, c->frame);
+        // the forward's work queue (same ranges, same split) is in the
+        // frame with its item count: rewind its head only
+        launch_fill_u32(q, f->info, 0u, 1);
+        launch_set_frame(q, FrameK{f->k, f->o, color, D, T, last, nullptr, nullptr, nullptr, nullptr}, c->frame);
         BwdArgs a;
-        a.ranges = c->ranges;
-        a.vals = c->last_in_1 ? c->vals1 : c->vals0;
-        a.recs = c->recs;
-        a.cell_v = c->cell_v;
+        a.ranges = f->ranges;
+        a.vals = f->vals;
+        a.recs = f->recs;
+        a.cell_v = f->cell_v;
         a.K = K;
         a.M = M;
         a.fr = c->frame;
-        a.k = k;
-        a.o = o;
-        a.color = fwd->color;
-        a.D = fwd->weight_sum;
-        a.T = fwd->final_T;
-        a.last = fwd->last;
+        a.k = f->k;
+        a.o = f->o;
+        a.color = color;
+        a.D = D;
+        a.T = T;
+        a.last = last;
         a.grad_color = grad_color;
         a.grad_D = grad_weight_sum;
         a.g2d = c->g2d;
         a.gv = c->gv;
-        a.order = c->tile_order;
-        a.queue = c->misc + 11;
+        a.order = f->order;
+        a.queue = f->info;
         launch_composite_bwd(q, a);
         ProjBwdArgs b;
         b.N = N;
@@ -661,6 +790,33 @@ dgs_status dgs_render_backward(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     return launched(c);
 oom:
     return fail(c, DGS_ERR_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+}
+
+dgs_status dgs_frame_release(dgs_ctx c, dgs_frame f) {
+    if (!c) return DGS_ERR_INVALID_ARG;
+    if (!own_live_frame(c, f)) return fail(c, DGS_ERR_INVALID_ARG, "not a live saved frame of this context");
+    f->live = false;
+    return DGS_OK;
+}
+
+dgs_status dgs_frame_stats(dgs_ctx c, dgs_frame f, dgs_stats* out) {
+    if (!c || !out) return DGS_ERR_INVALID_ARG;
+    if (!own_live_frame(c, f)) return fail(c, DGS_ERR_INVALID_ARG, "not a live saved frame of this context");
+    hipSetDevice(c->device);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, DGS_ERR_DEVICE, "stream synchronize failed");
+    uint32_t info[16];
+    if (hipMemcpy(info, f->info, sizeof info, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(c, DGS_ERR_DEVICE, "frame counters readback failed");
+    unsigned long long cnt[4];
+    memcpy(cnt, info + 4, sizeof cnt);
+    memset(out, 0, sizeof *out);
+    out->num_keys = info[2];
+    out->key_capacity = f->cap_vals;
+    out->n_val = (int64_t)cnt[0];
+    out->n_rendered = (int64_t)cnt[1];
+    out->n_box = (int64_t)cnt[2];
+    out->n_cell_hits = (int64_t)cnt[3];
+    return DGS_OK;
 }
 
 dgs_status dgs_sync(dgs_ctx c) {
@@ -714,8 +870,9 @@ dgs_status dgs_read_lists(dgs_ctx c, uint64_t* keys, uint32_t* values, uint32_t*
     const uint32_t* sv = c->last_in_1 ? c->vals1 : c->vals0;
     if (keys && total) hipMemcpyAsync(keys, sk, total * sizeof(uint64_t), hipMemcpyDeviceToDevice, c->stream);
     if (values && total) hipMemcpyAsync(values, sv, total * sizeof(uint32_t), hipMemcpyDeviceToDevice, c->stream);
-    if (ranges)
-        hipMemcpyAsync(ranges, c->ranges, 2 * c->last_tiles * sizeof(uint32_t), hipMemcpyDeviceToDevice, c->stream);
+    if (ranges && c->cur_ranges)
+        hipMemcpyAsync(ranges, c->cur_ranges, 2 * c->last_tiles * sizeof(uint32_t), hipMemcpyDeviceToDevice,
+                       c->stream);
     return launched(c);
 }
 
@@ -773,6 +930,7 @@ dgs_status dgs_sort_pairs(dgs_ctx c, uint64_t* keys, uint32_t* values, int64_t n
     hipSetDevice(c->device);
     dgs_status st;
     if ((st = ensure(c, 0, 0, n, 0)) != DGS_OK) return st;
+    c->last_mode = -1;  // the sort overwrites the last render's sorted lists (saved frames keep their own)
     ClearList cl;
     cl.add(c->hist, 8 * 256);
     cl.add(c->misc + 2, 8);

@@ -48,7 +48,24 @@ struct FrameK {
     float* D;
     float* T;
     int32_t* last;
+    // a saved Duplex frame's own per-pixel state for its backward (null when
+    // the frame is not saved): colour [3][H][W], D, and the replay start --
+    // 1 + list position of the last contributing cell whose transmittance in
+    // front is at least kMinReplayT -- with that transmittance
+    float* sv_color;
+    float* sv_D;
+    float* sv_T;
+    int32_t* sv_last;
 };
+
+// The backward recovers the transmittance in front of each replayed cell
+// from the one behind it, T_n = T_{n+1} / P_n.  It starts at a cell whose own
+// front transmittance the forward stored, and every cell in front of that
+// one had a front transmittance >= kMinReplayT, so each P_n >= kMinReplayT
+// and the division neither overflows nor meets 0/0.  Cells behind the
+// replay start (only reachable with termination off or eps below this
+// bound) carry weights below 2^-64 and are held at zero gradient.
+constexpr float kMinReplayT = 0x1p-64f;
 
 // Projected Gaussian as the compositor reads it (48 bytes).
 //   dx = (px - x0) + ox, dy = (py - y0) + oy      (pixel offset from the mean)

@@ -133,6 +133,10 @@ struct FrameView {
     float* D;
     float* T;
     int32_t* last;
+    float* sv_color;  // saved state of the frame for its backward (SAVE walks only)
+    float* sv_D;
+    float* sv_T;
+    int32_t* sv_last;
 };
 
 __device__ inline FrameView frame_view(const FrameK* fr) {
@@ -150,6 +154,10 @@ __device__ inline FrameView frame_view(const FrameK* fr) {
     f.D = fr->D;
     f.T = fr->T;
     f.last = fr->last;
+    f.sv_color = fr->sv_color;
+    f.sv_D = fr->sv_D;
+    f.sv_T = fr->sv_T;
+    f.sv_last = fr->sv_last;
     return f;
 }
 
@@ -174,7 +182,12 @@ struct Counters {
 // P = prod (1 - v alpha) updates T after the cell; C = N / D at the end.
 // LC: the "w/o T^cell" weights -- cell_v holds w_n = v_n max(0, 1 - d_n / tau),
 // no transmittance and no termination.
-template <bool STATS, int NS, bool LC>
+// A cell counts as contributing at a pixel (`last`) when any of its members
+// passed both gates there, whatever its weight.
+// SAVE: also write the state the backward replays from -- colour, D, and the
+// list position of the last contributing cell whose transmittance in front
+// is at least kMinReplayT together with that transmittance.
+template <bool STATS, int NS, bool LC, bool SAVE>
 __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, int tile, int s0, int lane, GRec* lds,
                                  Counters& cn) {
     const int tx0 = (tile % f.TX) * kTile, ty0 = (tile / f.TX) * kTile;
@@ -189,10 +202,13 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
     float T[NS], N0[NS], N1[NS], N2[NS], D[NS];
     float thj[NS];  // gate threshold of strip j's pixel for the current cell, +inf once it has terminated
     int32_t last[NS];
+    int32_t rlast[NS];  // SAVE: replay start (list position + 1, 0 = none)
+    float rT[NS];       // SAVE: transmittance in front of that entry
     bool inb[NS];  // the pixel lies in the image
 #pragma unroll
     for (int j = 0; j < NS; j++) {
         T[j] = 1.0f; N0[j] = N1[j] = N2[j] = D[j] = 0.0f; last[j] = 0;
+        rlast[j] = 0; rT[j] = 1.0f;
         inb[j] = px < f.W && py0 + 4 * j < f.H;
         thj[j] = inb[j] ? th : INFINITY;
     }
@@ -254,9 +270,10 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
             // the cell's weight is fixed before its members: w alpha c and
             // w alpha go straight into N and D (no per-cell sums A, B); in the
             // Duplex walk al below is v alpha and w alpha = T (v alpha)
-            float wj[NS], P[NS], Bs[NS];
+            float wj[NS], P[NS];
+            bool hc[NS];  // some member of this cell passed both gates at the pixel
 #pragma unroll
-            for (int j = 0; j < NS; j++) { wj[j] = LC ? v : T[j]; P[j] = 1.0f; Bs[j] = 0.0f; }
+            for (int j = 0; j < NS; j++) { wj[j] = LC ? v : T[j]; P[j] = 1.0f; hc[j] = false; }
             for (uint32_t rem = any; rem; rem &= rem - 1) {
                 const int k = __builtin_ctz(rem);
                 const RecView e = read_rec(lb, base + k);
@@ -295,19 +312,23 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
                     N2[j] = fmaf(wa, e.b, N2[j]);
                     D[j] += wa;
                     if constexpr (!LC) P[j] = fmaf(-P[j], al, P[j]);
-                    else Bs[j] += al;
+                    hc[j] = hc[j] | hit;
                 }
             }
             // no branch: a pixel that no longer blends had threshold +inf in
-            // this cell, so P = 1 and Bs = 0 there (T and last unchanged)
+            // this cell, so P = 1 and no hit there (T and last unchanged)
 #pragma unroll
             for (int j = 0; j < NS; j++) {
                 if (!mj[j]) continue;  // scalar: nothing of this cell in strip j
+                const int32_t idx = (int32_t)(pos + c - start + 1);
+                if constexpr (SAVE) {
+                    const bool rep = hc[j] && T[j] >= kMinReplayT;
+                    rlast[j] = rep ? idx : rlast[j];
+                    rT[j] = rep ? T[j] : rT[j];
+                }
                 if constexpr (!LC) T[j] *= P[j];
-                // a hit lowers P by v alpha >= v / 255
-                const bool hitc = LC ? Bs[j] > 0.0f : P[j] < 1.0f;
-                last[j] = hitc ? (int32_t)(pos + c - start + 1) : last[j];
-                if (STATS) cn.cellhit += hitc;
+                last[j] = hc[j] ? idx : last[j];
+                if (STATS) cn.cellhit += hc[j];
             }
         }
         pos = next;
@@ -331,6 +352,14 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
         if (f.D) f.D[p] = D[j];
         if (f.T) f.T[p] = T[j];
         if (f.last) f.last[p] = last[j];
+        if constexpr (SAVE) {
+            f.sv_color[p] = f.color[p];
+            f.sv_color[HW + p] = f.color[HW + p];
+            f.sv_color[2 * HW + p] = f.color[2 * HW + p];
+            f.sv_D[p] = D[j];
+            f.sv_T[p] = rT[j];
+            f.sv_last[p] = rlast[j];
+        }
     }
 }
 
@@ -434,7 +463,7 @@ __device__ inline void alpha_tile(const CompositeArgs& a, const FrameView& f, in
 // them heaviest first, so long tiles start early and short ones fill in
 // behind them on every XCD.  Every wavefront leaves once the queue is empty.
 // MODE: kModeDuplex, kModeAlpha or kModeLcwsr.
-template <int MODE, bool STATS>
+template <int MODE, bool STATS, bool SAVE>
 __global__ __launch_bounds__(256) void k_composite(CompositeArgs a) {
     __shared__ GRec s_rec[kWaves][64];
     const FrameView f = frame_view(a.fr);
@@ -459,9 +488,9 @@ __global__ __launch_bounds__(256) void k_composite(CompositeArgs a) {
         } else {
             constexpr bool LC = MODE == kModeLcwsr;
             if (mode == 0)
-                duplex_tile<STATS, 4, LC>(a, f, tile, 0, lane, lds, cn);
+                duplex_tile<STATS, 4, LC, SAVE>(a, f, tile, 0, lane, lds, cn);
             else
-                duplex_tile<STATS, 2, LC>(a, f, tile, 2 * (mode - 2), lane, lds, cn);
+                duplex_tile<STATS, 2, LC, SAVE>(a, f, tile, 2 * (mode - 2), lane, lds, cn);
         }
     }
     if (STATS) {
@@ -530,10 +559,19 @@ static void launch_mode(hipStream_t st, const CompositeArgs& a) {
     const int tiles = a.k.TX * a.k.TY;  // host copy of the frame's tile grid
     if (tiles <= 0) return;
     const dim3 g(persistent_grid(tiles)), b(256);
+    if constexpr (MODE == kModeDuplex) {
+        if (a.save) {
+            if (a.counters)
+                hipLaunchKernelGGL((k_composite<MODE, true, true>), g, b, 0, st, a);
+            else
+                hipLaunchKernelGGL((k_composite<MODE, false, true>), g, b, 0, st, a);
+            return;
+        }
+    }
     if (a.counters)
-        hipLaunchKernelGGL((k_composite<MODE, true>), g, b, 0, st, a);
+        hipLaunchKernelGGL((k_composite<MODE, true, false>), g, b, 0, st, a);
     else
-        hipLaunchKernelGGL((k_composite<MODE, false>), g, b, 0, st, a);
+        hipLaunchKernelGGL((k_composite<MODE, false, false>), g, b, 0, st, a);
 }
 
 void launch_composite_duplex(hipStream_t st, const CompositeArgs& a) { launch_mode<kModeDuplex>(st, a); }

@@ -9,6 +9,32 @@
 #include "duplexgs.h"
 #include "launch.h"
 
+// A saved Duplex frame (dgs_render with a non-NULL `saved`): the state its
+// backward replays, in buffers of its own so that later renders on the
+// context leave it intact.  Released frames stay with their context and are
+// reused by later saved renders.
+struct dgs_frame_s {
+    dgs_ctx owner = nullptr;
+    bool live = false;
+    dgs::CamK k;  // host copies of the frame's camera and options
+    dgs::OptK o;
+    int N = 0, K = 0, tiles = 0;
+    int64_t M = 0;
+    dgs::GRec* recs = nullptr;  // [M] projected Gaussians
+    int64_t cap_recs = 0;
+    float* cell_v = nullptr;    // [N] v_n
+    int64_t cap_cells = 0;
+    uint32_t* vals = nullptr;   // sorted cell ids (the tile lists)
+    int64_t cap_vals = 0;
+    uint32_t* ranges = nullptr; // [2][tiles] per-tile [start, end)
+    uint32_t* order = nullptr;  // [4][tiles] compositor work items
+    int64_t cap_tiles = 0;
+    float* pix = nullptr;       // [6][H*W]: colour (3 planes), D, replay T, replay start (int32)
+    int64_t cap_pix = 0;
+    uint32_t* info = nullptr;   // [16]: [0] work-queue head, [1] item count, [2] key total,
+                                // [4..11] n_val, n_rendered, n_box, n_cell_hits (u64)
+};
+
 struct dgs_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -58,6 +84,11 @@ struct dgs_ctx_s {
     int64_t last_prims = 0, last_gauss = 0, last_tiles = 0;
     bool last_in_1 = false;
 
+    uint32_t* cur_ranges = nullptr;  // tile ranges of the last render (the context's or a saved frame's)
+
+    // saved frames (live and released), owned by the context
+    std::vector<dgs_frame_s*> frames;
+
     // stage timing
     bool timing = false;
     std::vector<std::array<hipEvent_t, DGS_NUM_STAGES + 1>> events;
@@ -90,8 +121,10 @@ struct NeuralSrc {
     const dgs_neural_scene* scene;
     const dgs_decoder* decoder;
 };
+// With save set (Duplex only), the frame's replay state goes into *save.
 dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* cam, const dgs_render_opts* opts,
-                               const dgs_image* out, bool write_frame, const NeuralSrc* nn = nullptr);
+                               const dgs_image* out, bool write_frame, const NeuralSrc* nn = nullptr,
+                               dgs_frame_s* save = nullptr);
 
 // Validates camera, options and output and builds the frame record; *mode
 // receives the render mode.  c may be a host-only context (errors land in c->err).

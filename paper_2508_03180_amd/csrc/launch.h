@@ -79,9 +79,10 @@ void launch_emit_keys(hipStream_t st, int P, const uint32_t* order, const uint32
                       uint64_t* keys, uint32_t* vals, uint32_t* hist, int tile_passes, int* err);
 
 // [start, end) per tile of the sorted keys; ranges (2 words per tile) must
-// be zero beforehand (tiles without keys keep [0, 0)).
+// be zero beforehand (tiles without keys keep [0, 0)).  With vout set, the
+// sorted values vin are also copied there (a saved frame's own lists).
 void launch_tile_ranges(hipStream_t st, const uint64_t* keys, const uint32_t* n_ptr, uint32_t cap,
-                        uint32_t* ranges);
+                        uint32_t* ranges, const uint32_t* vin = nullptr, uint32_t* vout = nullptr);
 
 // Onesweep LSD radix sort of (u64 key, u32 value) pairs on key bits
 // [first_bit, first_bit + bits).  The count is read on the device from
@@ -122,6 +123,7 @@ struct CompositeArgs {
     unsigned long long* counters;  // [4]: n_val, n_rendered, n_box, n_cell_hits (stats mode), nullable
     uint32_t* order;               // [4 * tiles] scratch: heaviest-first work items
     uint32_t* queue;               // [2] scratch: work-queue head, item count
+    bool save;                     // Duplex: also write the frame record's sv_* state (host-side choice)
 };
 // Work queue of the compositor (heaviest-first tile / half-tile items); must
 // precede launch_composite_*.  Tiles with at least split_len entries become

@@ -332,22 +332,24 @@ void launch_emit_keys(hipStream_t st, int P, const uint32_t* order, const uint32
 
 __global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t* __restrict__ keys,
                                                      const uint32_t* __restrict__ n_ptr, uint32_t cap,
-                                                     uint32_t* __restrict__ ranges) {
+                                                     uint32_t* __restrict__ ranges,
+                                                     const uint32_t* __restrict__ vin, uint32_t* __restrict__ vout) {
     uint32_t n = *n_ptr;
     if (n > cap) n = cap;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         uint32_t t = (uint32_t)(keys[i] >> 32);
         if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != t) ranges[2 * t] = i;
         if (i == n - 1 || (uint32_t)(keys[i + 1] >> 32) != t) ranges[2 * t + 1] = i + 1;
+        if (vout) vout[i] = vin[i];
     }
 }
 
 void launch_tile_ranges(hipStream_t st, const uint64_t* keys, const uint32_t* n_ptr, uint32_t cap,
-                        uint32_t* ranges) {
+                        uint32_t* ranges, const uint32_t* vin, uint32_t* vout) {
     unsigned grid = (unsigned)((cap + 255) / 256);
     if (grid > 2048) grid = 2048;
     if (grid == 0) grid = 1;
-    hipLaunchKernelGGL(k_tile_ranges, dim3(grid), dim3(256), 0, st, keys, n_ptr, cap, ranges);
+    hipLaunchKernelGGL(k_tile_ranges, dim3(grid), dim3(256), 0, st, keys, n_ptr, cap, ranges, vin, vout);
 }
 
 }  // namespace dgs

@@ -140,6 +140,32 @@ def opts_struct(mode="duplex", v_one=False, no_et=False, stats=False, eps=None, 
     return o
 
 
+class Frame:
+    """A saved Duplex frame (the library's dgs_frame): what its backward
+    replays, kept apart from later renders.  Released when closed or
+    garbage-collected."""
+
+    def __init__(self, renderer, handle):
+        self.renderer, self.handle = renderer, handle
+
+    def stats(self):
+        s = capi.dgs_frame_stats(self.renderer.ctx, self.handle)
+        return dict(num_keys=s.num_keys, n_val=s.n_val, n_rendered=s.n_rendered, n_box=s.n_box,
+                    n_cell_hits=s.n_cell_hits)
+
+    def release(self):
+        r, self.renderer = self.renderer, None
+        if r is not None and r.ctx and self.handle:
+            capi.check(capi.dgs_frame_release(r.ctx, self.handle), r.ctx)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
 class Renderer:
     """One library context bound to a device and a stream."""
 
@@ -147,7 +173,6 @@ class Renderer:
         self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.ctx = capi.dgs_create(self.device.index or 0, self.stream.cuda_stream)
-        self.frame_id = 0  # incremented by every render; backward needs the latest
 
     def close(self):
         if self.ctx:
@@ -173,23 +198,23 @@ class Renderer:
                        last=torch.empty((H, W), device=d, dtype=torch.int32))
         return out
 
-    def render_into(self, scene: DeviceScene, cam, out, opts):
-        """Enqueue one frame (no host synchronisation); returns the status."""
+    def render_into(self, scene: DeviceScene, cam, out, opts, saved=None):
+        """Enqueue one frame (no host synchronisation); returns the status.
+        saved: None, or a capi.dgs_frame() that receives a saved-frame handle."""
         img = capi.dgs_image()
         img.color = out["color"].data_ptr()
         img.weight_sum = out["D"].data_ptr() if "D" in out else None
         img.final_T = out["T"].data_ptr() if "T" in out else None
         img.last = out["last"].data_ptr() if "last" in out else None
-        self.frame_id += 1
-        return capi.dgs_render(self.ctx, scene.struct(), camera_struct(cam), opts, img)
+        return capi.dgs_render(self.ctx, scene.struct(), camera_struct(cam), opts, img, saved)
 
-    def render_backward(self, scene: DeviceScene, cam, out, grad_color, grad_D=None, mean2d=False, into=None,
-                        **kw):
+    def render_backward(self, scene: DeviceScene, frame, grad_color, grad_D=None, mean2d=False, into=None):
         """Gradients (planar, float32) of a loss whose gradient w.r.t. the
-        last render's colour is grad_color [3,H,W] (and w.r.t. D, grad_D).
-        Without `into`, new buffers are returned, written whole by the
-        library; with `into` (a dict as returned here), the gradients are
-        added to its buffers and it is returned."""
+        colour of the saved frame `frame` (a Frame from render(save=True)) is
+        grad_color [3,H,W] (and w.r.t. D, grad_D).  Without `into`, new
+        buffers are returned, written whole by the library; with `into` (a
+        dict as returned here), the gradients are added to its buffers and it
+        is returned."""
         d = self.device
         M, N = scene.M, scene.N
         if into is None:
@@ -209,30 +234,36 @@ class Renderer:
         gr.d_opacities, gr.d_sh = g["opacities"].data_ptr(), g["sh"].data_ptr()
         gr.d_cell_v_sh, gr.d_cell_pos = g["cell_v_sh"].data_ptr(), g["cell_pos"].data_ptr()
         gr.d_mean2d = g["mean2d"].data_ptr() if "mean2d" in g and (mean2d or into is not None) else None
-        img = capi.dgs_image()
-        img.color, img.weight_sum = out["color"].data_ptr(), out["D"].data_ptr()
-        img.final_T, img.last = out["T"].data_ptr(), out["last"].data_ptr()
         gc = grad_color.contiguous().float()
         gd = grad_D.contiguous().float() if grad_D is not None else None
-        st = capi.dgs_render_backward(self.ctx, scene.struct(), camera_struct(cam), opts_struct(**kw), img,
-                                      gc.data_ptr(), gd.data_ptr() if gd is not None else None, gr)
+        st = capi.dgs_render_backward(self.ctx, scene.struct(), None, None, frame.handle, gc.data_ptr(),
+                                      gd.data_ptr() if gd is not None else None, gr)
         capi.check(st, self.ctx)
         return g
 
-    def render(self, scene: DeviceScene, cam, out=None, check=True, **kw):
+    def render(self, scene: DeviceScene, cam, out=None, check=True, save=False, **kw):
         """Render a frame.  With check=True the call synchronises, and on a
         key-capacity overflow it reserves the reported count and renders
-        again."""
+        again.  With save=True (Duplex) out["frame"] is a Frame whose
+        backward can be taken later (render_backward)."""
         opts = opts_struct(**kw)
         if out is None:
             out = self.alloc_image(cam)
-        capi.check(self.render_into(scene, cam, out, opts), self.ctx)
+
+        def go():
+            h = capi.dgs_frame() if save else None
+            capi.check(self.render_into(scene, cam, out, opts, h), self.ctx)
+            if save:
+                out["frame"] = Frame(self, h)
+        go()
         if check:
             st = capi.dgs_sync(self.ctx)
             if st == capi.DGS_ERR_CAPACITY:
                 need = capi.dgs_get_stats(self.ctx).num_keys
+                if save:
+                    out.pop("frame").release()
                 self.reserve(int(need * 1.25) + 4096)
-                capi.check(self.render_into(scene, cam, out, opts), self.ctx)
+                go()
                 st = capi.dgs_sync(self.ctx)
             capi.check(st, self.ctx)
         return out
@@ -249,7 +280,6 @@ class Renderer:
             img = capi.dgs_image(out["color"].data_ptr(), out["D"].data_ptr() if "D" in out else None,
                                  out["T"].data_ptr() if "T" in out else None,
                                  out["last"].data_ptr() if "last" in out else None)
-            self.frame_id += 1
             return capi.dgs_render_neural(self.ctx, scene.struct(), scene.decoder_struct(), camera_struct(cam), opts,
                                           img)
         capi.check(go(), self.ctx)
@@ -321,8 +351,10 @@ class DuplexRender(torch.autograd.Function):
     cell_rot [N,4], cell_v_sh [N,Cv], means [M,3], scales [M,3], rots [M,4],
     opacities [M], sh [M,C,3].  Returns (color [3,H,W], D [H,W]).  Cell
     scales and rotations only choose tiles, so their gradient is None.  The
-    backward replays the renderer context's most recent frame: call it before
-    rendering again on the same Renderer.
+    inputs are copied into the library's planar layout on every call; keep
+    the parameters planar and use DuplexRenderPlanar to avoid that.  The
+    frame is saved by the library, so any number of renders may await their
+    backward on one Renderer.
     """
 
     @staticmethod
@@ -331,21 +363,51 @@ class DuplexRender(torch.autograd.Function):
         K = means.shape[0] // max(cell_pos.shape[0], 1)
         ds = DeviceScene.from_tensors(cell_pos, cell_scale, cell_rot, cell_v_sh, means, scales, rots, opacities,
                                       sh, K)
-        out = renderer.render(ds, cam, mode="duplex", **opts)
-        ctx.renderer, ctx.ds, ctx.cam, ctx.opts, ctx.out = renderer, ds, cam, opts, out
-        ctx.frame = renderer.frame_id
+        out = renderer.render(ds, cam, mode="duplex", save=True, **opts)
+        ctx.renderer, ctx.ds, ctx.frame = renderer, ds, out["frame"]
         ctx.shapes = (cell_v_sh.shape, sh.shape)
+        ctx.hw = out["color"].shape[1:]
         return out["color"], out["D"]
 
     @staticmethod
     def backward(ctx, g_color, g_D):
-        r = ctx.renderer
-        if r.frame_id != ctx.frame:
-            raise RuntimeError("the renderer rendered another frame before this backward; "
-                               "use one Renderer per pending backward")
         if g_color is None:
-            g_color = torch.zeros_like(ctx.out["color"])
-        g = r.render_backward(ctx.ds, ctx.cam, ctx.out, g_color, g_D, **ctx.opts)
+            g_color = torch.zeros((3, *ctx.hw), device=ctx.renderer.device)
+        g = ctx.renderer.render_backward(ctx.ds, ctx.frame, g_color, g_D)
         cv_shape, sh_shape = ctx.shapes
         return (None, None, None, g["cell_pos"].t(), None, None, g["cell_v_sh"].t().reshape(cv_shape),
                 g["means"].t(), g["scales"].t(), g["rots"].t(), g["opacities"], g["sh"].permute(2, 0, 1).reshape(sh_shape))
+
+
+class DuplexRenderPlanar(torch.autograd.Function):
+    """Differentiable Duplex render on parameters held in the library's
+    planar layout (contiguous float32 device tensors, used in place with no
+    copy): cell_pos [3,N], cell_scale [3,N], cell_rot [4,N], cell_v_sh [Cv,N],
+    means [3,M], scales [3,M], rots [4,M], opacities [M], sh [C,3,M].  The
+    gradients come back in the same layout, written whole by the library.
+    Returns (color [3,H,W], D [H,W])."""
+
+    @staticmethod
+    def forward(ctx, renderer, cam, opts, cell_pos, cell_scale, cell_rot, cell_v_sh, means, scales, rots,
+                opacities, sh):
+        t = dict(cell_pos=cell_pos, cell_scale=cell_scale, cell_rot=cell_rot, cell_v_sh=cell_v_sh, means=means,
+                 scales=scales, rots=rots, opacities=opacities, sh=sh)
+        for k, v in t.items():
+            if v.dtype != torch.float32 or not v.is_contiguous():
+                raise ValueError(f"{k} must be a contiguous float32 tensor in the planar layout")
+        N = cell_pos.shape[1]
+        K = means.shape[1] // max(N, 1)
+        ds = DeviceScene({k: v.detach() for k, v in t.items()}, N, K, round(cell_v_sh.shape[0] ** 0.5) - 1,
+                         round(sh.shape[0] ** 0.5) - 1)
+        out = renderer.render(ds, cam, mode="duplex", save=True, **opts)
+        ctx.renderer, ctx.ds, ctx.frame = renderer, ds, out["frame"]
+        ctx.hw = out["color"].shape[1:]
+        return out["color"], out["D"]
+
+    @staticmethod
+    def backward(ctx, g_color, g_D):
+        if g_color is None:
+            g_color = torch.zeros((3, *ctx.hw), device=ctx.renderer.device)
+        g = ctx.renderer.render_backward(ctx.ds, ctx.frame, g_color, g_D)
+        return (None, None, None, g["cell_pos"], None, None, g["cell_v_sh"], g["means"], g["scales"], g["rots"],
+                g["opacities"], g["sh"])

@@ -37,9 +37,12 @@ def main(argv=None):
     for mode in a.modes.split(","):
         for i in range(a.frames):
             cam = cams[(10 * i) % 60]
-            r.render(ds, cam, out=out, mode=mode)
             if a.backward and mode == "duplex":
-                r.render_backward(ds, cam, out, g)
+                out = r.render(ds, cam, out=out, mode=mode, save=True)
+                r.render_backward(ds, out["frame"], g)
+                out.pop("frame").release()
+            else:
+                r.render(ds, cam, out=out, mode=mode)
         print(f"rendered {a.frames} {mode} frames" + (" with backward" if a.backward else ""), flush=True)
     n = a.copy_mib * (1 << 20) // 4
     x = torch.ones(n, dtype=torch.float32, device="cuda")

@@ -63,3 +63,38 @@ def test_large_scene_4k_lists_and_sampled_pixels(R, large, ci):
     err = oracle.admissible_max_err(col, ref)
     assert np.isfinite(err).mean() > 0.998
     assert np.nanmax(err) <= TOL, f"max abs error {np.nanmax(err):.3e}"
+
+
+@pytest.mark.parametrize("size", [(1280, 720), (1920, 1080)], ids=["720p", "1080p"])
+@pytest.mark.parametrize("ci", [0, 20], ids=["street", "aerial"])
+def test_large_scene_lists_and_pixels(R, large, ci, size):
+    """The sizes at which the benchmark reports the key reduction and the
+    termination ratio: lists bit-exact, 10,000 random pixels within the
+    tolerance, with D, T and `last` checked on pixels without marginal
+    decisions."""
+    s, ds = large
+    w, h = size
+    cam = scenes.large_scene_cameras(2, w, h, n_near=20, n_far=20)[ci]
+    out = R.render(ds, cam)
+    cd = oracle.cells_discrete(s, cam)
+    tiles = ((w + 15) // 16) * ((h + 15) // 16)
+    keys, vals, ranges = R.read_lists(tiles)
+    ids, _, oranges = oracle.build_lists(cd["visible"], cd["depth_bits"], cd["rect"], w, h)
+    assert keys.numel() == len(ids) > 100_000
+    np.testing.assert_array_equal(vals.cpu().numpy(), ids)
+    np.testing.assert_array_equal(ranges.cpu().numpy(), oranges)
+    del keys, vals
+    rng = np.random.default_rng(100 + ci)
+    pix = np.stack([rng.integers(0, w, 10_000), rng.integers(0, h, 10_000)], 1)
+    ref = oracle.render(s, cam, pixels=pix)
+    col = out["color"].permute(1, 2, 0).double().cpu().numpy()[pix[:, 1], pix[:, 0]]
+    err = oracle.admissible_max_err(col, ref)
+    assert np.isfinite(err).mean() > 0.999
+    assert np.nanmax(err) <= TOL, f"max abs error {np.nanmax(err):.3e}"
+    exact = ref["status"] == 0
+    for k in ("D", "T"):
+        g = out[k].double().cpu().numpy()[pix[:, 1], pix[:, 0]]
+        np.testing.assert_allclose(g[exact], ref[k][exact], atol=TOL)
+    last = out["last"].cpu().numpy()[pix[:, 1], pix[:, 0]]
+    np.testing.assert_array_equal(last[exact], ref["last"][exact])
+    assert (ref["D"] > 0).mean() > 0.2

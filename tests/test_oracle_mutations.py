@@ -55,6 +55,12 @@ MUTATIONS = {
     "lcwsr_without_v": [("vv[n] *= lin > 0 ? lin : 0.0;", "vv[n] = lin > 0 ? lin : 0.0;")],
     "lcwsr_terminates": [("        int n = c->ids[i];\n        double w = c->v[n];",
                           "        if (D > 1.0) break;\n        int n = c->ids[i];\n        double w = c->v[n];")],
+    # the termination-ratio counters (Sec. VII) and the last contributing entry
+    "nval_with_termination": [("if (mode == 0) walk_duplex(&c, px, py, &sv, 1, &rv);",
+                               "if (mode == 0) walk_duplex(&c, px, py, &sv, c.o.no_et, &rv);")],
+    "nrend_counts_cells": [("if (cnt) { last = i - s + 1; nrend += cnt; }", "if (cnt) { last = i - s + 1; nrend += 1; }")],
+    "last_requires_transmittance_drop": [("if (cnt) { last = i - s + 1; nrend += cnt; }",
+                                          "if (cnt && P < 1.0) { last = i - s + 1; nrend += cnt; }")],
     # the neural decode
     "decode_no_relu": [("h[j] = acc > 0.0f ? acc : 0.0f;", "h[j] = acc;")],
     "decode_no_scale_clamp": [("r = r < lim ? r : lim;", "")],

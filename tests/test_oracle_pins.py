@@ -266,6 +266,45 @@ def test_hand_worked_two_cell_scene():
         np.testing.assert_allclose(r["D"][0], float(Fraction(case["D"])), atol=1e-12)
         np.testing.assert_allclose(r["T"][0], float(Fraction(case["T"])), atol=1e-12)
         assert r["last"][0] == 2
+        # the termination-ratio counters of Sec. VII, counted by hand
+        assert r["nval"][0] == case["nval"] and r["nrend"][0] == case["nrend"]
+
+
+def test_counters_skip_members_below_alpha_min_and_outside_the_box():
+    """N^val / N^rendered count the members that pass both gates (Sec. VI-A
+    box, alpha_min): the two-cell scene plus a member of alpha 0.003 < 1/255
+    at the pixel and a member whose box misses it keep the hand counts at 3;
+    colour, D and T are unchanged."""
+    g = json.load(open(os.path.join(GOLDEN, "two_cell_hand.json")))
+    cam = dict(g["camera"], viewmat=np.array(g["camera"]["viewmat"], np.float32))
+    case = g["cases"][0]
+    cells = [dict(pos=c["pos"], members=[dict(sigma=m["sigma"], rgb=m["rgb"]) for m in c["members"]])
+             for c in g["cells"]]
+    far = list(np.add(cells[1]["pos"], [0.1, 0.0, 0.0]))  # 4.3 px right of the pixel, box half-width ~2.1 px
+    cells[1]["members"] = cells[1]["members"] + [dict(sigma=0.003, rgb=[1, 1, 1]),
+                                                 dict(mean=far, sigma=1.0, rgb=[1, 1, 1])]
+    sc = manual_scene(cells, K=3, v_logit=30.0)
+    r = oracle.render(sc, cam, pixels=[g["pixel"]], v_one=True)
+    np.testing.assert_allclose(r["color"][0], [float(Fraction(x)) for x in case["C"]], atol=1e-12)
+    np.testing.assert_allclose(r["T"][0], float(Fraction(case["T"])), atol=1e-12)
+    assert r["nval"][0] == 3 and r["nrend"][0] == 3 and r["status"][0] == 0
+
+
+def test_zero_weight_cell_still_contributes():
+    """A cell with v = 0 (logit -1000) adds nothing to N, D or T, but its
+    members pass both gates at the pixel: it is the last contributing entry
+    and its two members count in N^val and N^rendered (the reading of
+    `last` and of the counters: a member counts when it passes the gates,
+    whatever its cell's weight)."""
+    g = json.load(open(os.path.join(GOLDEN, "two_cell_hand.json")))
+    cam = dict(g["camera"], viewmat=np.array(g["camera"]["viewmat"], np.float32))
+    c0 = g["cells"][0]
+    sc = manual_scene([dict(pos=c0["pos"], v_logit=-1000.0,
+                            members=[dict(sigma=m["sigma"], rgb=m["rgb"]) for m in c0["members"]])], K=2)
+    r = oracle.render(sc, cam, pixels=[g["pixel"]], bg=(0.1, 0.2, 0.3))
+    assert r["D"][0] == 0.0 and r["T"][0] == 1.0
+    np.testing.assert_array_equal(r["color"][0], [0.1, 0.2, 0.3])
+    assert r["last"][0] == 1 and r["nval"][0] == 2 and r["nrend"][0] == 2
 
 
 def test_lcwsr_hand_worked_two_cell_scene():
@@ -283,6 +322,7 @@ def test_lcwsr_hand_worked_two_cell_scene():
         np.testing.assert_allclose(r["color"][0], [float(Fraction(x)) for x in case["C"]], atol=1e-12)
         np.testing.assert_allclose(r["D"][0], float(Fraction(case["D"])), atol=1e-12)
         assert r["T"][0] == 1.0
+        assert r["nval"][0] == case["nval"] and r["nrend"][0] == case["nrend"]
     with pytest.raises(ValueError):
         oracle.render(manual_scene(cells, K=2), cam, mode="lcwsr", pixels=[g["pixel"]])
 
@@ -482,10 +522,13 @@ def test_opaque_front_cell_terminates():
         r = oracle.render(sc, cam, pixels=[[8, 8]], v_one=True)
         np.testing.assert_allclose(r["color"][0], np.mean([m["rgb"] for m in front], 0), atol=1e-6)
         assert r["last"][0] == 1 and r["status"][0] == 0
+        # hand counts: 3 front members rendered; the 3 back ones are valid but cut off
+        assert r["nrend"][0] == 3 and r["nval"][0] == 6
         sc2 = manual_scene([dict(pos=[0.0078125, 0.0078125, 2.0], members=front[:2]),
                             dict(pos=[0.01171875, 0.01171875, 3.0], members=back)], 3)
         r2 = oracle.render(sc2, cam, pixels=[[8, 8]], v_one=True)
         assert r2["last"][0] == 2 and r2["status"][0] == 1
+        assert r2["nrend"][0] == 5 and r2["nval"][0] == 5
         alt = r2["alt"][r2["alt_slot"][0], 0, :3]
         np.testing.assert_allclose(alt, np.mean([m["rgb"] for m in front[:2]], 0), atol=1e-6)
 
