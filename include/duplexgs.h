@@ -53,7 +53,7 @@ typedef struct dgs_frame_s* dgs_frame;
 
 typedef enum {
     DGS_OK = 0,
-    DGS_ERR_INVALID_ARG = 1, /* bad pointer, size, degree or camera */
+    DGS_ERR_INVALID_ARG = 1, /* bad pointer, size, degree or camera (also from dgs_sync: bad cell_offsets) */
     DGS_ERR_OOM = 2,         /* device allocation failed */
     DGS_ERR_CAPACITY = 3,    /* more (tile, primitive) keys than reserved; reserve more, render again */
     DGS_ERR_DEVICE = 4,      /* a HIP call failed */
@@ -75,12 +75,15 @@ typedef enum {
 #define DGS_FLAG_STATS 4u  /* also count N^val / N^rendered (termination ratio) */
 
 /*
- * Scene (Sec. IV-A): N ellipsoidal cells, each emitting K Gaussians.
- * Member k of cell n is Gaussian n*K + k; M = N*K.
+ * Scene (Sec. IV-A): N ellipsoidal cells, each emitting its own Gaussians.
+ * Fixed layout (cell_offsets NULL): K per cell, member k of cell n is
+ * Gaussian n*K + k, M = N*K.  Ragged layout (cell_offsets set): the members
+ * of cell n are Gaussians cell_offsets[n] .. cell_offsets[n+1]-1, at most
+ * K of them (a cell may have none), M = num_gaussians.
  */
 typedef struct {
     int32_t num_cells;          /* N >= 0 */
-    int32_t gaussians_per_cell; /* K in 1..32 */
+    int32_t gaussians_per_cell; /* K in 1..32: members per cell, or with cell_offsets their upper bound */
     const float* cell_pos;      /* [3][N]  x_n */
     const float* cell_scale;    /* [3][N]  S_n, semi-axes (> 0) */
     const float* cell_rot;      /* [4][N]  Q_n as (w, x, y, z); normalised here */
@@ -92,6 +95,11 @@ typedef struct {
     const float* opacities;     /* [M]     sigma in [0, 1]; sigma <= 0 marks an invalid Gaussian */
     const float* sh;            /* [C][3][M] colour SH, C = (sh_degree+1)^2, colour = max(0, 0.5 + sum sh Y) */
     int32_t sh_degree;          /* 0..3 */
+    const int32_t* cell_offsets; /* [N+1] device, nullable (fixed layout): CSR offsets, cell_offsets[0] = 0,
+                                    non-decreasing, cell_offsets[N] = num_gaussians, each cell's count <= K.
+                                    A cell that breaks this is culled and the device error flag set
+                                    (DGS_ERR_INVALID_ARG from dgs_sync) */
+    int32_t num_gaussians;      /* M of the ragged layout (>= 0); ignored in the fixed layout */
 } dgs_scene;
 
 /* Pinhole camera, host struct passed by pointer and copied at the call. */

@@ -13,10 +13,12 @@ Parity status of each function (see the pins under tests/test_oracle_*.py):
                                   numerical-Jacobian projection, rigid motion)
   build_lists                     pinned (numpy stable sort, brute-force tiles)
   sh_basis                        pinned (scipy complex spherical harmonics)
-  render (duplex, alpha)          pinned (K=1 -> sorted alpha blending,
+  render (duplex, alpha, lcwsr)   pinned (K=1 -> sorted alpha blending,
                                   one cell -> weighted sum, permutation
                                   invariance, opaque front cell, hand-worked
-                                  two-cell scene, Gaussian mass, rigid motion)
+                                  two-cell scene and its N^val / N^rendered
+                                  counts, Gaussian mass, rigid motion, ragged
+                                  cells -> the same scene padded to fixed K)
 """
 from __future__ import annotations
 
@@ -149,7 +151,13 @@ def render(scene, cam, mode="duplex", pixels=None, alt_cap=None, **opts):
     o.update(opts)
     L = _load()
     N = scene["cell_pos"].shape[0]
-    K = int(scene["K"])
+    offs = scene.get("cell_offsets")
+    if offs is not None:  # variable members per cell (CSR)
+        offs = np.ascontiguousarray(offs, np.int32)
+        K, M = 0, int(offs[-1])
+    else:
+        K = int(scene["K"])
+        M = N * K
     W, H = int(cam["width"]), int(cam["height"])
     if pixels is None:
         P = W * H
@@ -178,13 +186,15 @@ def render(scene, cam, mode="duplex", pixels=None, alt_cap=None, **opts):
     nkeys = np.zeros(1, np.int32)
     sh = _f32(scene["sh"])
     vsh = _f32(scene["cell_v_sh"])
-    cnt = L.orc_render(C.c_int(MODES[mode]), C.c_int(N), C.c_int(K),
+    cnt = L.orc_render(C.c_int(MODES[mode]), C.c_int(N), C.c_int(K), _p(offs), C.c_int(M),
                        _p(_f32(scene["cell_pos"])), _p(_f32(scene["cell_scale"])), _p(_f32(scene["cell_rot"])),
                        _p(vsh), C.c_int(int(scene["v_sh_degree"])), _p(_f32(scene["means"])),
                        _p(_f32(scene["scales"])), _p(_f32(scene["rots"])), _p(_f32(scene["opacities"])),
                        _p(sh), C.c_int(int(scene["sh_degree"])), _p(camera_vector(cam)), _p(ro), C.c_int(P),
                        _p(pix), _p(color), _p(D), _p(T), _p(last), _p(nrend), _p(nval), _p(status), _p(n_alt),
                        _p(alt_slot), _p(alt), C.c_int32(alt_cap), _p(alt_count), _p(nkeys))
+    if cnt < 0:
+        raise ValueError("cell_offsets must start at 0, never decrease and end at the number of Gaussians")
     return dict(color=color, D=D, T=T, last=last, nrend=nrend, nval=nval, status=status, n_alt=n_alt,
                 alt_slot=alt_slot, alt=alt[:min(int(alt_count[0]), alt_cap)], n_keys=int(cnt))
 

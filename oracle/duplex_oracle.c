@@ -401,7 +401,7 @@ typedef struct {
     const uint8_t *gvis;
     const int32_t *grect;
     const double *v;      /* per cell (duplex) */
-    int K;
+    const int32_t *first; /* [N+1]: the members of cell n are Gaussians first[n] .. first[n+1]-1 */
     const int32_t *ids;
     const int32_t *ranges;
     ropt_t o;
@@ -424,8 +424,7 @@ static void walk_duplex(const ctx_t *c, int px, int py, dec_t *st, int no_et, pi
         double v = c->v[n];
         double A[3] = {0, 0, 0}, B = 0.0, P = 1.0;
         int cnt = 0;
-        for (int kk = 0; kk < c->K; kk++) {
-            int g = n * c->K + kk;
+        for (int g = c->first[n]; g < c->first[n + 1]; g++) {
             if (!c->gvis[g] || !in_rect(c->grect + 4 * g, px, py)) continue; /* AABB skip */
             const g64_t *G = c->G + g;
             double dx = qx - G->u[0], dy = qy - G->u[1];
@@ -463,8 +462,7 @@ static void walk_lcwsr(const ctx_t *c, int px, int py, dec_t *st, pix_t *out) {
         int n = c->ids[i];
         double w = c->v[n];
         int cnt = 0;
-        for (int kk = 0; kk < c->K; kk++) {
-            int g = n * c->K + kk;
+        for (int g = c->first[n]; g < c->first[n + 1]; g++) {
             if (!c->gvis[g] || !in_rect(c->grect + 4 * g, px, py)) continue;
             const g64_t *G = c->G + g;
             double dx = qx - G->u[0], dy = qy - G->u[1];
@@ -517,15 +515,20 @@ static void walk_alpha(const ctx_t *c, int px, int py, dec_t *st, int no_et, pix
  * the whole image in row-major order).
  *   mode 0: Duplex hybrid renderer; mode 1: per-Gaussian alpha blending;
  *   mode 2: the Duplex pipeline with LC-WSR cell weights ("w/o T^cell").
+ * Cell n emits the Gaussians offsets[n] .. offsets[n+1]-1 (Sec. IV-A: each
+ * cell spawns its own Gaussians), M_in in total; offsets == NULL means K per
+ * cell, Gaussians n*K .. n*K+K-1, M = N*K.
  *   ropt[] = eps, alpha_min, alpha_max, delta, kappa, bg0, bg1, bg2,
  *            v_one, no_et, band_alpha, band_T, tau (mode 2)
  * Outputs per pixel: color[3], D, T, last, nrend, nval, status
  * (0 exact, 1 marginal with n_alt admissible alternatives, 2 unverifiable).
  * Alternatives (C[3], D, T per entry, up to 8 per pixel) go to alt[] in
  * slots taken from *alt_count (capacity alt_cap); alt_slot[i] = slot or -1.
- * Returns the total number of (tile, primitive) entries, or -1 on error.
+ * Returns the total number of (tile, primitive) entries, or -1 on error
+ * (offsets not starting at 0, decreasing, or not ending at M_in).
  */
-int64_t orc_render(int mode, int N, int K, const float *cell_pos, const float *cell_scale,
+int64_t orc_render(int mode, int N, int K, const int32_t *offsets, int M_in, const float *cell_pos,
+                   const float *cell_scale,
                    const float *cell_rot, const float *cell_vsh, int vdeg, const float *means,
                    const float *scales, const float *rots, const float *opac, const float *sh, int sh_deg,
                    const float *camv, const double *ropt, int npix, const int32_t *pix,
@@ -533,10 +536,20 @@ int64_t orc_render(int mode, int N, int K, const float *cell_pos, const float *c
                    int8_t *status, int32_t *n_alt, int32_t *alt_slot, double *alt, int32_t alt_cap,
                    int32_t *alt_count, int32_t *lists_out_len) {
     cam_t k; cam_load(camv, &k);
-    int M = N * K;
+    /* members of each cell: K per cell in id order, or the CSR offsets */
+    int32_t *first = malloc(sizeof(int32_t) * (N + 1));
+    for (int n = 0; n <= N; n++) first[n] = offsets ? offsets[n] : n * K;
+    int M = offsets ? M_in : N * K;
+    if (first[0] != 0 || first[N] != M) { free(first); return -1; }
+    for (int n = 0; n < N; n++)
+        if (first[n + 1] < first[n]) { free(first); return -1; }
+    /* the cell of every Gaussian */
+    int32_t *gcell = malloc(sizeof(int32_t) * (M ? M : 1));
+    for (int n = 0; n < N; n++)
+        for (int g = first[n]; g < first[n + 1]; g++) gcell[g] = n;
     float delta = (float)ropt[3], kappa = (float)ropt[4];
     ctx_t c; memset(&c, 0, sizeof c);
-    c.k = &k; c.K = K;
+    c.k = &k; c.first = first;
     c.o.eps = ropt[0]; c.o.amin = ropt[1]; c.o.amax = ropt[2];
     c.o.bg[0] = ropt[5]; c.o.bg[1] = ropt[6]; c.o.bg[2] = ropt[7];
     int v_one = (int)ropt[8];
@@ -584,7 +597,7 @@ int64_t orc_render(int mode, int N, int K, const float *cell_pos, const float *c
     g64_t *G = calloc(M ? M : 1, sizeof(g64_t));
 #pragma omp parallel for schedule(static)
     for (int g = 0; g < M; g++)
-        if (gvis[g] && (mode == 1 || cvis[g / K])) gauss64(&k, g, means, scales, rots, opac, sh, sh_deg, delta, &G[g]);
+        if (gvis[g] && (mode == 1 || cvis[gcell[g]])) gauss64(&k, g, means, scales, rots, opac, sh, sh_deg, delta, &G[g]);
     c.G = G; c.gvis = gvis; c.grect = grect; c.v = vv; c.ids = ids; c.ranges = ranges;
 
     int total = pix ? npix : k.W * k.H;
@@ -628,7 +641,7 @@ int64_t orc_render(int mode, int N, int K, const float *cell_pos, const float *c
     }
     if (lists_out_len) *lists_out_len = (int32_t)cnt;
     free(G); free(gvis); free(gdep); free(grect); free(gnt); free(ranges); free(ids);
-    free(vv); free(cvis);
+    free(vv); free(cvis); free(first); free(gcell);
     return cnt;
 }
 

@@ -99,7 +99,13 @@ class FrozenScene:
 
     def __init__(self, scene, cam, kappa=1.0, delta=0.3):
         self.cam = cam
-        self.K = int(scene["K"])
+        N = scene["cell_pos"].shape[0]
+        offs = scene.get("cell_offsets")
+        # members of cell n: Gaussians first[n] .. first[n + 1] - 1
+        self.first = (np.asarray(offs, np.int64) if offs is not None
+                      else np.arange(N + 1, dtype=np.int64) * int(scene["K"]))
+        counts = np.diff(self.first)
+        self.K = int(counts.max()) if N else 1
         self.cd = cells_discrete(scene, cam, kappa, delta)
         self.gd = gauss_discrete(scene, cam, delta)
         W, H = int(cam["width"]), int(cam["height"])
@@ -129,9 +135,11 @@ def render(params, frozen: FrozenScene, pixels, return_masks=False, **opts):
         CI[i, :e - s] = frozen.ids[s:e]
     valid = CI >= 0
     cell = np.where(valid, CI, 0)
-    G = cell[:, :, None] * K + np.arange(K)[None, None, :]
+    kk = np.arange(max(K, 1))[None, None, :]
+    member = valid[:, :, None] & (kk < np.diff(frozen.first)[cell][:, :, None])
+    G = np.where(member, frozen.first[cell][:, :, None] + kk, 0)
     rect = frozen.gd["rect"][G]
-    inbox = (valid[:, :, None] & frozen.gd["visible"][G].astype(bool)
+    inbox = (member & frozen.gd["visible"][G].astype(bool)
              & (pix[:, None, None, 0] >= rect[..., 0]) & (pix[:, None, None, 0] <= rect[..., 1])
              & (pix[:, None, None, 1] >= rect[..., 2]) & (pix[:, None, None, 1] <= rect[..., 3]))
     # continuous quantities

@@ -34,7 +34,8 @@ class dgs_scene(C.Structure):
                 ("cell_pos", C.c_void_p), ("cell_scale", C.c_void_p), ("cell_rot", C.c_void_p),
                 ("cell_v_sh", C.c_void_p), ("v_sh_degree", C.c_int32),
                 ("means", C.c_void_p), ("scales", C.c_void_p), ("rots", C.c_void_p),
-                ("opacities", C.c_void_p), ("sh", C.c_void_p), ("sh_degree", C.c_int32)]
+                ("opacities", C.c_void_p), ("sh", C.c_void_p), ("sh_degree", C.c_int32),
+                ("cell_offsets", C.c_void_p), ("num_gaussians", C.c_int32)]
 
 
 class dgs_camera(C.Structure):

@@ -20,6 +20,7 @@
 // wavefront and added atomically; a second kernel carries them through the
 // projection (EWA covariance, quaternion, scales, SH colour and its view
 // direction) and a third through v_n = sigmoid(SH(d_n)).
+#include "cells.h"
 #include "common.h"
 #include "launch.h"
 
@@ -136,15 +137,14 @@ __device__ inline BRec read_brec(uint32_t lb, int i) {
 // pixel walks back from its own last contributing entry; per member, the
 // lane first sums its pixels' contributions, then the wavefront reduces
 // them once for the tile.
-template <int NS>
+template <int NS, bool RAGGED>
 __device__ inline void duplex_tile_bwd(const BwdArgs& a, int tile, int s0, int lane, GRec* lds) {
     const CamK& k = a.k;
     const int tx0 = (tile % k.TX) * kTile, ty0 = (tile / k.TX) * kTile;
     const int px = tx0 + (lane & 15), py0 = ty0 + 4 * s0 + (lane >> 4);
     const uint32_t start = a.ranges[2 * tile], len = a.ranges[2 * tile + 1] - start;
     const int K = a.K;
-    const int cpc = 64 / K;
-    const uint32_t kmask = K == 32 ? 0xffffffffu : ((1u << K) - 1u);
+    const uint32_t kmask = member_mask(K);
     const float th = a.o.log2_alpha_min, amax = a.o.alpha_max;
     const size_t HW = (size_t)k.W * k.H;
     const uint32_t lb = lds_base(lds);
@@ -180,20 +180,17 @@ __device__ inline void duplex_tile_bwd(const BwdArgs& a, int tile, int s0, int l
     for (int o = 32; o > 0; o >>= 1) maxlast = max(maxlast, __shfl_xor(maxlast, o, 64));
     maxlast = __builtin_amdgcn_readfirstlane(maxlast);  // uniform: scalar loop control
     for (int hi = maxlast; hi > 0;) {
-        // chunk of cells [lo_c, hi) (list positions relative to start)
-        const int nch = hi < cpc ? hi : cpc;
+        // chunk of whole cells [lo_c, hi) (list positions relative to start)
+        const int nch = cells_fitting_back<RAGGED>(a.vals, a.offs, K, start, start + (uint32_t)hi, lane);
         const int lo_c = hi - nch;
-        const int nrec = nch * K;
-        float v_lane = 0.0f;
+        CellChunk ch;
+        load_cells<RAGGED>(a.vals, a.offs, a.cell_v, K, start + (uint32_t)lo_c, start + (uint32_t)hi, nch, lane, ch);
         uint32_t sm = 0;
-        if (lane < nrec) {
-            const int c = lane / K, kk = lane - c * K;
-            const uint32_t cell = a.vals[start + lo_c + c];
-            const float4* p = reinterpret_cast<const float4*>(a.recs + (size_t)cell * K + kk);
+        if (ch.g >= 0) {
+            const float4* p = reinterpret_cast<const float4*>(a.recs + ch.g);
             float4* d = reinterpret_cast<float4*>(lds + lane);
             const float4 r0 = p[0], r1 = p[1], r2 = p[2];
             d[0] = r0; d[1] = r1; d[2] = r2;
-            if (kk == 0) v_lane = a.cell_v[cell];
             const int x0 = __float_as_int(r2.y), y0 = __float_as_int(r2.z);
             const uint32_t wxy = __float_as_uint(r2.w);
             const int x1 = x0 + (int)(wxy & 0xffffu), y1 = y0 + (int)(wxy >> 16);
@@ -209,24 +206,27 @@ __device__ inline void duplex_tile_bwd(const BwdArgs& a, int tile, int s0, int l
 #pragma unroll
         for (int j = 0; j < NS; j++) Bm[j] = __ballot((sm >> j) & 1u);
         for (int c = nch - 1; c >= 0; c--) {
-            const int base = c * K;
+            // fixed K: cell c holds record lanes cK .. cK + K - 1
+            const int base = RAGGED ? lane_value(ch.first, c) : c * K;
+            const uint32_t cm = RAGGED ? member_mask(lane_value(ch.cnt, c)) : kmask;
             const int p = lo_c + c;  // list position (0-based) of this cell
             uint32_t mj[NS], mm = 0;
             bool act[NS], anyact = false;
             float thj[NS];  // gate threshold, +inf where the pixel does not reach this cell
-            const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v_lane), base));
+            const float v = __int_as_float(lane_value(__float_as_int(ch.vc), c));
             const float lv = fold_log2_weight(v);  // as the forward stages it
             const float thc = th + lv;
 #pragma unroll
             for (int j = 0; j < NS; j++) {
-                mj[j] = (uint32_t)(Bm[j] >> base) & kmask;
+                mj[j] = (uint32_t)(Bm[j] >> base) & cm;
                 mm |= mj[j];
                 act[j] = p < last[j];
                 thj[j] = act[j] ? thc : INFINITY;
                 anyact = anyact || act[j];
             }
             if (!mm || !__any(anyact)) continue;  // no member touches the owned rows / no pixel reaches the cell
-            const uint32_t cell = a.vals[start + p];
+            const uint32_t cell = (uint32_t)lane_value((int)ch.id, c);
+            const int gfirst = lane_value(ch.gfirst, c);  // Gaussian of member 0
             // pass 1: cell totals at each pixel (same decisions as the forward)
             float A0[NS], A1[NS], A2[NS], Bs[NS], P[NS];
 #pragma unroll
@@ -329,7 +329,7 @@ __device__ inline void duplex_tile_bwd(const BwdArgs& a, int tile, int s0, int l
                     const float t = head ? t8 : tb;
                     const int q = head ? (lane >> 3) : 8;
                     if ((head || lane == 1) && t != 0.0f)
-                        atomicAdd(&a.g2d[((size_t)cell * K + kk) * kG2dRow + q], t);
+                        atomicAdd(&a.g2d[((size_t)gfirst + kk) * kG2dRow + q], t);
                 }
             }
             const float dvs = wave_sum(dv);
@@ -339,6 +339,7 @@ __device__ inline void duplex_tile_bwd(const BwdArgs& a, int tile, int s0, int l
     }
 }
 
+template <bool RAGGED>
 __global__ __launch_bounds__(256) void k_composite_bwd(BwdArgs a) {
     __shared__ GRec s_rec[kBwdWaves][64];
     a.k = a.fr->k;
@@ -356,9 +357,9 @@ __global__ __launch_bounds__(256) void k_composite_bwd(BwdArgs a) {
         const uint32_t item = a.order[t];
         const int tile = (int)(item >> 3), mode = (int)(item & 7u);
         if (mode == 0)
-            duplex_tile_bwd<4>(a, tile, 0, lane, lds);
+            duplex_tile_bwd<4, RAGGED>(a, tile, 0, lane, lds);
         else
-            duplex_tile_bwd<2>(a, tile, 2 * (mode - 2), lane, lds);
+            duplex_tile_bwd<2, RAGGED>(a, tile, 2 * (mode - 2), lane, lds);
     }
 }
 
@@ -646,7 +647,11 @@ void launch_composite_bwd(hipStream_t st, const BwdArgs& a) {
     const int tiles = a.k.TX * a.k.TY;
     if (tiles <= 0) return;
     const int waves = 4 * tiles < 256 * 4 * 4 ? 4 * tiles : 256 * 4 * 4;
-    hipLaunchKernelGGL(k_composite_bwd, dim3((waves + kBwdWaves - 1) / kBwdWaves), dim3(256), 0, st, a);
+    const dim3 g((waves + kBwdWaves - 1) / kBwdWaves), b(256);
+    if (a.offs)
+        hipLaunchKernelGGL(k_composite_bwd<true>, g, b, 0, st, a);
+    else
+        hipLaunchKernelGGL(k_composite_bwd<false>, g, b, 0, st, a);
 }
 
 template <bool OW, int DEG>

@@ -150,17 +150,22 @@ dgs_status make_opts(dgs_ctx c, const dgs_render_opts* in, OptK& o, int& mode) {
     return DGS_OK;
 }
 
+// Number of Gaussians of a scene (fixed or ragged layout).
+int64_t scene_gaussians(const dgs_scene* s) {
+    return s->cell_offsets ? (int64_t)s->num_gaussians : (int64_t)s->num_cells * s->gaussians_per_cell;
+}
+
 dgs_status check_scene(dgs_ctx c, const dgs_scene* s, int mode, bool decoded = false) {
     if (!s) return fail(c, DGS_ERR_INVALID_ARG, "scene is NULL");
     if (s->num_cells < 0) return fail(c, DGS_ERR_INVALID_ARG, "num_cells < 0");
     if (s->gaussians_per_cell < 1 || s->gaussians_per_cell > kMaxK)
         return fail(c, DGS_ERR_INVALID_ARG, "gaussians_per_cell must be in 1..32");
-    if ((int64_t)s->num_cells * s->gaussians_per_cell > (int64_t)(1 << 30))
-        return fail(c, DGS_ERR_INVALID_ARG, "too many Gaussians");
+    if (s->cell_offsets && s->num_gaussians < 0) return fail(c, DGS_ERR_INVALID_ARG, "num_gaussians < 0");
+    if (scene_gaussians(s) > (int64_t)(1 << 30)) return fail(c, DGS_ERR_INVALID_ARG, "too many Gaussians");
     if (s->sh_degree < (decoded ? -1 : 0) || s->sh_degree > 3 || s->v_sh_degree < 0 || s->v_sh_degree > 3)
         return fail(c, DGS_ERR_INVALID_ARG, "SH degree must be in 0..3");
     if (s->num_cells == 0) return DGS_OK;
-    if (!s->means || !s->scales || !s->rots || !s->opacities || !s->sh)
+    if (scene_gaussians(s) > 0 && (!s->means || !s->scales || !s->rots || !s->opacities || !s->sh))
         return fail(c, DGS_ERR_INVALID_ARG, "Gaussian arrays must not be NULL");
     if (mode != DGS_MODE_ALPHA && (!s->cell_pos || !s->cell_scale || !s->cell_rot || !s->cell_v_sh))
         return fail(c, DGS_ERR_INVALID_ARG, "cell arrays must not be NULL");
@@ -366,7 +371,7 @@ dgs_status dgs_internal_frame(dgs_ctx c, const dgs_camera* cam, const dgs_render
 dgs_status dgs_internal_check_scene(dgs_ctx c, const dgs_scene* s, int mode) { return check_scene(c, s, mode); }
 
 dgs_status dgs_internal_prepare(dgs_ctx c, const dgs_scene* s, int mode, int width, int height, int64_t keys) {
-    const int64_t M = (int64_t)s->num_cells * s->gaussians_per_cell;
+    const int64_t M = scene_gaussians(s);
     const int64_t P = mode != DGS_MODE_ALPHA ? s->num_cells : M;
     const int64_t tiles = (int64_t)((width + kTile - 1) / kTile) * ((height + kTile - 1) / kTile);
     hipSetDevice(c->device);
@@ -474,7 +479,7 @@ dgs_status dgs_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* cam, cons
     if (mode != DGS_MODE_DUPLEX) return fail(c, DGS_ERR_UNSUPPORTED, "only DGS_MODE_DUPLEX frames can be saved");
     if ((st = check_scene(c, s, mode)) != DGS_OK) return st;
     hipSetDevice(c->device);
-    const int64_t N = s->num_cells, M = N * s->gaussians_per_cell;
+    const int64_t N = s->num_cells, M = scene_gaussians(s);
     const int64_t tiles = (int64_t)k.TX * k.TY, pixels = (int64_t)k.W * k.H;
     const int64_t keys = c->cap_keys ? c->cap_keys : dgs_internal_default_keys(N);
     dgs_frame_s* f = nullptr;
@@ -486,6 +491,7 @@ dgs_status dgs_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* cam, cons
     f->o = o;
     f->N = (int)N;
     f->K = s->gaussians_per_cell;
+    f->offs = s->cell_offsets;
     f->M = M;
     f->tiles = (int)tiles;
     *saved = f;
@@ -529,6 +535,8 @@ dgs_status dgs_render_neural(dgs_ctx c, const dgs_neural_scene* ns, const dgs_de
     s.opacities = c->dec + 10 * M;
     s.sh = c->dec + 11 * M;
     s.sh_degree = -1;
+    s.cell_offsets = nullptr;
+    s.num_gaussians = 0;
     const NeuralSrc nn{ns, dec};
     dgs_status st = dgs_internal_render(c, &s, cam, opts, out, true, &nn);
     if (st == DGS_OK) c->dec_gauss = M;
@@ -567,7 +575,7 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     if (!out || !out->color) return fail(c, DGS_ERR_INVALID_ARG, "output color buffer is NULL");
     hipSetDevice(c->device);
     const int N = s->num_cells, K = s->gaussians_per_cell;
-    const int M = N * K;
+    const int M = (int)scene_gaussians(s);
     const int tiles = k.TX * k.TY;
     const bool cells = mode != DGS_MODE_ALPHA;
     const int P = cells ? N : M;
@@ -610,7 +618,8 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     // meanwhile; with stage timing on, everything stays on one stream
     if (cells) {
         launch_cell_preprocess(q, N, s->cell_pos, s->cell_scale, s->cell_rot, s->cell_v_sh, s->v_sh_degree,
-                               c->frame, c->p_depth, c->p_rect, c->p_ntiles, cell_v);
+                               s->cell_offsets, M, K, c->frame, c->p_depth, c->p_rect, c->p_ntiles, cell_v,
+                               c->dev_err);
         hipStream_t pq = q;
         if (overlap) {
             hipEventRecord(c->ev_fork, q);
@@ -619,8 +628,10 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
         }
         if (nn) launch_decode(pq, decode_args(c, *nn, c->p_ntiles));
         sm.mark(1);
+        // fixed layout: members of culled cells are skipped (the cell of
+        // Gaussian g is g / K); ragged cells: every Gaussian is projected
         launch_gauss_project(pq, M, K, s->means, s->scales, s->rots, s->opacities, s->sh, s->sh_degree, c->frame,
-                             c->p_ntiles, recs, c->grect, nullptr, nullptr, overlap);
+                             s->cell_offsets ? nullptr : c->p_ntiles, recs, c->grect, nullptr, nullptr, overlap);
         if (overlap) hipEventRecord(c->ev_join, c->aux);
     } else {
         if (nn) launch_decode(q, decode_args(c, *nn, nullptr));
@@ -656,6 +667,7 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     a.vals = svals;
     a.recs = recs;
     a.cell_v = cell_v;
+    a.offs = cells ? s->cell_offsets : nullptr;
     a.K = K;
     a.fr = c->frame;
     a.k = k;  // host copy: grid sizes only
@@ -719,8 +731,9 @@ dgs_status dgs_render_backward(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     if (!gr->d_means || !gr->d_scales || !gr->d_rots || !gr->d_opacities || !gr->d_sh || !gr->d_cell_v_sh ||
         !gr->d_cell_pos)
         return fail(c, DGS_ERR_INVALID_ARG, "gradient buffers must not be NULL (only d_mean2d is optional)");
-    const int N = s->num_cells, K = s->gaussians_per_cell, M = N * K;
-    if (N != f->N || K != f->K) return fail(c, DGS_ERR_INVALID_ARG, "scene sizes differ from the saved frame's");
+    const int N = s->num_cells, K = s->gaussians_per_cell, M = (int)scene_gaussians(s);
+    if (N != f->N || K != f->K || M != f->M || s->cell_offsets != f->offs)
+        return fail(c, DGS_ERR_INVALID_ARG, "scene sizes or layout differ from the saved frame's");
     if (M == 0) return DGS_OK;
     hipSetDevice(c->device);
     hipError_t e = hipSuccess;
@@ -750,6 +763,7 @@ dgs_status dgs_render_backward(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
         a.vals = f->vals;
         a.recs = f->recs;
         a.cell_v = f->cell_v;
+        a.offs = f->offs;
         a.K = K;
         a.M = M;
         a.fr = c->frame;
@@ -829,6 +843,8 @@ dgs_status dgs_sync(dgs_ctx c) {
     if (e) {
         hipMemset(c->dev_err, 0, sizeof(int));
         if (e & (1 << kErrTimeout)) return fail(c, DGS_ERR_TIMEOUT, "device look-back wait timed out");
+        if (e & (1 << kErrInvalid))
+            return fail(c, DGS_ERR_INVALID_ARG, "malformed cell_offsets (those cells were culled)");
         if (e & (1 << kErrCapacity)) return fail(c, DGS_ERR_CAPACITY, "key capacity exceeded; reserve more keys");
         return fail(c, DGS_ERR_DEVICE, "device error flag set");
     }
@@ -851,7 +867,10 @@ dgs_status dgs_get_stats(dgs_ctx c, dgs_stats* out) {
     out->n_rendered = (int64_t)cnt[1];
     out->n_box = (int64_t)cnt[2];
     out->n_cell_hits = (int64_t)cnt[3];
-    out->device_error = (e & (1 << kErrTimeout)) ? DGS_ERR_TIMEOUT : (e & (1 << kErrCapacity)) ? DGS_ERR_CAPACITY : 0;
+    out->device_error = (e & (1 << kErrTimeout))    ? DGS_ERR_TIMEOUT
+                        : (e & (1 << kErrInvalid))  ? DGS_ERR_INVALID_ARG
+                        : (e & (1 << kErrCapacity)) ? DGS_ERR_CAPACITY
+                                                    : 0;
     out->sort_passes = c->last_passes;
     return DGS_OK;
 }

@@ -18,6 +18,7 @@ constexpr int kModeAlpha = 1;
 constexpr int kModeLcwsr = 2;
 
 // Device-side error codes (mirror dgs_status values).
+constexpr int kErrInvalid = 1;  // malformed cell_offsets
 constexpr int kErrCapacity = 3;
 constexpr int kErrTimeout = 6;
 

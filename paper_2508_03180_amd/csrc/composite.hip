@@ -25,6 +25,7 @@
 // broadcasts.  The next chunk is fetched into registers while the current
 // one is composited.  Cells and members that touch none of the tile's
 // strips are skipped with scalar bit tests on the ballots.
+#include "cells.h"
 #include "common.h"
 #include "launch.h"
 
@@ -36,27 +37,41 @@ struct Chunk {
     float4 r0, r1, r2;  // this lane's record
     float v;            // v of this lane's cell (Duplex walks)
     bool ok;
+    int nch;            // entries in the chunk (cells, or Gaussians in the alpha walk)
+    int first, cnt;     // cell walks, lane c < nch: first record lane and member count of cell c
 };
 
-__device__ inline void load_chunk(const CompositeArgs& a, uint32_t pos, int nrec, int K, int lane, bool cells,
-                                  Chunk& q) {
+// The next chunk of a cell walk: whole cells from list position pos (at
+// most 64 records, at most end - pos cells).
+template <bool RAGGED>
+__device__ inline void load_cell_chunk(const CompositeArgs& a, uint32_t pos, uint32_t end, int lane, Chunk& q) {
     // every field is set on every path: a partly set struct would be kept in
     // scratch memory instead of registers
-    q.ok = lane < nrec;
+    CellChunk ch;
+    load_cells<RAGGED>(a.vals, a.offs, a.cell_v, a.K, pos, end, -1, lane, ch);
+    q.nch = ch.nch;
+    q.first = ch.first;
+    q.cnt = ch.cnt;
+    q.ok = ch.g >= 0;
+    q.v = ch.v;
+    q.r0 = q.r1 = q.r2 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (!q.ok) return;
+    const float4* p = reinterpret_cast<const float4*>(a.recs + ch.g);
+    q.r0 = p[0];
+    q.r1 = p[1];
+    q.r2 = p[2];
+}
+
+// The next chunk of the per-Gaussian walk: up to 64 list entries from pos.
+__device__ inline void load_gauss_chunk(const CompositeArgs& a, uint32_t pos, uint32_t end, int lane, Chunk& q) {
+    const int n = (int)min(64u, end - pos);
+    q.nch = n;
+    q.first = q.cnt = 0;
+    q.ok = lane < n;
     q.r0 = q.r1 = q.r2 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     q.v = 0.0f;
     if (!q.ok) return;
-    uint32_t g;
-    if (cells) {
-        const int c = lane / K, k = lane - c * K;
-        const uint32_t cell = a.vals[pos + c];
-        g = cell * K + k;
-        q.v = a.cell_v[cell];
-    } else {
-        g = a.vals[pos + lane];
-        q.v = 0.0f;
-    }
-    const float4* p = reinterpret_cast<const float4*>(a.recs + g);
+    const float4* p = reinterpret_cast<const float4*>(a.recs + a.vals[pos + lane]);
     q.r0 = p[0];
     q.r1 = p[1];
     q.r2 = p[2];
@@ -187,15 +202,15 @@ struct Counters {
 // SAVE: also write the state the backward replays from -- colour, D, and the
 // list position of the last contributing cell whose transmittance in front
 // is at least kMinReplayT together with that transmittance.
-template <bool STATS, int NS, bool LC, bool SAVE>
+// RAGGED: cells with their own member counts (CSR offsets), else K per cell.
+template <bool STATS, int NS, bool LC, bool SAVE, bool RAGGED>
 __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, int tile, int s0, int lane, GRec* lds,
                                  Counters& cn) {
     const int tx0 = (tile % f.TX) * kTile, ty0 = (tile / f.TX) * kTile;
     const int px = tx0 + (lane & 15), py0 = ty0 + 4 * s0 + (lane >> 4);
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
     const int K = a.K;
-    const int cpc = 64 / K;  // cells per chunk
-    const uint32_t kmask = K == 32 ? 0xffffffffu : ((1u << K) - 1u);
+    const uint32_t kmask = member_mask(K);
     const float eps = f.eps, th = f.th, amax = f.amax;
     const uint32_t lb = lds_base(lds);
 
@@ -214,10 +229,15 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
     }
 
     Chunk q;
-    if (start < end) load_chunk(a, start, (int)min((uint32_t)cpc, end - start) * K, K, lane, true, q);
+    if (start < end) load_cell_chunk<RAGGED>(a, start, end, lane, q);
     bool alive = true;
     for (uint32_t pos = start; pos < end && (alive || STATS);) {
-        const int nch = (int)min((uint32_t)cpc, end - pos);
+        const int nch = q.nch;
+        int cfirst = 0, ccnt = 0;  // of this chunk (q takes the next one below)
+        if constexpr (RAGGED) {
+            cfirst = q.first;
+            ccnt = q.cnt;
+        }
         // Duplex: log2 v goes into the record's log2 sigma, so that the
         // walk computes v alpha directly (the alpha_min test moves by log2 v)
         // per record lane, its cell's gate threshold and weight clamp (read
@@ -234,13 +254,15 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
         strip_ballots<NS>(q, tx0, ty0, s0, B);
         const float cv = q.v;
         const uint32_t next = pos + nch;
-        if (next < end) load_chunk(a, next, (int)min((uint32_t)cpc, end - next) * K, K, lane, true, q);
+        if (next < end) load_cell_chunk<RAGGED>(a, next, end, lane, q);
         for (int c = 0; c < nch; c++) {
-            const int base = c * K;
+            // fixed K: cell c holds record lanes cK .. cK + K - 1
+            const int base = RAGGED ? lane_value(cfirst, c) : c * K;
+            const uint32_t cm = RAGGED ? member_mask(lane_value(ccnt, c)) : kmask;
             uint32_t mj[NS], any = 0;
 #pragma unroll
             for (int j = 0; j < NS; j++) {
-                mj[j] = (uint32_t)(B[j] >> base) & kmask;
+                mj[j] = (uint32_t)(B[j] >> base) & cm;
                 any |= mj[j];
             }
             if (!any) continue;  // no member of this cell touches the owned strips
@@ -381,17 +403,17 @@ __device__ inline void alpha_tile(const CompositeArgs& a, const FrameView& f, in
     }
     const uint32_t lb = lds_base(lds);
     Chunk q;
-    if (start < end) load_chunk(a, start, (int)min(64u, end - start), 1, lane, false, q);
+    if (start < end) load_gauss_chunk(a, start, end, lane, q);
     bool alive = true;
     for (uint32_t pos = start; pos < end && (alive || STATS);) {
-        const int n = (int)min(64u, end - pos);
+        const int n = q.nch;
         store_chunk(lds, lane, q);
         uint64_t B[NS], any = 0;
         strip_ballots<NS>(q, tx0, ty0, s0, B);
 #pragma unroll
         for (int j = 0; j < NS; j++) any |= B[j];
         const uint32_t next = pos + n;
-        if (next < end) load_chunk(a, next, (int)min(64u, end - next), 1, lane, false, q);
+        if (next < end) load_gauss_chunk(a, next, end, lane, q);
         int since_check = 0;
         for (; any; any &= any - 1) {
             const int m = __builtin_ctzll(any);
@@ -463,7 +485,7 @@ __device__ inline void alpha_tile(const CompositeArgs& a, const FrameView& f, in
 // them heaviest first, so long tiles start early and short ones fill in
 // behind them on every XCD.  Every wavefront leaves once the queue is empty.
 // MODE: kModeDuplex, kModeAlpha or kModeLcwsr.
-template <int MODE, bool STATS, bool SAVE>
+template <int MODE, bool STATS, bool SAVE, bool RAGGED>
 __global__ __launch_bounds__(256) void k_composite(CompositeArgs a) {
     __shared__ GRec s_rec[kWaves][64];
     const FrameView f = frame_view(a.fr);
@@ -488,9 +510,9 @@ __global__ __launch_bounds__(256) void k_composite(CompositeArgs a) {
         } else {
             constexpr bool LC = MODE == kModeLcwsr;
             if (mode == 0)
-                duplex_tile<STATS, 4, LC, SAVE>(a, f, tile, 0, lane, lds, cn);
+                duplex_tile<STATS, 4, LC, SAVE, RAGGED>(a, f, tile, 0, lane, lds, cn);
             else
-                duplex_tile<STATS, 2, LC, SAVE>(a, f, tile, 2 * (mode - 2), lane, lds, cn);
+                duplex_tile<STATS, 2, LC, SAVE, RAGGED>(a, f, tile, 2 * (mode - 2), lane, lds, cn);
         }
     }
     if (STATS) {
@@ -554,24 +576,30 @@ void launch_tile_order(hipStream_t st, const uint32_t* ranges, int tiles, uint32
     hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, st, ranges, tiles, split_len, order, queue);
 }
 
+template <int MODE, bool SAVE, bool RAGGED>
+static void launch_variant(hipStream_t st, dim3 g, dim3 b, const CompositeArgs& a) {
+    if (a.counters)
+        hipLaunchKernelGGL((k_composite<MODE, true, SAVE, RAGGED>), g, b, 0, st, a);
+    else
+        hipLaunchKernelGGL((k_composite<MODE, false, SAVE, RAGGED>), g, b, 0, st, a);
+}
+
 template <int MODE>
 static void launch_mode(hipStream_t st, const CompositeArgs& a) {
     const int tiles = a.k.TX * a.k.TY;  // host copy of the frame's tile grid
     if (tiles <= 0) return;
     const dim3 g(persistent_grid(tiles)), b(256);
-    if constexpr (MODE == kModeDuplex) {
-        if (a.save) {
-            if (a.counters)
-                hipLaunchKernelGGL((k_composite<MODE, true, true>), g, b, 0, st, a);
-            else
-                hipLaunchKernelGGL((k_composite<MODE, false, true>), g, b, 0, st, a);
-            return;
-        }
+    if constexpr (MODE == kModeAlpha) {
+        launch_variant<MODE, false, false>(st, g, b, a);
+    } else if constexpr (MODE == kModeDuplex) {
+        if (a.save && a.offs) launch_variant<MODE, true, true>(st, g, b, a);
+        else if (a.save) launch_variant<MODE, true, false>(st, g, b, a);
+        else if (a.offs) launch_variant<MODE, false, true>(st, g, b, a);
+        else launch_variant<MODE, false, false>(st, g, b, a);
+    } else {
+        if (a.offs) launch_variant<MODE, false, true>(st, g, b, a);
+        else launch_variant<MODE, false, false>(st, g, b, a);
     }
-    if (a.counters)
-        hipLaunchKernelGGL((k_composite<MODE, true, false>), g, b, 0, st, a);
-    else
-        hipLaunchKernelGGL((k_composite<MODE, false, false>), g, b, 0, st, a);
 }
 
 void launch_composite_duplex(hipStream_t st, const CompositeArgs& a) { launch_mode<kModeDuplex>(st, a); }

@@ -20,6 +20,7 @@ struct dgs_frame_s {
     dgs::OptK o;
     int N = 0, K = 0, tiles = 0;
     int64_t M = 0;
+    const int32_t* offs = nullptr;  // the scene's CSR offsets (null: fixed layout)
     dgs::GRec* recs = nullptr;  // [M] projected Gaussians
     int64_t cap_recs = 0;
     float* cell_v = nullptr;    // [N] v_n

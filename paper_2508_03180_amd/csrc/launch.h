@@ -25,9 +25,12 @@ struct DecodeArgs {
 };
 void launch_decode(hipStream_t st, const DecodeArgs& a);
 
+// offs: CSR member offsets [N+1] (null: the fixed layout) of M Gaussians,
+// each cell at most kmax; malformed ranges cull the cell and set
+// 1 << kErrInvalid in *err.
 void launch_cell_preprocess(hipStream_t st, int N, const float* pos, const float* scale, const float* rot,
-                            const float* vsh, int vdeg, const FrameK* fr, uint32_t* depth_bits,
-                            uint64_t* prect, uint32_t* ntiles, float* v);
+                            const float* vsh, int vdeg, const int32_t* offs, int M, int kmax, const FrameK* fr,
+                            uint32_t* depth_bits, uint64_t* prect, uint32_t* ntiles, float* v, int* err);
 
 void launch_gauss_project(hipStream_t st, int M, int K, const float* means, const float* scales,
                           const float* rots, const float* opac, const float* sh, int sh_deg, const FrameK* fr,
@@ -112,7 +115,8 @@ struct CompositeArgs {
     const uint32_t* vals;
     const GRec* recs;
     const float* cell_v;  // Duplex only
-    int K;
+    const int32_t* offs;  // [N+1] members of cell n: Gaussians offs[n] .. offs[n+1]-1; null: K per cell
+    int K;                // members per cell (fixed), or their upper bound
     const FrameK* fr;  // the frame's camera and options (device)
     CamK k;            // filled from fr inside the kernel
     OptK o;
@@ -150,6 +154,7 @@ struct BwdArgs {
     const uint32_t* vals;
     const GRec* recs;
     const float* cell_v;
+    const int32_t* offs;  // as in CompositeArgs
     int K, M;
     const FrameK* fr;  // the frame's camera and options (device)
     CamK k;            // filled from fr inside the kernels

@@ -128,26 +128,38 @@ __device__ inline void unit_dir(const CamK& k, float px, float py, float pz, flo
 
 // a1: one thread per cell.  Outputs the camera-depth key bits, the packed
 // pixel rectangle of the kappa-sigma proxy box padded by 3 sqrt(delta), the
-// number of tiles it touches (0 = culled) and v_n.
+// number of tiles it touches (0 = culled) and v_n.  With CSR offsets it also
+// checks the cell's member range (start >= 0, count in 0..kmax, end <= M,
+// offs[0] = 0, offs[N] = M): a cell that breaks it is culled (no keys, so no
+// walk reads its members) and the device error flag is set.
 __global__ __launch_bounds__(256) void k_cell_preprocess(int N, const float* __restrict__ pos,
                                                          const float* __restrict__ scale,
                                                          const float* __restrict__ rot,
                                                          const float* __restrict__ vsh, int vdeg,
+                                                         const int32_t* __restrict__ offs, int M, int kmax,
                                                          const FrameK* __restrict__ fr,
                                                          uint32_t* __restrict__ depth_bits,
                                                          uint64_t* __restrict__ prect,
-                                                         uint32_t* __restrict__ ntiles, float* __restrict__ v_out) {
+                                                         uint32_t* __restrict__ ntiles, float* __restrict__ v_out,
+                                                         int* __restrict__ err) {
     int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
     const CamK k = fr->k;
     const OptK o = fr->o;
+    bool members_ok = true;
+    if (offs) {
+        const int a0 = offs[n], a1 = offs[n + 1];
+        members_ok = a0 >= 0 && a1 >= a0 && a1 - a0 <= kmax && a1 <= M && (n > 0 || a0 == 0) &&
+                     (n < N - 1 || a1 == M);
+        if (!members_ok) atomicOr(err, 1 << kErrInvalid);
+    }
     float p0 = pos[n], p1 = pos[N + n], p2 = pos[2 * N + n];
     float tc[3];
     view32(k, p0, p1, p2, tc);
     depth_bits[n] = __float_as_uint(tc[2]);
     uint64_t pr = kEmptyRect;
     uint32_t nt = 0;
-    if (tc[2] > k.znear) {
+    if (members_ok && tc[2] > k.znear) {
         float cov[3];
         ewa32(k, tc, scale[n], scale[N + n], scale[2 * N + n], rot[n], rot[N + n], rot[2 * N + n], rot[3 * N + n],
               cov);
@@ -282,11 +294,11 @@ __global__ __launch_bounds__(256) void k_gauss_project(
 }
 
 void launch_cell_preprocess(hipStream_t st, int N, const float* pos, const float* scale, const float* rot,
-                            const float* vsh, int vdeg, const FrameK* fr, uint32_t* depth_bits,
-                            uint64_t* prect, uint32_t* ntiles, float* v) {
+                            const float* vsh, int vdeg, const int32_t* offs, int M, int kmax, const FrameK* fr,
+                            uint32_t* depth_bits, uint64_t* prect, uint32_t* ntiles, float* v, int* err) {
     if (N <= 0) return;
     hipLaunchKernelGGL(k_cell_preprocess, dim3((N + 255) / 256), dim3(256), 0, st, N, pos, scale, rot, vsh, vdeg,
-                       fr, depth_bits, prect, ntiles, v);
+                       offs, M, kmax, fr, depth_bits, prect, ntiles, v, err);
 }
 
 void launch_gauss_project(hipStream_t st, int M, int K, const float* means, const float* scales,

@@ -335,7 +335,7 @@ struct dgs_server_s {
 
     WorkspaceCaps want_of(const Request& r) const {
         const dgs_scene& sc = scenes[r.scene];
-        const int64_t M = (int64_t)sc.num_cells * sc.gaussians_per_cell;
+        const int64_t M = sc.cell_offsets ? (int64_t)sc.num_gaussians : (int64_t)sc.num_cells * sc.gaussians_per_cell;
         const int64_t P = r.mode != DGS_MODE_ALPHA ? sc.num_cells : M;
         const int64_t tiles = (int64_t)((r.cam.width + kTile - 1) / kTile) * ((r.cam.height + kTile - 1) / kTile);
         auto it = key_est.find(r.shape);

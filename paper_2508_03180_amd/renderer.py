@@ -26,12 +26,14 @@ def _planar_t(t):
 
 
 class DeviceScene:
-    """A scene resident in device memory in the library's planar layout."""
+    """A scene resident in device memory in the library's planar layout.
+    With tensors["cell_offsets"] (int32 [N+1]) the cells have their own
+    member counts (at most K each) and M = offsets[N]."""
 
-    def __init__(self, tensors, N, K, v_sh_degree, sh_degree):
+    def __init__(self, tensors, N, K, v_sh_degree, sh_degree, M=None):
         self.t = tensors
         self.N, self.K = int(N), int(K)
-        self.M = self.N * self.K
+        self.M = self.N * self.K if M is None else int(M)
         self.v_sh_degree, self.sh_degree = int(v_sh_degree), int(sh_degree)
 
     @classmethod
@@ -45,7 +47,12 @@ class DeviceScene:
                  rots=_planar(scene["rots"], device),
                  opacities=torch.as_tensor(np.ascontiguousarray(scene["opacities"], np.float32)).to(device),
                  sh=torch.as_tensor(np.ascontiguousarray(sh.transpose(1, 2, 0))).to(device))
-        return cls(t, N, K, scene["v_sh_degree"], scene["sh_degree"])
+        M = None
+        if scene.get("cell_offsets") is not None:
+            offs = np.ascontiguousarray(scene["cell_offsets"], np.int32)
+            t["cell_offsets"] = torch.as_tensor(offs).to(device)
+            M = int(offs[-1])
+        return cls(t, N, K, scene["v_sh_degree"], scene["sh_degree"], M)
 
     @classmethod
     def from_tensors(cls, cell_pos, cell_scale, cell_rot, cell_v_sh, means, scales, rots, opacities, sh, K):
@@ -69,6 +76,9 @@ class DeviceScene:
             setattr(s, k, self.t[k].data_ptr() if self.t[k].numel() else None)
         s.v_sh_degree = self.v_sh_degree
         s.sh_degree = self.sh_degree
+        if "cell_offsets" in self.t:
+            s.cell_offsets = self.t["cell_offsets"].data_ptr()
+            s.num_gaussians = self.M
         return s
 
 

@@ -196,6 +196,59 @@ def make_neural_scene(seed=1, n_cells=100_000, K=10, F=32, H=32):
     return scene, decoder
 
 
+def make_ragged_scene(seed=0, n_cells=1500, k_max=32, sh_degree=0):
+    """Tiny-scene cells that each emit their own number of Gaussians (Sec.
+    IV-A: a cell spawns its Gaussians; nothing fixes their count): counts
+    uniform over 0..k_max with a tenth of the cells at k_max and a twentieth
+    empty, stored as CSR offsets ``cell_offsets`` [N+1] (members of cell n
+    are Gaussians cell_offsets[n] .. cell_offsets[n+1]-1)."""
+    rng = np.random.default_rng(seed)
+    N = n_cells
+    counts = rng.integers(0, k_max + 1, N)
+    counts[rng.random(N) < 0.1] = k_max
+    counts[rng.random(N) < 0.05] = 0
+    offsets = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    M = int(offsets[-1])
+    cell_pos = rng.uniform(-1.0, 1.0, (N, 3))
+    cell_scale = np.exp(rng.normal(-3.0, 0.3, (N, 3)))
+    cell_rot = _unit_quats(rng, N)
+    cell_v_sh = _v_sh(rng, N, 1)
+    rep = np.repeat(np.arange(N), counts)
+    u = _points_in_unit_ball(rng, M)
+    means = cell_pos[rep] + _rotate(cell_rot[rep].astype(np.float64), u * cell_scale[rep])
+    scales = np.exp(rng.normal(-4.5, 0.4, (M, 3)))
+    rots = _unit_quats(rng, M)
+    opac = _sigmoid(rng.standard_normal(M))
+    C = (sh_degree + 1) ** 2
+    sh = np.concatenate([((rng.uniform(0.0, 1.0, (M, 3)) - 0.5) / _Y00)[:, None, :],
+                         rng.normal(0.0, 0.2, (M, C - 1, 3))], 1)
+    out = _f32(dict(cell_pos=cell_pos, cell_scale=cell_scale, cell_rot=cell_rot, cell_v_sh=cell_v_sh,
+                    v_sh_degree=1, means=means, scales=scales, rots=rots, opacities=opac, sh=sh,
+                    sh_degree=sh_degree, K=k_max))
+    out["cell_offsets"] = offsets
+    return out
+
+
+def pad_to_fixed_k(scene, K=None):
+    """The same scene with K members per cell: each cell's Gaussians in their
+    order, then invalid ones (opacity 0) up to K.  Renders identically (an
+    invalid Gaussian has no keys and no contribution)."""
+    offs = np.asarray(scene["cell_offsets"], np.int64)
+    counts = np.diff(offs)
+    N = counts.shape[0]
+    K = int(counts.max()) if K is None else K
+    slot = np.arange(K)[None, :]
+    have = slot < counts[:, None]
+    src = np.where(have, offs[:-1, None] + slot, 0).reshape(-1)
+    out = {k: v for k, v in scene.items() if k != "cell_offsets"}
+    for k in ("means", "scales", "rots", "sh"):
+        out[k] = np.ascontiguousarray(scene[k][src])
+    out["opacities"] = np.where(have.reshape(-1), scene["opacities"][src], 0.0).astype(np.float32)
+    out["K"] = K
+    assert N == scene["cell_pos"].shape[0]
+    return out
+
+
 def subset_scene(scene, cells):
     """Scene restricted to the given cell indices (members follow their cells)."""
     cells = np.asarray(cells)

@@ -404,3 +404,11 @@ def test_planar_autograd_function(R):
             continue
         want = torch.tensor(planar(k, nat[k].grad.cpu().numpy()), device="cuda")
         torch.testing.assert_close(pl[k].grad, want, rtol=1e-5, atol=1e-6, msg=k)
+
+
+def test_backward_ragged_cells(R):
+    """Cells with their own member counts (CSR offsets, 0..32 members):
+    gradients against the binary64 oracle."""
+    s = scenes.make_ragged_scene(3, n_cells=300, sh_degree=1)
+    cam = scenes.tiny_camera(64, 64)
+    check(run_case(R, s, cam, np.ones((64, 64)), seed=10))

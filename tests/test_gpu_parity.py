@@ -516,3 +516,74 @@ def test_stats_counters_match_oracle(R):
         assert st["n_rendered"] == int(ref["nrend"].sum())
     else:
         assert abs(st["n_val"] - int(ref["nval"].sum())) <= 8 * (ref["status"] != 0).sum()
+
+
+# ------------------------------------------------------------------ ragged cells
+
+@pytest.mark.parametrize("mode,kw", [("duplex", {}), ("lcwsr", dict(tau=4.5)), ("duplex", dict(no_et=True)),
+                                     ("alpha", {})])
+def test_ragged_cells_against_oracle(R, mode, kw):
+    """Cells with their own member counts (0..32, CSR offsets): lists
+    bit-exact, pixels within the tolerance, D, T and `last` on exact pixels;
+    the cell modes also give the same bits as the scene padded to 32
+    members per cell with invalid Gaussians."""
+    s = scenes.make_ragged_scene(0)
+    cam = scenes.tiny_camera()
+    out = {k: v.clone() for k, v in R.render(upload(s), cam, mode=mode, **kw).items()}
+    keys, vals, ranges = R.read_lists(256)
+    d = oracle.cells_discrete(s, cam) if mode != "alpha" else oracle.gauss_discrete(s, cam)
+    ids, _, oranges = oracle.build_lists(d["visible"], d["depth_bits"], d["rect"], 256, 256)
+    assert keys.numel() == len(ids) > 1000
+    np.testing.assert_array_equal(vals.cpu().numpy(), ids)
+    np.testing.assert_array_equal(ranges.cpu().numpy(), oranges)
+    ref = oracle.render(s, cam, mode=mode, **kw)
+    check_image(out, ref)
+    check_aux(out, ref, d_rtol=1e-5 if mode == "lcwsr" else 0.0)
+    if mode != "alpha":
+        pad = R.render(upload(scenes.pad_to_fixed_k(s)), cam, mode=mode, **kw)
+        for k in ("color", "D", "T", "last"):
+            assert torch.equal(out[k], pad[k]), k
+
+
+def test_ragged_cells_wide_view(R):
+    """A 1280x720 view of a larger ragged scene (k_max 12): lists and pixels."""
+    s = scenes.make_ragged_scene(5, n_cells=20_000, k_max=12, sh_degree=3)
+    cam = scenes.pinhole(scenes.tiny_camera()["viewmat"], 1280, 720, fov_x_deg=50.0)
+    out = R.render(upload(s), cam)
+    cd = oracle.cells_discrete(s, cam)
+    keys, vals, ranges = R.read_lists(80 * 45)
+    ids, _, oranges = oracle.build_lists(cd["visible"], cd["depth_bits"], cd["rect"], 1280, 720)
+    np.testing.assert_array_equal(vals.cpu().numpy(), ids)
+    np.testing.assert_array_equal(ranges.cpu().numpy(), oranges)
+    ref = oracle.render(s, cam)
+    check_image(out, ref)
+    check_aux(out, ref)
+
+
+def test_malformed_offsets_are_reported(R):
+    """A cell whose offsets run backwards, or claim more than K members, is
+    culled on the device and dgs_sync reports DGS_ERR_INVALID_ARG; the other
+    cells render as without it."""
+    from paper_2508_03180_amd import _capi
+    from paper_2508_03180_amd.renderer import opts_struct
+    s = scenes.make_ragged_scene(2, n_cells=300, k_max=8)
+    cam = scenes.tiny_camera()
+    ds = upload(s)
+    good = R.render(ds, cam)["color"].clone()
+    offs = s["cell_offsets"].copy()
+    n = int(np.nonzero(np.diff(offs) >= 2)[0][0])
+    for bad in ("backwards", "too_many"):
+        o = offs.copy()
+        if bad == "backwards":
+            o[n + 1] = o[n] - 1
+        else:
+            o[n + 1:] += 9  # cell n claims 9 + count members (> K = 8)
+            o[-1] = offs[-1]
+        ds.t["cell_offsets"] = torch.tensor(o, device="cuda")
+        out = R.alloc_image(cam)
+        _capi.check(R.render_into(ds, cam, out, opts_struct()), R.ctx)
+        assert _capi.dgs_sync(R.ctx) == _capi.DGS_ERR_INVALID_ARG, bad
+        assert "cell_offsets" in _capi.dgs_last_error(R.ctx)
+        assert torch.isfinite(out["color"]).all()
+    ds.t["cell_offsets"] = torch.tensor(offs, device="cuda")
+    assert torch.equal(R.render(ds, cam)["color"], good)

@@ -122,3 +122,34 @@ def test_c_oracle_finite_differences_eps_1e3():
         assert abs(fd - an) <= 1e-2 * max(abs(an), 1e-2), (key, idx, fd, an)
         checked += 1
     assert checked >= 15
+
+
+def test_ragged_cells_gradient_equals_padded_scene():
+    """Variable member counts (CSR offsets): the forward equals the C oracle
+    and the gradient of every Gaussian equals that of its copy in the same
+    scene padded to 32 members per cell with invalid Gaussians (which get
+    exactly zero)."""
+    s = scenes.make_ragged_scene(3, n_cells=300, sh_degree=1)
+    cam = scenes.tiny_camera(64, 64)
+    pix = np.stack(np.meshgrid(np.arange(64), np.arange(64), indexing="xy"), -1).reshape(-1, 2)
+    fz = go.FrozenScene(s, cam)
+    C, D, T = go.render(go.params_from_scene(s, requires_grad=False), fz, pix)
+    ref = oracle.render(s, cam, pixels=pix)
+    ok = ref["status"] == 0
+    assert (ref["D"] > 0).mean() > 0.3
+    np.testing.assert_allclose(C.numpy()[ok], ref["color"][ok], atol=1e-11)
+    rng = np.random.default_rng(0)
+    gC = rng.standard_normal((pix.shape[0], 3))
+    gD = rng.standard_normal(pix.shape[0])
+    a = go.gradients(s, cam, pix, gC, gD)
+    p = scenes.pad_to_fixed_k(s)
+    b = go.gradients(p, cam, pix, gC, gD)
+    offs = s["cell_offsets"].astype(np.int64)
+    counts = np.diff(offs)
+    have = (np.arange(32)[None, :] < counts[:, None]).reshape(-1)
+    for k in ("means", "scales", "rots", "opacities", "sh"):
+        np.testing.assert_allclose(b[k][have], a[k], rtol=1e-12, atol=1e-14, err_msg=k)
+        assert np.all(b[k][~have] == 0), k
+    for k in ("cell_v_sh", "cell_pos"):
+        np.testing.assert_allclose(b[k], a[k], rtol=1e-12, atol=1e-14, err_msg=k)
+    assert np.abs(a["means"]).max() > 0

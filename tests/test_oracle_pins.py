@@ -625,3 +625,31 @@ def test_v_is_sigmoid_of_sh_logit():
     Y = _scipy_real_sh(1, theta, phi)
     want = 1 / (1 + np.exp(-(Y * s["cell_v_sh"].astype(np.float64)).sum(1)))
     np.testing.assert_allclose(v, want, rtol=1e-12)
+
+
+# ------------------------------------------------------------- ragged cells
+
+@pytest.mark.parametrize("mode,kw", [("duplex", {}), ("alpha", {}), ("lcwsr", dict(tau=4.5)),
+                                     ("duplex", dict(no_et=True))])
+def test_ragged_cells_equal_the_padded_scene(mode, kw):
+    """Cells with their own member counts (0..32, CSR offsets) render exactly
+    as the same scene with every cell padded to 32 members by invalid
+    Gaussians (opacity 0: no keys, no contribution, Sec. VII validity):
+    colour, D, T, last and the counters, pixel for pixel."""
+    s = scenes.make_ragged_scene(0)
+    counts = np.diff(s["cell_offsets"])
+    assert counts.min() == 0 and counts.max() == 32 and len(set(counts.tolist())) > 20
+    cam = scenes.tiny_camera()
+    a = oracle.render(s, cam, mode=mode, **kw)
+    b = oracle.render(scenes.pad_to_fixed_k(s), cam, mode=mode, **kw)
+    for k in ("color", "D", "T", "last", "nrend", "nval", "status"):
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+    assert a["n_keys"] == b["n_keys"] > 1000 and (a["D"] > 0).mean() > 0.3
+
+
+def test_ragged_offsets_are_checked():
+    s = scenes.make_ragged_scene(1, n_cells=50)
+    cam = scenes.tiny_camera(32, 32)
+    for bad in (s["cell_offsets"] + 1, s["cell_offsets"][::-1].copy()):
+        with pytest.raises(ValueError):
+            oracle.render(dict(s, cell_offsets=bad), cam)
