@@ -328,6 +328,22 @@ dgs_status dgs_get_timing(dgs_ctx ctx, float* ms, int32_t n_stages, int32_t* fra
  * buffers of n entries. */
 dgs_status dgs_sort_pairs(dgs_ctx ctx, uint64_t* keys, uint32_t* values, int64_t n, int32_t key_bits);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * sort as dgs_sort_pairs, with the same results, whose scratch memory (the
+ * ping-pong key/value buffers, digit counts, look-back words and counters,
+ * ~14.3 MB) is one static device array per GPU, held from library load until
+ * the process ends.  It calls no hipMalloc, hipFree or allocating routine;
+ * it enqueues on the context's stream (kernels and device-to-device copies,
+ * no memset).  n above DGS_SORT_NOALLOC_MAX_KEYS returns DGS_ERR_INVALID_ARG
+ * and enqueues nothing.  All calls on one GPU share that GPU's array, from
+ * every context and thread: calls whose work overlaps on one GPU (different
+ * streams, or threads) race and give undefined results; serialise them.
+ * Device-side errors (a look-back wait that timed out) are reported by
+ * dgs_sync on the context. */
+#define DGS_SORT_NOALLOC_MAX_KEYS (1 << 20)
+dgs_status dgs_sort_pairs_noalloc(dgs_ctx ctx, uint64_t* keys, uint32_t* values, int64_t n, int32_t key_bits);
+
 /*
  * Serving runtime.  A server renders requests (scene, camera, options,
  * output image) submitted from any host thread.  It keeps num_slots frames

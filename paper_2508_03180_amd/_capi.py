@@ -126,6 +126,7 @@ _SIGS = {
     "dgs_read_prims": (C.c_int, [dgs_ctx, C.c_void_p, C.c_void_p, C.c_void_p]),
     "dgs_read_gauss_rects": (C.c_int, [dgs_ctx, C.c_void_p]),
     "dgs_sort_pairs": (C.c_int, [dgs_ctx, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32]),
+    "dgs_sort_pairs_noalloc": (C.c_int, [dgs_ctx, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32]),
     "dgs_set_timing": (C.c_int, [dgs_ctx, C.c_int32]),
     "dgs_get_timing": (C.c_int, [dgs_ctx, C.POINTER(C.c_float), C.c_int32, C.POINTER(C.c_int32)]),
     "dgs_server_default_config": (None, [C.POINTER(dgs_server_config)]),
@@ -271,6 +272,14 @@ def dgs_read_gauss_rects(ctx, rect_ptr):
 def dgs_sort_pairs(ctx, keys_ptr, values_ptr, n, key_bits):
     return check(lib().dgs_sort_pairs(ctx, C.c_void_p(keys_ptr), C.c_void_p(values_ptr), int(n), int(key_bits)),
                  ctx)
+
+
+DGS_SORT_NOALLOC_MAX_KEYS = 1 << 20
+
+
+def dgs_sort_pairs_noalloc(ctx, keys_ptr, values_ptr, n, key_bits):
+    """Returns the status (no raise): callers check DGS_ERR_INVALID_ARG for n above the maximum."""
+    return lib().dgs_sort_pairs_noalloc(ctx, C.c_void_p(keys_ptr), C.c_void_p(values_ptr), int(n), int(key_bits))
 
 
 def dgs_set_timing(ctx, enable):

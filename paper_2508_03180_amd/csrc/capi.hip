@@ -401,6 +401,7 @@ dgs_status dgs_create(int device, void* hip_stream, dgs_ctx* out) {
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return DGS_ERR_INVALID_ARG;
     if (hipSetDevice(device) != hipSuccess) return DGS_ERR_DEVICE;
+    if (dgs_internal_noalloc_init(device) != hipSuccess) return DGS_ERR_DEVICE;
     dgs_ctx c = new dgs_ctx_s();
     c->device = device;
     c->stream = (hipStream_t)hip_stream;

@@ -96,6 +96,10 @@ struct dgs_ctx_s {
     size_t events_used = 0;
 };
 
+// Looks up the device address of the static scratch array of
+// dgs_sort_pairs_noalloc on `device` (current); once per device.
+hipError_t dgs_internal_noalloc_init(int device);
+
 // Workspace capacities (elements): cells or Gaussians that get keys,
 // projected Gaussians, sort keys, screen tiles.
 struct WorkspaceCaps {
