@@ -38,6 +38,11 @@ PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 #   Duplex blended cell per pixel: w = v T (1), N, D (4 FMA = 8), T *= P (1) = 10
 #   alpha blended Gaussian: clamp (1), w = alpha T (1), C (3 FMA = 6),
 #   T -= w (1)                                                         = 9
+# lane operations per second of the FP32 vector units without packing
+# (256 CUs x 64 lanes x 2.4 GHz) and of the transcendental unit (a quarter
+# of that): the survey's per-lane work model of the compositor
+LANE_OPS_PEAK = 256 * 64 * 2.4e9
+EXP_PEAK = LANE_OPS_PEAK / 4
 FLOP_BOX = 12
 FLOP_DUPLEX_MEMBER = 11
 FLOP_DUPLEX_CELL = 10
@@ -80,6 +85,12 @@ def composite_traffic():
     return COMPOSITE_TRAFFIC_BYTES
 
 
+def progress(msg):
+    """One line on stderr as each part of the run completes (stdout carries
+    only the result line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -87,7 +98,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=10)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-alpha", action="store_true")
-    p.add_argument("--cpu-frames", type=int, default=4)
+    p.add_argument("--cpu-frames", type=int, default=3)
     p.add_argument("--bwd-steps", type=int, default=10)
     p.add_argument("--no-neural", action="store_true")
     p.add_argument("--no-ablation", action="store_true")
@@ -96,7 +107,7 @@ def parse():
     p.add_argument("--no-large", action="store_true")
     p.add_argument("--large-cams", type=int, default=20, help="cameras of each kind (near, far) per resolution")
     p.add_argument("--no-serve", action="store_true")
-    p.add_argument("--serve-seconds", type=float, default=4.0, help="length of each Poisson stream")
+    p.add_argument("--serve-seconds", type=float, default=30.0, help="length of each Poisson stream")
     p.add_argument("--serve-rates", default="30,120,480", help="request rates (req/s)")
     p.add_argument("--serve-slots", type=int, default=4)
     p.add_argument("--serve-budget-gb", type=float, default=16.0, help="workspace budget of the server")
@@ -425,6 +436,7 @@ def serving(a):
                 sched = poisson_schedule(rate, a.serve_seconds, 4, cams, seed=100 + k)
                 res[f"{int(rate)}"] = {kk: (round(v, 4) if isinstance(v, float) else v)
                                        for kk, v in run_load(srv, ids, sched, rate).summary().items()}
+                progress(f"serving {name} at {rate:g} req/s: p99 {res[f'{int(rate)}'].get('p99_ms')} ms")
             st = srv.stats()
             res["stats"] = {k: st[k] for k in ("completed", "failed", "retries", "graph_captures",
                                                "graph_replays", "releases", "peak_workspace_bytes")}
@@ -434,6 +446,50 @@ def serving(a):
         out[f"p99_speedup_{k}"] = round(o["p99_ms"] / s["p99_ms"], 3) if s["p99_ms"] else None
     out["throughput_speedup"] = round(out["server"]["saturated_frames_per_s"]
                                       / out["one_at_a_time"]["saturated_frames_per_s"], 3)
+    return out
+
+
+def cpu_baseline(scene, cams, nframes):
+    """The oracle (plain CPU reference, not an optimised renderer) timed on
+    the host: the headline value is full 1080p frames of the benchmark's
+    workload on every host thread; also one frame on one thread, the
+    per-Gaussian alpha-blend oracle on one frame, the tiny scene (median of
+    three) and two street-level plus two aerial 720p views of the large
+    scene."""
+    import numpy as np
+
+    import oracle
+    from paper_2508_03180_amd import scenes
+
+    allc = oracle.num_threads()
+
+    def per_frame(fn, reps=1):
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    idx = [0, 20, 40][:nframes]
+    t = sum(per_frame(lambda i=i: oracle.render(scene, cams[i])) for i in idx)
+    out = {"value": round(len(idx) / t, 4), "unit": "frames/s", "cores": allc, "kind": "oracle",
+           "sample": f"{len(idx)} full 1920x1080 frames (orbit frames {idx}) of the benchmark scene, "
+                     f"Duplex oracle on {allc} threads"}
+    out["alpha_oracle_frame_s"] = round(per_frame(lambda: oracle.render(scene, cams[0], mode="alpha")), 3)
+    tiny, tcam = scenes.make_tiny_scene(0), scenes.tiny_camera()
+    out["tiny_frame_ms"] = round(1e3 * per_frame(lambda: oracle.render(tiny, tcam), 3), 2)
+    large = scenes.make_large_scene(2)
+    lc = scenes.large_scene_cameras(2, 1280, 720, n_near=20, n_far=20)
+    out["large_720p_frame_s"] = round(np.mean([per_frame(lambda c=c: oracle.render(large, c))
+                                               for c in (lc[0], lc[1], lc[20], lc[21])]), 3)
+    del large
+    oracle.set_threads(1)
+    try:
+        out["one_core"] = {"frame_s": round(per_frame(lambda: oracle.render(scene, cams[0])), 3),
+                           "tiny_frame_ms": round(1e3 * per_frame(lambda: oracle.render(tiny, tcam), 3), 2)}
+    finally:
+        oracle.set_threads(allc)
     return out
 
 
@@ -513,11 +569,11 @@ def main():
         return {k: v / nfr for k, v in zip(capi.STAGE_NAMES, ms)}
 
     def counters(mode, idx):
-        tot = dict(n_val=0, n_rendered=0, n_box=0, n_cell_hits=0, keys=0, projected=0)
+        tot = dict(n_val=0, n_rendered=0, n_box=0, n_cell_hits=0, n_cell_pixels=0, keys=0, projected=0)
         for i in idx:
             r.render(ds, cams[i], out=out, mode=mode, stats=True)
             s = r.stats()
-            for k in ("n_val", "n_rendered", "n_box", "n_cell_hits"):
+            for k in ("n_val", "n_rendered", "n_box", "n_cell_hits", "n_cell_pixels"):
                 tot[k] += s[k]
             tot["keys"] += s["num_keys"]
             if mode == "duplex":
@@ -530,6 +586,7 @@ def main():
     keys_dup = size_all("duplex")
     dt = timed("duplex", a.steps, a.warmup)
     fps = a.steps / dt
+    progress(f"duplex: {fps:.1f} frames/s")
     st_dup = stage_times("duplex")
     fr_dup = frame_times("duplex")
     cnt = counters("duplex", range(0, NF, 6))
@@ -541,6 +598,7 @@ def main():
         st_alpha = stage_times("alpha")
         fr_alpha = frame_times("alpha")
         cnt_a = counters("alpha", range(0, NF, 6))
+        progress(f"alpha-blend baseline: {a.steps / dta:.1f} frames/s")
         comp_a = st_alpha["composite"]
         flops_a = FLOP_BOX * cnt_a["n_box"] + FLOP_ALPHA_HIT * cnt_a["n_rendered"]
         alpha = {"fps": round(a.steps / dta, 2), "ms_per_step": round(1e3 * dta / a.steps, 4), "frame_ms": fr_alpha,
@@ -558,34 +616,47 @@ def main():
     flops = (FLOP_BOX * cnt["n_box"] + FLOP_DUPLEX_MEMBER * cnt["n_rendered"]
              + FLOP_DUPLEX_CELL * cnt["n_cell_hits"])
     achieved = flops / (comp_ms * 1e-3) / 1e12
-    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP32_UNPACKED_TFLOPS, 2),
-            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_UNPACKED_TFLOPS, 4),
-            "peak_packed_fp32": PEAK_FP32_TFLOPS, "traffic": composite_traffic(),
-            "kernel": "k_composite<0, false>", "kernel_ms": round(comp_ms, 4),
-            "algorithmic_gflop_per_launch": round(flops / 1e9, 4)}
+    # the survey's work terms: E in-box member-pixel evaluations (~16 lane
+    # operations and one exp each), L listed member-pixel pairs (~4 for the
+    # box test), cell-pixel pairs reached (~8 for the cell update)
+    E, cp = cnt["n_box"], cnt["n_cell_pixels"]
+    Lp = cp * ds.K
+    lane_ops = 16 * E + 4 * Lp + 8 * cp
+    t_s = comp_ms * 1e-3
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+            "peak_issuable_unpacked": round(PEAK_FP32_UNPACKED_TFLOPS, 2),
+            "frac_of_issuable": round(achieved / PEAK_FP32_UNPACKED_TFLOPS, 4), "traffic": composite_traffic(),
+            "kernel": "k_composite<0, false, false, false>", "kernel_ms": round(comp_ms, 4),
+            "algorithmic_gflop_per_launch": round(flops / 1e9, 4),
+            "work_terms": {"E_inbox_member_pixels": int(E), "L_listed_member_pixels": int(Lp),
+                           "cell_pixels": int(cp), "lane_ops_per_launch": int(lane_ops),
+                           "lane_op_rate_T_per_s": round(lane_ops / t_s / 1e12, 3),
+                           "lane_op_frac_of_39_3T": round(lane_ops / t_s / LANE_OPS_PEAK, 4),
+                           "exp_rate_T_per_s": round(E / t_s / 1e12, 3),
+                           "exp_frac_of_9_8T": round(E / t_s / EXP_PEAK, 4)}}
     proj_gbs = cnt["projected"] * BYTES_PROJECT_SH3 / (st_dup["gauss_project"] * 1e-3) / 1e9
 
     # differentiation: forward + 0.8 L1 + 0.2 (1 - SSIM) + backward at 1080p
     # against a target rendered from a perturbed copy of the scene
     bwd = differentiation(r, scene, cams[0], a.bwd_steps)
+    progress(f"differentiation: {bwd['fwd_loss_bwd_ms']} ms per step")
 
     neu = None if a.no_neural else neural(a, cams, a.steps)
+    progress("neural decode done")
     abl = None if a.no_ablation else ablation(r, ds, cams, a.steps)
+    progress("ablation done")
     ksw = None if a.no_ksweep else k_sweep(a)
+    progress("K sweep done")
     large = None if a.no_large else large_scene(a)
+    progress("large scene done")
     serve = None if a.no_serve else serving(a)
+    progress("serving done")
 
     cpu = None
     if not a.no_cpu_baseline:
-        import oracle
-        idx = [0, 15, 30, 45][: a.cpu_frames]
-        t0 = time.perf_counter()
-        for i in idx:
-            oracle.render(scene, cams[i])
-        cdt = time.perf_counter() - t0
-        cpu = {"value": round(len(idx) / cdt, 4), "unit": "frames/s", "cores": oracle.num_threads(),
-               "kind": "oracle",
-               "sample": f"{len(idx)} full 1920x1080 frames (orbit frames {idx}) of the same scene"}
+        cpu = cpu_baseline(scene, cams, a.cpu_frames)
+        progress("cpu baseline done")
 
     line = {
         "metric": "FPS @1080p, 1M Gaussians vs per-Gaussian-sort baseline; serve p50/p99 ms",
@@ -594,7 +665,10 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "clustered scene, 100k cells x 10 Gaussians (1M), SH degree 3, "
                                "1920x1080, 60-frame orbit", "cells": ds.N, "gaussians": ds.M,
-                   "width": W, "height": H, "frames": NF},
+                   "width": W, "height": H, "frames": NF,
+                   "timed_frames": f"orbit frames i mod {NF} for i = 0..{a.steps - 1} "
+                                   f"({'the whole orbit' if a.steps >= NF else f'{a.steps} of {NF} frames'}), "
+                                   f"after {a.warmup} untimed warm-up frames"},
         "alpha_baseline": alpha,
         "speedup_vs_alpha": None if alpha is None else round(fps / alpha["fps"], 3),
         "frame_ms": fr_dup,

@@ -162,6 +162,8 @@ typedef struct {
     int64_t n_cell_hits;   /* (pixel, list entry) pairs that contributed (Duplex: cells; alpha: Gaussians) */
     int32_t device_error;  /* dgs_status of the last device-side error, 0 if none */
     int32_t sort_passes;   /* radix passes of the last sort */
+    int64_t n_cell_pixels; /* (pixel, cell) pairs the cell walks reach (listed cells of the pixel's tile before
+                              termination; DGS_FLAG_STATS renders in the Duplex and LC-WSR modes, else 0) */
 } dgs_stats;
 
 /* Fills *opts with the defaults listed above (mode Duplex, flags 0). */

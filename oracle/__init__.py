@@ -85,6 +85,11 @@ def num_threads():
     return int(_load().orc_num_threads())
 
 
+def set_threads(n):
+    """Threads the oracle's later calls use (timing of the CPU baseline)."""
+    _load().orc_set_threads(C.c_int(int(n)))
+
+
 def cells_discrete(scene, cam, kappa=1.0, delta=0.3):
     L = _load()
     N = scene["cell_pos"].shape[0]

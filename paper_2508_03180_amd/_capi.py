@@ -62,7 +62,7 @@ class dgs_grads(C.Structure):
 class dgs_stats(C.Structure):
     _fields_ = [("num_keys", C.c_int64), ("key_capacity", C.c_int64), ("n_val", C.c_int64),
                 ("n_rendered", C.c_int64), ("n_box", C.c_int64), ("n_cell_hits", C.c_int64),
-                ("device_error", C.c_int32), ("sort_passes", C.c_int32)]
+                ("device_error", C.c_int32), ("sort_passes", C.c_int32), ("n_cell_pixels", C.c_int64)]
 
 
 class dgs_decoder(C.Structure):

@@ -308,7 +308,7 @@ bool own_live_frame(dgs_ctx c, dgs_frame f) {
 __global__ void k_frame_info(const uint32_t* misc, const unsigned long long* counters, uint32_t* info) {
     const int i = threadIdx.x;
     if (i == 0) info[2] = misc[0];
-    if (i < 4) reinterpret_cast<unsigned long long*>(info + 4)[i] = counters[i];
+    if (i < 5) reinterpret_cast<unsigned long long*>(info + 4)[i] = counters[i];
 }
 
 }  // namespace
@@ -408,7 +408,7 @@ dgs_status dgs_create(int device, void* hip_stream, dgs_ctx* out) {
     if (hipMalloc((void**)&c->hist, 8 * 256 * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc((void**)&c->misc, 16 * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc((void**)&c->dev_err, sizeof(int)) != hipSuccess ||
-        hipMalloc((void**)&c->counters, 4 * sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc((void**)&c->counters, 5 * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc((void**)&c->frame, sizeof(FrameK)) != hipSuccess) {
         dgs_destroy(c);
         return DGS_ERR_OOM;
@@ -423,7 +423,7 @@ dgs_status dgs_create(int device, void* hip_stream, dgs_ctx* out) {
     }
     hipMemsetAsync(c->misc, 0, 16 * sizeof(uint32_t), c->stream);
     hipMemsetAsync(c->dev_err, 0, sizeof(int), c->stream);
-    hipMemsetAsync(c->counters, 0, 4 * sizeof(unsigned long long), c->stream);
+    hipMemsetAsync(c->counters, 0, 5 * sizeof(unsigned long long), c->stream);
     hipStreamSynchronize(c->stream);
     *out = c;
     return DGS_OK;
@@ -601,7 +601,7 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
         cl.add(c->hist, 8 * 256);
         cl.add(c->misc + 1, 12);
         cl.add(ranges, 2 * (size_t)tiles);
-        if (o.stats || save) cl.add((uint32_t*)c->counters, 8);
+        if (o.stats || save) cl.add((uint32_t*)c->counters, 10);
         cl.bump = c->misc + 13;
         FrameK f{k, o, out->color, out->weight_sum, out->final_T, out->last, nullptr, nullptr, nullptr, nullptr};
         if (save) {
@@ -822,7 +822,7 @@ dgs_status dgs_frame_stats(dgs_ctx c, dgs_frame f, dgs_stats* out) {
     uint32_t info[16];
     if (hipMemcpy(info, f->info, sizeof info, hipMemcpyDeviceToHost) != hipSuccess)
         return fail(c, DGS_ERR_DEVICE, "frame counters readback failed");
-    unsigned long long cnt[4];
+    unsigned long long cnt[5];
     memcpy(cnt, info + 4, sizeof cnt);
     memset(out, 0, sizeof *out);
     out->num_keys = info[2];
@@ -831,6 +831,7 @@ dgs_status dgs_frame_stats(dgs_ctx c, dgs_frame f, dgs_stats* out) {
     out->n_rendered = (int64_t)cnt[1];
     out->n_box = (int64_t)cnt[2];
     out->n_cell_hits = (int64_t)cnt[3];
+    out->n_cell_pixels = (int64_t)cnt[4];
     return DGS_OK;
 }
 
@@ -857,7 +858,7 @@ dgs_status dgs_get_stats(dgs_ctx c, dgs_stats* out) {
     hipSetDevice(c->device);
     if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, DGS_ERR_DEVICE, "stream synchronize failed");
     uint32_t total = 0;
-    unsigned long long cnt[4] = {0, 0, 0, 0};
+    unsigned long long cnt[5] = {0, 0, 0, 0, 0};
     int e = 0;
     hipMemcpy(&total, c->misc, sizeof(uint32_t), hipMemcpyDeviceToHost);
     hipMemcpy(cnt, c->counters, sizeof(cnt), hipMemcpyDeviceToHost);
@@ -868,6 +869,7 @@ dgs_status dgs_get_stats(dgs_ctx c, dgs_stats* out) {
     out->n_rendered = (int64_t)cnt[1];
     out->n_box = (int64_t)cnt[2];
     out->n_cell_hits = (int64_t)cnt[3];
+    out->n_cell_pixels = (int64_t)cnt[4];
     out->device_error = (e & (1 << kErrTimeout))    ? DGS_ERR_TIMEOUT
                         : (e & (1 << kErrInvalid))  ? DGS_ERR_INVALID_ARG
                         : (e & (1 << kErrCapacity)) ? DGS_ERR_CAPACITY

@@ -33,6 +33,7 @@ namespace dgs {
 
 constexpr int kWaves = 4;  // tiles per workgroup
 
+
 struct Chunk {
     float4 r0, r1, r2;  // this lane's record
     float v;            // v of this lane's cell (Duplex walks)
@@ -183,7 +184,7 @@ __device__ inline FrameView frame_view(const FrameK* fr) {
 // 1 - n_rendered / n_val), in-box member evaluations and (pixel, entry) pairs
 // that contributed, for the algorithmic work count.
 struct Counters {
-    uint32_t val = 0, rend = 0, box = 0, cellhit = 0;
+    uint32_t val = 0, rend = 0, box = 0, cellhit = 0, cellpx = 0;
 };
 
 // The hybrid renderer over one tile (NS = 4) or one half (NS = 2, strips s0
@@ -256,6 +257,10 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
         const uint32_t next = pos + nch;
         if (next < end) load_cell_chunk<RAGGED>(a, next, end, lane, q);
         for (int c = 0; c < nch; c++) {
+            if (STATS) {  // (pixel, cell) pairs the walk reaches: listed, in the image, not terminated
+#pragma unroll
+                for (int j = 0; j < NS; j++) cn.cellpx += LC ? inb[j] : inb[j] && !(T[j] < eps);
+            }
             // fixed K: cell c holds record lanes cK .. cK + K - 1
             const int base = RAGGED ? lane_value(cfirst, c) : c * K;
             const uint32_t cm = RAGGED ? member_mask(lane_value(ccnt, c)) : kmask;
@@ -520,47 +525,73 @@ __global__ __launch_bounds__(256) void k_composite(CompositeArgs a) {
         atomicAdd(&a.counters[1], (unsigned long long)cn.rend);
         atomicAdd(&a.counters[2], (unsigned long long)cn.box);
         atomicAdd(&a.counters[3], (unsigned long long)cn.cellhit);
+        atomicAdd(&a.counters[4], (unsigned long long)cn.cellpx);
     }
 }
 
-// Builds the work queue: one item per tile, or one per half for tiles whose
-// list has at least split_len entries; items are bucketed by
-// floor(log2(estimated cost)) and laid out from costly to cheap (order inside
-// a bucket is arbitrary: it only affects scheduling, never results).
+// Builds the work queue: per tile one whole-tile item, or for lists of at
+// least split_len entries two half-tile items.  Items are counting-sorted by
+// estimated cost -- list length times the vector instructions a list
+// entry's member costs over the item's strips -- and laid out costliest
+// first, so the longest walks start at once (order within a cost class is
+// arbitrary: it only affects scheduling, never results).
 // queue[0] = head (reset), queue[1] = item count.  One workgroup.
+constexpr int kOrderClasses = 4096;
+
+__device__ inline void tile_items(uint32_t len, uint32_t split_len, uint32_t& n, uint32_t& cls) {
+    // vector instructions per member of a whole-tile (4 strips) and a half
+    // (2 strips) walk, counted in the compiled member loop
+    const uint32_t w = len >= split_len ? 45u : 77u;
+    n = len >= split_len ? 2u : 1u;
+    const uint32_t c = (len * w) >> 5;
+    cls = c < (uint32_t)kOrderClasses ? c : (uint32_t)kOrderClasses - 1u;
+}
+
 __global__ __launch_bounds__(1024) void k_tile_order(const uint32_t* __restrict__ ranges, int ntiles,
                                                      uint32_t split_len, uint32_t* __restrict__ order,
                                                      uint32_t* __restrict__ queue) {
-    __shared__ uint32_t s_cnt[33], s_off[33];
+    __shared__ uint32_t s_cnt[kOrderClasses];  // counts, then first slot of each class
+    __shared__ uint32_t s_part[1024];
     const int tid = threadIdx.x;
-    if (tid < 33) s_cnt[tid] = 0;
+    for (int i = tid; i < kOrderClasses; i += 1024) s_cnt[i] = 0;
     __syncthreads();
-    for (int t = tid; t < ntiles; t += blockDim.x) {
-        const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
-        if (len >= split_len)
-            atomicAdd(&s_cnt[32 - __clz(len)], 2u);  // two halves, each walking the whole list
-        else
-            atomicAdd(&s_cnt[32 - __clz(len)], 1u);
+    for (int t = tid; t < ntiles; t += 1024) {
+        uint32_t n, cls;
+        tile_items(ranges[2 * t + 1] - ranges[2 * t], split_len, n, cls);
+        atomicAdd(&s_cnt[cls], n);
     }
     __syncthreads();
-    if (tid == 0) {
-        uint32_t run = 0;
-        for (int b = 32; b >= 0; b--) {
-            s_off[b] = run;
-            run += s_cnt[b];
-        }
+    // costliest first: thread i owns classes 4095 - 4i .. 4092 - 4i
+    constexpr int kPer = kOrderClasses / 1024;
+    uint32_t loc[kPer], run = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; j++) {
+        loc[j] = run;
+        run += s_cnt[kOrderClasses - 1 - (kPer * tid + j)];
+    }
+    s_part[tid] = run;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {  // inclusive scan of the per-thread totals
+        const uint32_t x = tid >= o ? s_part[tid - o] : 0u;
+        __syncthreads();
+        s_part[tid] += x;
+        __syncthreads();
+    }
+    const uint32_t before = s_part[tid] - run;
+#pragma unroll
+    for (int j = 0; j < kPer; j++) s_cnt[kOrderClasses - 1 - (kPer * tid + j)] = before + loc[j];
+    if (tid == 1023) {
         queue[0] = 0;
-        queue[1] = run;
+        queue[1] = s_part[1023];
     }
     __syncthreads();
-    for (int t = tid; t < ntiles; t += blockDim.x) {
-        const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
-        if (len >= split_len) {
-            const uint32_t o = atomicAdd(&s_off[32 - __clz(len)], 2u);
-            for (uint32_t h = 0; h < 2; h++) order[o + h] = ((uint32_t)t << 3) | (2u + h);
-        } else {
-            order[atomicAdd(&s_off[32 - __clz(len)], 1u)] = (uint32_t)t << 3;
-        }
+    for (int t = tid; t < ntiles; t += 1024) {
+        uint32_t n, cls;
+        tile_items(ranges[2 * t + 1] - ranges[2 * t], split_len, n, cls);
+        const uint32_t o = atomicAdd(&s_cnt[cls], n);
+        // mode 0: whole tile; 2 + h: half h
+        if (n == 1u) order[o] = (uint32_t)t << 3;
+        else for (uint32_t h = 0; h < 2u; h++) order[o + h] = ((uint32_t)t << 3) | (2u + h);
     }
 }
 

@@ -33,7 +33,7 @@ struct dgs_frame_s {
     float* pix = nullptr;       // [6][H*W]: colour (3 planes), D, replay T, replay start (int32)
     int64_t cap_pix = 0;
     uint32_t* info = nullptr;   // [16]: [0] work-queue head, [1] item count, [2] key total,
-                                // [4..11] n_val, n_rendered, n_box, n_cell_hits (u64)
+                                // [4..13] n_val, n_rendered, n_box, n_cell_hits, n_cell_pixels (u64)
 };
 
 struct dgs_ctx_s {
@@ -78,7 +78,7 @@ struct dgs_ctx_s {
                                   // [11..12] compositor work-queue head and item count,
                                   // [13] look-back frame counter
     int* dev_err = nullptr;
-    unsigned long long* counters = nullptr;  // n_val, n_rendered, n_box, n_cell_hits
+    unsigned long long* counters = nullptr;  // n_val, n_rendered, n_box, n_cell_hits, n_cell_pixels
 
     // last frame
     int last_mode = -1, last_passes = 0;

@@ -129,9 +129,9 @@ struct CompositeArgs {
     uint32_t* queue;               // [2] scratch: work-queue head, item count
     bool save;                     // Duplex: also write the frame record's sv_* state (host-side choice)
 };
-// Work queue of the compositor (heaviest-first tile / half-tile items); must
-// precede launch_composite_*.  Tiles with at least split_len entries become
-// two half-tile items (split_len 0: every tile is split).
+// Work queue of the compositor (costliest-first tile / half-tile items);
+// must precede launch_composite_*.  Tiles with at least split_len entries
+// become two half-tile items.
 void launch_tile_order(hipStream_t st, const uint32_t* ranges, int tiles, uint32_t split_len, uint32_t* order,
                        uint32_t* queue);
 // Split lengths, measured: lists of cells (each entry K members) and lists

@@ -161,7 +161,7 @@ class Frame:
     def stats(self):
         s = capi.dgs_frame_stats(self.renderer.ctx, self.handle)
         return dict(num_keys=s.num_keys, n_val=s.n_val, n_rendered=s.n_rendered, n_box=s.n_box,
-                    n_cell_hits=s.n_cell_hits)
+                    n_cell_hits=s.n_cell_hits, n_cell_pixels=s.n_cell_pixels)
 
     def release(self):
         r, self.renderer = self.renderer, None
@@ -321,7 +321,7 @@ class Renderer:
         s = capi.dgs_get_stats(self.ctx)
         return dict(num_keys=s.num_keys, key_capacity=s.key_capacity, n_val=s.n_val, n_rendered=s.n_rendered,
                     n_box=s.n_box, n_cell_hits=s.n_cell_hits, device_error=s.device_error,
-                    sort_passes=s.sort_passes)
+                    sort_passes=s.sort_passes, n_cell_pixels=s.n_cell_pixels)
 
     def read_lists(self, tiles):
         n = self.stats()["num_keys"]

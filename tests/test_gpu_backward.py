@@ -412,3 +412,4 @@ def test_backward_ragged_cells(R):
     s = scenes.make_ragged_scene(3, n_cells=300, sh_degree=1)
     cam = scenes.tiny_camera(64, 64)
     check(run_case(R, s, cam, np.ones((64, 64)), seed=10))
+

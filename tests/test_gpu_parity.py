@@ -505,9 +505,13 @@ def test_one_stream_and_two_stream_frames_are_identical(R, c1, mode):
 
 
 def test_stats_counters_match_oracle(R):
+    """N^val and N^rendered (Sec. VII termination ratio) equal the oracle's
+    sums; (pixel, cell) pairs reached equal the listed pairs without
+    termination and lie between the contributing entries and that with it."""
     s = scenes.make_tiny_scene(0)
     cam = scenes.tiny_camera()
-    R.render(upload(s), cam, stats=True)
+    ds = upload(s)
+    R.render(ds, cam, stats=True)
     st = R.stats()
     ref = oracle.render(s, cam)
     exact = (ref["status"] == 0).all()
@@ -516,6 +520,12 @@ def test_stats_counters_match_oracle(R):
         assert st["n_rendered"] == int(ref["nrend"].sum())
     else:
         assert abs(st["n_val"] - int(ref["nval"].sum())) <= 8 * (ref["status"] != 0).sum()
+    cd = oracle.cells_discrete(s, cam)
+    _, _, ranges = oracle.build_lists(cd["visible"], cd["depth_bits"], cd["rect"], 256, 256)
+    listed = int(((ranges[:, 1] - ranges[:, 0]) * 256).sum())  # 16x16 tiles, all inside the image
+    R.render(ds, cam, stats=True, no_et=True)
+    assert R.stats()["n_cell_pixels"] == listed
+    assert int(ref["last"].sum()) <= st["n_cell_pixels"] < listed
 
 
 # ------------------------------------------------------------------ ragged cells

@@ -112,3 +112,34 @@ def test_memory_budget_on_the_device(dev):
     reqs = [(i % 2, cameras(i % 2, 1280, 720)[i % 6], {}) for i in range(8)]
     results, st = serve_and_compare(dev, dict(num_slots=4, use_graphs=True, memory_budget=48 << 20), reqs)
     assert st["peak_workspace_bytes"] <= 48 << 20
+
+
+def test_full_size_scenes_and_4k_in_the_mix(dev):
+    """The serving benchmark's full-size scenes -- the 1M-Gaussian clustered
+    scene and the 6M-Gaussian large scene -- with 1920x1080 and 3840x2160
+    requests among small ones, several frames in flight with graph replay:
+    every result is bit-identical to the same request rendered alone."""
+    from paper_2508_03180_amd.renderer import DeviceScene
+    from paper_2508_03180_amd.serving import Server
+    _, r = dev
+    big = [DeviceScene.from_numpy(scenes.make_mid_scene(41), "cuda:0"),
+           DeviceScene.from_numpy(scenes.make_large_scene(43), "cuda:0")]
+    rng = np.random.default_rng(9)
+    reqs = []
+    for i in range(14):
+        s = i % 2
+        w, h = [(640, 480), (1920, 1080), (3840, 2160)][int(rng.integers(3))] if i > 1 else (3840, 2160)
+        cams = scenes.orbit_cameras(12, w, h, step_deg=30.0) if s == 0 else \
+            scenes.aerial_orbit_cameras(12, w, h, step_deg=30.0)
+        reqs.append((s, cams[int(rng.integers(12))], OPTS[int(rng.integers(2))]))
+    with Server(0, num_slots=4, use_graphs=True) as srv:
+        ids = [srv.add_scene(d) for d in big]
+        rids = [srv.submit(ids[s], cam, **o) for (s, cam, o) in reqs]
+        results = [srv.wait(i, timeout=120) for i in rids]
+        st = srv.stats()
+    torch.cuda.synchronize()
+    assert st["completed"] == len(reqs) and max(i["slot"] for i, _ in results) >= 1
+    assert any(cam["width"] == 3840 for _, cam, _ in reqs)
+    for (info, img), (s, cam, o) in zip(results, reqs):
+        assert info["state"] == capi.DGS_REQ_DONE, (info, s, cam["width"], o)
+        assert torch.equal(img, r.render(big[s], cam, **o)["color"]), (s, cam["width"], o)
