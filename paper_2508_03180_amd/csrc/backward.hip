@@ -185,7 +185,7 @@ __device__ inline void duplex_tile_bwd(const BwdArgs& a, int tile, int s0, int l
         const int lo_c = hi - nch;
         CellChunk ch;
         load_cells<RAGGED>(a.vals, a.offs, a.cell_v, K, start + (uint32_t)lo_c, start + (uint32_t)hi, nch, lane, ch);
-        uint32_t sm = 0;
+        uint32_t sm = 0, rcols = 0;  // strips and tile columns this lane's record touches
         if (ch.g >= 0) {
             const float4* p = reinterpret_cast<const float4*>(a.recs + ch.g);
             float4* d = reinterpret_cast<float4*>(lds + lane);
@@ -195,6 +195,8 @@ __device__ inline void duplex_tile_bwd(const BwdArgs& a, int tile, int s0, int l
             const uint32_t wxy = __float_as_uint(r2.w);
             const int x1 = x0 + (int)(wxy & 0xffffu), y1 = y0 + (int)(wxy >> 16);
             if (x0 <= tx0 + 15 && x1 >= tx0) {
+                const int lo = max(x0, tx0) - tx0, hi = min(x1, tx0 + 15) - tx0;
+                rcols = ((2u << (hi - lo)) - 1u) << lo;
 #pragma unroll
                 for (int j = 0; j < NS; j++) {
                     const int sy0 = ty0 + 4 * (s0 + j);
@@ -225,6 +227,24 @@ __device__ inline void duplex_tile_bwd(const BwdArgs& a, int tile, int s0, int l
                 anyact = anyact || act[j];
             }
             if (!mm || !__any(anyact)) continue;  // no member touches the owned rows / no pixel reaches the cell
+            {
+                // drop the members whose box misses every pixel that reaches
+                // this cell: they change nothing there (the other pixels have
+                // threshold +inf), so the cell's replay is the same without them
+                uint32_t live = 0;
+#pragma unroll
+                for (int j = 0; j < NS; j++) {
+                    const uint64_t am = __ballot(act[j]);
+                    if (am != ~0ull) {
+                        uint32_t ac = (uint32_t)(am | (am >> 32));
+                        ac = (ac | (ac >> 16)) & 0xffffu;  // columns (lane & 15) with a pixel reaching the cell
+                        mj[j] = (uint32_t)(__ballot(((sm >> j) & 1u) && (rcols & ac)) >> base) & cm;
+                    }
+                    live |= mj[j];
+                }
+                mm = live;
+                if (!mm) continue;
+            }
             const uint32_t cell = (uint32_t)lane_value((int)ch.id, c);
             const int gfirst = lane_value(ch.gfirst, c);  // Gaussian of member 0
             // pass 1: cell totals at each pixel (same decisions as the forward)

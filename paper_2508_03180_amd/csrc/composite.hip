@@ -82,14 +82,20 @@ __device__ inline void load_gauss_chunk(const CompositeArgs& a, uint32_t pos, ui
 // s0 + j (rows 4(s0 + j)..4(s0 + j) + 3 of the tile), j < NS; s0 = 0 for a
 // whole tile (NS = 4), 2h for half h (NS = 2).  s0 is wavefront-uniform, so
 // the ballots stay in scalar registers.
+// Also returns, per lane, its record's strip bits (sm) and the tile columns
+// its box covers (cols, bit x for column tx0 + x; 0 when it misses the tile).
 template <int NS>
-__device__ inline void strip_ballots(const Chunk& q, int tx0, int ty0, int s0, uint64_t* B) {
-    uint32_t sm = 0;
+__device__ inline void strip_ballots(const Chunk& q, int tx0, int ty0, int s0, uint64_t* B, uint32_t& sm,
+                                     uint32_t& cols) {
+    sm = 0;
+    cols = 0;
     if (q.ok) {
         const int x0 = __float_as_int(q.r2.y), y0 = __float_as_int(q.r2.z);
         const uint32_t wxy = __float_as_uint(q.r2.w);
         const int x1 = x0 + (int)(wxy & 0xffffu), y1 = y0 + (int)(wxy >> 16);
         if (x0 <= tx0 + 15 && x1 >= tx0) {
+            const int lo = max(x0, tx0) - tx0, hi = min(x1, tx0 + 15) - tx0;
+            cols = ((2u << (hi - lo)) - 1u) << lo;
 #pragma unroll
             for (int j = 0; j < NS; j++) {
                 const int r0 = ty0 + 4 * (s0 + j);
@@ -99,6 +105,14 @@ __device__ inline void strip_ballots(const Chunk& q, int tx0, int ty0, int s0, u
     }
 #pragma unroll
     for (int j = 0; j < NS; j++) B[j] = __ballot((sm >> j) & 1u);
+}
+
+// Columns (bit x: tile column x) holding an active pixel in a strip, from
+// the ballot of the strip's active lanes (lane l: column l & 15).
+__device__ inline uint32_t active_columns(uint64_t m) {
+    m |= m >> 32;
+    m |= m >> 16;
+    return (uint32_t)m & 0xffffu;
 }
 
 __device__ inline void store_chunk(GRec* lds, int lane, const Chunk& q) {
@@ -252,7 +266,8 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
         }
         store_chunk(lds, lane, q);
         uint64_t B[NS];
-        strip_ballots<NS>(q, tx0, ty0, s0, B);
+        uint32_t rsm, rcols;  // this lane's record: strips and tile columns its box touches
+        strip_ballots<NS>(q, tx0, ty0, s0, B, rsm, rcols);
         const float cv = q.v;
         const uint32_t next = pos + nch;
         if (next < end) load_cell_chunk<RAGGED>(a, next, end, lane, q);
@@ -292,6 +307,25 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
                 if (!STATS && !__any(anyact)) {
                     alive = false;
                     break;
+                }
+                // once pixels have terminated, a member whose box misses every
+                // pixel still blending cannot change anything: drop it (a
+                // finished pixel has threshold +inf, so it is never hit)
+                if (!STATS) {
+                    uint32_t live = 0;
+#pragma unroll
+                    for (int j = 0; j < NS; j++) {
+                        const uint64_t am = __ballot(act[j]);
+                        if (am == __ballot(inb[j])) {  // every pixel of strip j still blends
+                            live |= mj[j];
+                            continue;
+                        }
+                        const uint32_t ac = active_columns(am);
+                        mj[j] = (uint32_t)(__ballot(((rsm >> j) & 1u) && (rcols & ac)) >> base) & cm;
+                        live |= mj[j];
+                    }
+                    any = live;
+                    if (!any) continue;  // no member reaches a blending pixel: T, last unchanged
                 }
             }
             // the cell's weight is fixed before its members: w alpha c and
@@ -414,7 +448,8 @@ __device__ inline void alpha_tile(const CompositeArgs& a, const FrameView& f, in
         const int n = q.nch;
         store_chunk(lds, lane, q);
         uint64_t B[NS], any = 0;
-        strip_ballots<NS>(q, tx0, ty0, s0, B);
+        uint32_t rsm, rcols;
+        strip_ballots<NS>(q, tx0, ty0, s0, B, rsm, rcols);
 #pragma unroll
         for (int j = 0; j < NS; j++) any |= B[j];
         const uint32_t next = pos + n;

@@ -138,8 +138,9 @@ def test_full_size_scenes_and_4k_in_the_mix(dev):
         results = [srv.wait(i, timeout=120) for i in rids]
         st = srv.stats()
     torch.cuda.synchronize()
+    for (info, img), (s, cam, o) in zip(results, reqs):
+        assert info["state"] == capi.DGS_REQ_DONE, (info, st, s, cam["width"], o)
     assert st["completed"] == len(reqs) and max(i["slot"] for i, _ in results) >= 1
     assert any(cam["width"] == 3840 for _, cam, _ in reqs)
     for (info, img), (s, cam, o) in zip(results, reqs):
-        assert info["state"] == capi.DGS_REQ_DONE, (info, s, cam["width"], o)
         assert torch.equal(img, r.render(big[s], cam, **o)["color"]), (s, cam["width"], o)
