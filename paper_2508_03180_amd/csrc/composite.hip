@@ -456,16 +456,31 @@ __device__ inline void alpha_tile(const CompositeArgs& a, const FrameView& f, in
         if (next < end) load_gauss_chunk(a, next, end, lane, q);
         int since_check = 0;
         for (; any; any &= any - 1) {
-            const int m = __builtin_ctzll(any);
+            int m = __builtin_ctzll(any);
+            // every 8 Gaussians: stop when no pixel of the owned strips still
+            // blends, else keep only the records whose box meets a column
+            // that still holds a blending pixel in a strip the box covers
+            // (a record outside every such column and strip cannot hit a
+            // blending pixel, so dropping it changes no output)
             if (!STATS && ++since_check == 8) {
                 since_check = 0;
                 bool anyact = false;
+                uint64_t live = 0;
 #pragma unroll
-                for (int j = 0; j < NS; j++) anyact = anyact || (inb[j] && !(T[j] < eps));
+                for (int j = 0; j < NS; j++) {
+                    const bool actj = inb[j] && !(T[j] < eps);
+                    anyact = anyact || actj;
+                    // the column ballot runs on every lane, outside the &&
+                    const uint32_t ac = active_columns(__ballot(actj));
+                    live |= __ballot(((rsm >> j) & 1u) && (rcols & ac));
+                }
                 if (!__any(anyact)) {
                     alive = false;
                     break;
                 }
+                any &= live;
+                if (!any) break;
+                m = __builtin_ctzll(any);
             }
             const RecView e = read_rec(lb, m);
             const uint32_t rx = (uint32_t)(px - e.x0);
