@@ -30,10 +30,16 @@ hipError_t grow(T*& p, int64_t want, hipStream_t st) {
     return hipMalloc((void**)&p, sizeof(T) * (size_t)(want > 0 ? want : 1));
 }
 
-// Look-back status buffers start zeroed (epoch 0 is never used).
+// Look-back status buffers start zeroed (epoch 0 is never used).  The
+// zeroing is a fill kernel on the context's stream, ordered before the
+// frames that use the buffer: a null-stream memset is not ordered with a
+// non-blocking stream and could erase status words in the middle of a sort.
 hipError_t grow_zeroed(uint64_t*& p, int64_t want, hipStream_t st) {
     hipError_t e = grow(p, want, st);
-    if (e == hipSuccess) e = hipMemset(p, 0, sizeof(uint64_t) * (size_t)(want > 0 ? want : 1));
+    if (e == hipSuccess) {
+        launch_fill_u32(st, reinterpret_cast<uint32_t*>(p), 0u, 2 * (size_t)(want > 0 ? want : 1));
+        e = hipGetLastError();
+    }
     return e;
 }
 
@@ -843,8 +849,9 @@ dgs_status dgs_sync(dgs_ctx c) {
     if (hipMemcpy(&e, c->dev_err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
         return fail(c, DGS_ERR_DEVICE, "error flag readback failed");
     if (e) {
-        hipMemset(c->dev_err, 0, sizeof(int));
-        if (e & (1 << kErrTimeout)) return fail(c, DGS_ERR_TIMEOUT, "device look-back wait timed out");
+        // cleared in stream order, before the next frame can set a flag
+        launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(c->dev_err), 0u, 1);
+        if (e & (1 << kErrTimeout)) return fail(c, DGS_ERR_TIMEOUT, timeout_message(e));
         if (e & (1 << kErrInvalid))
             return fail(c, DGS_ERR_INVALID_ARG, "malformed cell_offsets (those cells were culled)");
         if (e & (1 << kErrCapacity)) return fail(c, DGS_ERR_CAPACITY, "key capacity exceeded; reserve more keys");

@@ -17,10 +17,13 @@ constexpr int kModeDuplex = 0;
 constexpr int kModeAlpha = 1;
 constexpr int kModeLcwsr = 2;
 
-// Device-side error codes (mirror dgs_status values).
+// Device-side error flags: bit n of the error word set for dgs_status n.
+// A timed-out wait also sets a bit naming the kernel that gave up.
 constexpr int kErrInvalid = 1;  // malformed cell_offsets
 constexpr int kErrCapacity = 3;
 constexpr int kErrTimeout = 6;
+constexpr int kErrWaitScan = 8;  // the exclusive scan's look-back
+constexpr int kErrWaitSort = 9;  // a radix sort pass's look-back
 
 // Per-frame camera constants, passed by value to kernels.
 struct CamK {

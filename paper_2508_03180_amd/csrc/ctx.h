@@ -9,6 +9,16 @@
 #include "duplexgs.h"
 #include "launch.h"
 
+// Text for a device error word with the timeout flag set: which bounded
+// look-back wait gave up.
+inline std::string timeout_message(int e) {
+    std::string m = "device look-back wait timed out in";
+    if (e & (1 << dgs::kErrWaitScan)) m += " the exclusive scan";
+    if ((e & (1 << dgs::kErrWaitScan)) && (e & (1 << dgs::kErrWaitSort))) m += " and";
+    if (e & (1 << dgs::kErrWaitSort)) m += " a radix sort pass";
+    return m;
+}
+
 // A saved Duplex frame (dgs_render with a non-NULL `saved`): the state its
 // backward replays, in buffers of its own so that later renders on the
 // context leave it intact.  Released frames stay with their context and are

@@ -120,7 +120,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_excl(const uint32_t* __re
                         continue;
                     }
                     if (++spins > kSpinLimit) {
-                        if (lane == 0) atomicOr(err, 1 << kErrTimeout);
+                        if (lane == 0) atomicOr(err, (1 << kErrTimeout) | (1 << kErrWaitScan));
                         break;
                     }
                     __builtin_amdgcn_s_sleep(1);

@@ -231,7 +231,7 @@ public:
             hipMemsetAsync(s.ctx->dev_err, 0, sizeof(int), s.stream);
             hipStreamSynchronize(s.stream);
             if (bits & (1u << kErrTimeout)) {
-                err = "device look-back wait timed out";
+                err = timeout_message((int)bits);
                 return DGS_ERR_TIMEOUT;
             }
             if (bits & (1u << kErrCapacity)) {

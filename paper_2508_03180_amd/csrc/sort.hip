@@ -201,7 +201,7 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const KeyT* __restric
             st_st64(my, tag | (2ull << 32) | tot);
         } else {
             st_st64(my, tag | (1ull << 32) | tot);
-            if (!look_back(status + d, 256, (int)part, epoch, &excl)) atomicOr(err, 1 << kErrTimeout);
+            if (!look_back(status + d, 256, (int)part, epoch, &excl)) atomicOr(err, (1 << kErrTimeout) | (1 << kErrWaitSort));
             st_st64(my, tag | (2ull << 32) | (excl + tot));
         }
         __syncthreads();

@@ -137,9 +137,10 @@ def test_full_size_scenes_and_4k_in_the_mix(dev):
         rids = [srv.submit(ids[s], cam, **o) for (s, cam, o) in reqs]
         results = [srv.wait(i, timeout=120) for i in rids]
         st = srv.stats()
+        err = srv.last_error()
     torch.cuda.synchronize()
     for (info, img), (s, cam, o) in zip(results, reqs):
-        assert info["state"] == capi.DGS_REQ_DONE, (info, st, s, cam["width"], o)
+        assert info["state"] == capi.DGS_REQ_DONE, (info, err, st, s, cam["width"], o)
     assert st["completed"] == len(reqs) and max(i["slot"] for i, _ in results) >= 1
     assert any(cam["width"] == 3840 for _, cam, _ in reqs)
     for (info, img), (s, cam, o) in zip(results, reqs):
