@@ -115,46 +115,15 @@ def parse():
     return p.parse_args()
 
 
-def _gauss_blur(x, g):
-    """Separable 11-tap Gaussian blur of [C, H, W] with zero padding (the
-    same values as a 2D convolution with the outer-product kernel and
-    padding 5), as shifted weighted sums along each axis."""
-    import torch.nn.functional as F
-    H, W = x.shape[-2], x.shape[-1]
-    xp = F.pad(x, (5, 5, 0, 0))
-    y = g[0] * xp[..., 0:W]
-    for i in range(1, 11):
-        y = y + g[i] * xp[..., i:i + W]
-    yp = F.pad(y, (0, 0, 5, 5))
-    z = g[0] * yp[..., 0:H, :]
-    for i in range(1, 11):
-        z = z + g[i] * yp[..., i:i + H, :]
-    return z
-
-
-def ssim_loss(C, T):
-    """1 - SSIM with an 11x11 Gaussian window (sigma 1.5), per channel."""
-    import torch
-    g = torch.exp(-0.5 * ((torch.arange(11, dtype=torch.float64) - 5) / 1.5) ** 2)
-    g = (g / g.sum()).tolist()
-    q = _gauss_blur(torch.cat([C, T, C * C, T * T, C * T], 0), g)
-    mu_x, mu_y, exx, eyy, exy = q.split(C.shape[0], 0)
-    sxx = exx - mu_x ** 2
-    syy = eyy - mu_y ** 2
-    sxy = exy - mu_x * mu_y
-    c1, c2 = 0.01 ** 2, 0.03 ** 2
-    ssim = ((2 * mu_x * mu_y + c1) * (2 * sxy + c2)) / ((mu_x ** 2 + mu_y ** 2 + c1) * (sxx + syy + c2))
-    return 1 - ssim.mean()
-
-
 def differentiation(r, scene, cam, steps):
     """Forward + loss + backward through the planar autograd Function (the
-    parameters are planar leaf tensors used in place), with the render, the
-    loss and the backward timed apart by HIP events on the torch stream."""
+    parameters are planar leaf tensors used in place) and the library's
+    l1 + SSIM loss, with the render, the loss and the backward timed apart
+    by HIP events on the torch stream."""
     import numpy as np
     import torch
 
-    from paper_2508_03180_amd.renderer import DeviceScene, DuplexRenderPlanar
+    from paper_2508_03180_amd.renderer import DeviceScene, DuplexRenderPlanar, L1SsimLoss
 
     rng = np.random.default_rng(3)
     pert = dict(scene)
@@ -175,7 +144,7 @@ def differentiation(r, scene, cam, steps):
         C, _ = DuplexRenderPlanar.apply(r, cam, {}, *[pl[k] for k in keys])
         if timed:
             ev[1].record()
-        loss = 0.8 * (C - target).abs().mean() + 0.2 * ssim_loss(C, target)
+        loss = L1SsimLoss.apply(r, C, target, 0.2)
         if timed:
             ev[2].record()
         loss.backward()
@@ -209,7 +178,8 @@ def differentiation(r, scene, cam, steps):
     bt = e0.elapsed_time(e1) / steps
     out.pop("frame").release()
     capi.check(capi.dgs_sync(r.ctx), r.ctx)
-    return {"loss": "0.8 L1 + 0.2 (1 - SSIM 11x11) vs perturbed-scene target", "width": 1920, "height": 1080,
+    return {"loss": "0.8 L1 + 0.2 (1 - SSIM 11x11), library kernels, vs perturbed-scene target",
+            "width": 1920, "height": 1080,
             "params": "planar leaf tensors (no layout copies)",
             "fwd_loss_bwd_ms": round(dt * 1e3, 3), "render_ms": round(float(parts[0]), 3),
             "loss_ms": round(float(parts[1]), 3), "loss_and_render_backward_ms": round(float(parts[2]), 3),

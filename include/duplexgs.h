@@ -347,6 +347,27 @@ dgs_status dgs_sort_pairs(dgs_ctx ctx, uint64_t* keys, uint32_t* values, int64_t
 dgs_status dgs_sort_pairs_noalloc(dgs_ctx ctx, uint64_t* keys, uint32_t* values, int64_t n, int32_t key_bits);
 
 /*
+ * Training loss (eq. `loss`, Sec. "Perceptual Loss"; lambda_1 = 0.2 in Sec.
+ * "Experimental Settings") without its perceptual term:
+ *     L = (1 - lambda) mean |image - target| + lambda (1 - mean SSIM),
+ * the means over every channel and pixel; SSIM per channel from an 11 x 11
+ * Gaussian window (sigma 1.5, weights summing to 1), the images zero
+ * outside their borders, c1 = 0.01^2, c2 = 0.03^2.
+ * image, target: device, planar [channels][height][width] binary32.
+ * loss: device, one float, written on the context's stream (no host
+ * synchronisation).  grad_image: device [channels][height][width], dL/dimage
+ * written whole (0 from the l1 term where image == target), or NULL for the
+ * loss alone.  The per-pixel gradient coefficients live in the context's
+ * workspace (3 floats per pixel, grown on demand).  The sum is taken in a
+ * fixed order, so repeated calls give identical results.
+ * Errors: DGS_ERR_INVALID_ARG for a NULL pointer, sizes outside 1..32767
+ * (channels 1..65535) or lambda outside [0, 1]; DGS_ERR_OOM when the
+ * workspace cannot grow.
+ */
+dgs_status dgs_loss_l1_ssim(dgs_ctx ctx, const float* image, const float* target, int32_t channels,
+                            int32_t height, int32_t width, float lambda, float* loss, float* grad_image);
+
+/*
  * Serving runtime.  A server renders requests (scene, camera, options,
  * output image) submitted from any host thread.  It keeps num_slots frames
  * in flight, each slot with its own context, workspace and HIP stream, and

@@ -127,6 +127,8 @@ _SIGS = {
     "dgs_read_gauss_rects": (C.c_int, [dgs_ctx, C.c_void_p]),
     "dgs_sort_pairs": (C.c_int, [dgs_ctx, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32]),
     "dgs_sort_pairs_noalloc": (C.c_int, [dgs_ctx, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32]),
+    "dgs_loss_l1_ssim": (C.c_int, [dgs_ctx, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_float,
+                                   C.c_void_p, C.c_void_p]),
     "dgs_set_timing": (C.c_int, [dgs_ctx, C.c_int32]),
     "dgs_get_timing": (C.c_int, [dgs_ctx, C.POINTER(C.c_float), C.c_int32, C.POINTER(C.c_int32)]),
     "dgs_server_default_config": (None, [C.POINTER(dgs_server_config)]),
@@ -275,6 +277,13 @@ def dgs_sort_pairs(ctx, keys_ptr, values_ptr, n, key_bits):
 
 
 DGS_SORT_NOALLOC_MAX_KEYS = 1 << 20
+
+
+def dgs_loss_l1_ssim(ctx, image_ptr, target_ptr, channels, height, width, lam, loss_ptr, grad_ptr):
+    """(1 - lam) l1 + lam (1 - SSIM) of two planar images and dL/dimage
+    (grad_ptr 0: the loss alone); all device pointers."""
+    return lib().dgs_loss_l1_ssim(ctx, C.c_void_p(image_ptr), C.c_void_p(target_ptr), int(channels), int(height),
+                                  int(width), float(lam), C.c_void_p(loss_ptr), C.c_void_p(grad_ptr or None))
 
 
 def dgs_sort_pairs_noalloc(ctx, keys_ptr, values_ptr, n, key_bits):

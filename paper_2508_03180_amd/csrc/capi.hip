@@ -451,6 +451,7 @@ dgs_status dgs_destroy(dgs_ctx c) {
     c->frames.clear();
     void* ptrs[] = {c->p_depth, c->p_ntiles, c->p_offsets, c->p_rect, c->cell_v, c->recs, c->grect,
                     c->keys0, c->keys1, c->vals0, c->vals1, c->ranges, c->tile_order, c->scan_status, c->sort_status, c->g2d, c->gv, c->dec,
+                    c->loss_coef, c->loss_part,
                     c->pk0, c->pk1, c->pv0, c->pv1, c->psort_status,
                     c->hist, c->misc, c->dev_err, c->counters, c->frame};
     for (void* p : ptrs)

@@ -82,6 +82,9 @@ struct dgs_ctx_s {
     float* g2d = nullptr;  // [M][kG2dRow] backward screen-space gradients
     float* gv = nullptr;   // [N] backward dL/dv
     int64_t cap_g2d = 0, cap_gv = 0;
+    float* loss_coef = nullptr;   // [3][C][H][W] per-pixel coefficients of the loss gradient
+    double* loss_part = nullptr;  // [tiles][2] per-tile sums of the loss
+    int64_t cap_loss_coef = 0, cap_loss_part = 0;
     uint32_t* hist = nullptr;     // [8][256]: [0..3] primitive depth bytes, [4..6] key tile bytes
     uint32_t* misc = nullptr;     // [0] key total, [1] scan ticket, [2..5] depth sort tickets,
                                   // [6..8] tile sort tickets, [9] spare, [10] sort count,

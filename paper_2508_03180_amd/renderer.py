@@ -346,6 +346,22 @@ class Renderer:
         self.stream.synchronize()
         return rect[:M]
 
+    def loss_l1_ssim(self, image, target, lam=0.2, grad=True):
+        """(1 - lam) mean |image - target| + lam (1 - mean SSIM) of two
+        contiguous float32 [C, H, W] device images, and dL/dimage when grad is
+        set, computed by the library on the renderer's stream.  Returns
+        (loss as a 0-dim tensor, gradient or None)."""
+        if image.dtype != torch.float32 or target.dtype != torch.float32:
+            raise ValueError("image and target must be float32")
+        if image.dim() != 3 or image.shape != target.shape or not image.is_contiguous() or not target.is_contiguous():
+            raise ValueError("image and target must be contiguous [C, H, W] tensors of one shape")
+        C_, H, W = image.shape
+        loss = torch.empty((), dtype=torch.float32, device=image.device)
+        g = torch.empty_like(image) if grad else None
+        capi.check(capi.dgs_loss_l1_ssim(self.ctx, image.data_ptr(), target.data_ptr(), C_, H, W, lam,
+                                         loss.data_ptr(), g.data_ptr() if g is not None else 0), self.ctx)
+        return loss, g
+
     def sort_pairs(self, keys, vals, key_bits):
         """In-place stable sort of int64 keys (as u64) and int32 values."""
         assert keys.dtype == torch.int64 and vals.dtype == torch.int32 and keys.is_contiguous()
@@ -421,3 +437,23 @@ class DuplexRenderPlanar(torch.autograd.Function):
         g = ctx.renderer.render_backward(ctx.ds, ctx.frame, g_color, g_D)
         return (None, None, None, g["cell_pos"], None, None, g["cell_v_sh"], g["means"], g["scales"], g["rots"],
                 g["opacities"], g["sh"])
+
+
+class L1SsimLoss(torch.autograd.Function):
+    """The training loss (1 - lam) l1 + lam (1 - SSIM) of a rendered image
+    against a fixed target, by the library: the forward computes the loss and
+    dL/dimage in one call, the backward scales that gradient by the incoming
+    one.  Inputs: renderer, image [C, H, W], target [C, H, W] (no gradient),
+    lam.  Returns a 0-dim tensor."""
+
+    @staticmethod
+    def forward(ctx, renderer, image, target, lam=0.2):
+        loss, g = renderer.loss_l1_ssim(image.detach(), target.detach(), lam, grad=image.requires_grad)
+        ctx.g = g
+        return loss
+
+    @staticmethod
+    def backward(ctx, g_loss):
+        g = ctx.g
+        ctx.g = None
+        return None, (g * g_loss if g is not None else None), None, None
