@@ -594,10 +594,13 @@ def main():
     Lp = cp * ds.K
     lane_ops = 16 * E + 4 * Lp + 8 * cp
     t_s = comp_ms * 1e-3
+    traffic = composite_traffic()  # measured HBM bytes per launch (None once the compositor changed)
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
             "peak_issuable_unpacked": round(PEAK_FP32_UNPACKED_TFLOPS, 2),
-            "frac_of_issuable": round(achieved / PEAK_FP32_UNPACKED_TFLOPS, 4), "traffic": composite_traffic(),
+            "frac_of_issuable": round(achieved / PEAK_FP32_UNPACKED_TFLOPS, 4), "traffic": traffic,
+            "traffic_gbs": round(traffic / t_s / 1e9, 1) if traffic else None,
+            "traffic_hbm_frac": round(traffic / t_s / (PEAK_HBM_GBS * 1e9), 4) if traffic else None,
             "kernel": "k_composite<0, false, false, false>", "kernel_ms": round(comp_ms, 4),
             "algorithmic_gflop_per_launch": round(flops / 1e9, 4),
             "work_terms": {"E_inbox_member_pixels": int(E), "L_listed_member_pixels": int(Lp),
