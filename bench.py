@@ -97,6 +97,8 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=120)
     p.add_argument("--warmup", type=int, default=10)
+    p.add_argument("--frames-in-flight", type=int, default=3,
+                   help="renderers (contexts on their own streams) taking the timed frames in turn")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-alpha", action="store_true")
     p.add_argument("--cpu-frames", type=int, default=3)
@@ -515,6 +517,47 @@ def main():
         capi.check(capi.dgs_sync(r.ctx), r.ctx)
         return dt
 
+    # frames in flight: F renderers, each a context on its own stream with its
+    # own workspace and output image, take the orbit frames in turn, so one
+    # frame's sort can run beside another's compositor.  Every frame is still
+    # rendered whole; in-frame overlap is off (one stream per context).
+    F = max(1, a.frames_in_flight)
+    flight = []
+    for _ in range(F):
+        rr = Renderer(0, stream=torch.cuda.Stream(), overlap=(F == 1))
+        oo = rr.alloc_image(cams[0])
+        flight.append((rr, oo, capi.dgs_image(oo["color"].data_ptr(), oo["D"].data_ptr(), oo["T"].data_ptr(),
+                                              oo["last"].data_ptr())))
+
+    def timed_in_flight(mode, steps, warmup):
+        op = opts_struct(mode=mode)
+        for rr, oo, _ in flight:  # size every workspace for the whole orbit
+            for c in cams:
+                rr.render(ds, c, out=oo, mode=mode)
+        torch.cuda.synchronize()
+
+        def go(first, n):
+            for i in range(first, first + n):
+                rr, _, ii = flight[i % F]
+                st = L.dgs_render(rr.ctx, sc, cam_structs[i % NF], op, ii, None)
+                if st:
+                    capi.check(st, rr.ctx)
+
+        go(-warmup, warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        go(0, steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        for j, (rr, oo, _) in enumerate(flight):
+            capi.check(capi.dgs_sync(rr.ctx), rr.ctx)
+            done = [i for i in range(steps) if i % F == j]
+            if done:  # the renderer's last frame is the frame rendered alone
+                ref = r.render(ds, cams[done[-1] % NF], out=out, mode=mode)["color"]
+                torch.cuda.synchronize()
+                assert torch.equal(oo["color"], ref), ("frames in flight changed a frame", mode, j)
+        return dt
+
     def frame_times(mode, orbits=2):
         """Per-frame GPU time (HIP events between consecutive frames on the
         context stream) over the orbit: median, p99 and max in ms."""
@@ -555,9 +598,10 @@ def main():
         return {k: v / len(idx) for k, v in tot.items()}
 
     keys_dup = size_all("duplex")
-    dt = timed("duplex", a.steps, a.warmup)
+    dt1 = timed("duplex", a.steps, a.warmup)
+    dt = timed_in_flight("duplex", a.steps, a.warmup)
     fps = a.steps / dt
-    progress(f"duplex: {fps:.1f} frames/s")
+    progress(f"duplex: {fps:.1f} frames/s with {F} frames in flight, {a.steps / dt1:.1f} with one")
     st_dup = stage_times("duplex")
     fr_dup = frame_times("duplex")
     cnt = counters("duplex", range(0, NF, 6))
@@ -565,14 +609,17 @@ def main():
     alpha = None
     if not a.no_alpha:
         keys_alpha = size_all("alpha")
-        dta = timed("alpha", a.steps, a.warmup)
+        dta1 = timed("alpha", a.steps, a.warmup)
+        dta = timed_in_flight("alpha", a.steps, a.warmup)
         st_alpha = stage_times("alpha")
         fr_alpha = frame_times("alpha")
         cnt_a = counters("alpha", range(0, NF, 6))
         progress(f"alpha-blend baseline: {a.steps / dta:.1f} frames/s")
         comp_a = st_alpha["composite"]
         flops_a = FLOP_BOX * cnt_a["n_box"] + FLOP_ALPHA_HIT * cnt_a["n_rendered"]
-        alpha = {"fps": round(a.steps / dta, 2), "ms_per_step": round(1e3 * dta / a.steps, 4), "frame_ms": fr_alpha,
+        alpha = {"fps": round(a.steps / dta, 2), "ms_per_step": round(1e3 * dta / a.steps, 4),
+                 "one_in_flight": {"fps": round(a.steps / dta1, 2), "ms_per_step": round(1e3 * dta1 / a.steps, 4)},
+                 "frame_ms": fr_alpha,
                  "stages_ms": {k: round(v, 4) for k, v in st_alpha.items()},
                  "keys_mean": float(np.mean(keys_alpha)),
                  "composite_tflops": round(flops_a / (comp_a * 1e-3) / 1e12, 3),
@@ -642,9 +689,13 @@ def main():
                    "width": W, "height": H, "frames": NF,
                    "timed_frames": f"orbit frames i mod {NF} for i = 0..{a.steps - 1} "
                                    f"({'the whole orbit' if a.steps >= NF else f'{a.steps} of {NF} frames'}), "
-                                   f"after {a.warmup} untimed warm-up frames"},
+                                   f"after {a.warmup} untimed warm-up frames",
+                   "frames_in_flight": F},
         "alpha_baseline": alpha,
         "speedup_vs_alpha": None if alpha is None else round(fps / alpha["fps"], 3),
+        "one_in_flight": {"fps": round(a.steps / dt1, 2), "ms_per_step": round(1e3 * dt1 / a.steps, 4),
+                          "speedup_vs_alpha": None if alpha is None
+                          else round(dta1 / dt1, 3)},
         "frame_ms": fr_dup,
         "stages_ms": {k: round(v, 4) for k, v in st_dup.items()},
         "keys_mean": float(np.mean(keys_dup)),
@@ -666,6 +717,8 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+    for rr, _, _ in flight:
+        rr.close()
     r.close()
 
 

@@ -179,6 +179,16 @@ dgs_status dgs_destroy(dgs_ctx ctx);
 /* Changes the stream later calls enqueue on. */
 dgs_status dgs_set_stream(dgs_ctx ctx, void* hip_stream);
 
+/* Overlap inside a frame (on by default): a Duplex or LC-WSR frame projects
+ * its members (Sec. IV-A, the Gaussians each cell emits) on a second stream
+ * of the context while the cells are sorted (Sec. IV-B), and joins it
+ * before compositing.  The second stream is created by the first frame that
+ * uses it (never inside a graph capture: such a frame runs on one stream).
+ * Callers that overlap whole frames themselves -- several contexts on
+ * several streams -- can turn it off (enable = 0) so that each context
+ * holds one stream.  Results are identical either way. */
+dgs_status dgs_set_overlap(dgs_ctx ctx, int32_t enable);
+
 /* Sizes the workspace for up to max_keys (tile, primitive) keys,
  * max_prims cells or Gaussians and max_tiles screen tiles.  Allocates (and
  * synchronises) only when growing.  Render grows prims/tiles by itself;

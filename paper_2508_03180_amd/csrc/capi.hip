@@ -419,14 +419,9 @@ dgs_status dgs_create(int device, void* hip_stream, dgs_ctx* out) {
         dgs_destroy(c);
         return DGS_ERR_OOM;
     }
-    // the frame's second stream, created here so that no frame (a captured
-    // one included) has to create it
-    if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
-        dgs_destroy(c);
-        return DGS_ERR_DEVICE;
-    }
+    // the frame's second stream is created by the first frame that uses it
+    // (ensure_aux), so contexts that never overlap inside a frame hold one
+    // stream only
     hipMemsetAsync(c->misc, 0, 16 * sizeof(uint32_t), c->stream);
     hipMemsetAsync(c->dev_err, 0, sizeof(int), c->stream);
     hipMemsetAsync(c->counters, 0, 5 * sizeof(unsigned long long), c->stream);
@@ -457,6 +452,12 @@ dgs_status dgs_destroy(dgs_ctx c) {
     for (void* p : ptrs)
         if (p) hipFree(p);
     delete c;
+    return DGS_OK;
+}
+
+dgs_status dgs_set_overlap(dgs_ctx c, int32_t enable) {
+    if (!c) return DGS_ERR_INVALID_ARG;
+    c->two_streams = enable != 0;
     return DGS_OK;
 }
 
@@ -567,6 +568,29 @@ dgs_status dgs_read_decoded(dgs_ctx c, float* means, float* scales, float* rots,
 
 }  // extern "C"
 
+// The context's second stream and its fork/join events, created on first
+// use.  Not while the context's stream is being captured into a graph (a
+// stream cannot be created inside a capture): such a frame runs on one
+// stream.  False when the second stream is not available.
+static bool ensure_aux(dgs_ctx c) {
+    if (c->aux) return true;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(c->stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return false;
+    if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess) {
+        c->aux = nullptr;
+        return false;
+    }
+    if (hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+        if (c->ev_fork) hipEventDestroy(c->ev_fork);
+        hipStreamDestroy(c->aux);
+        c->aux = nullptr;
+        c->ev_fork = nullptr;
+        return false;
+    }
+    return true;
+}
+
 // The frame pipeline.  With write_frame the frame's camera and options are
 // written to the context's device FrameK by the first kernel; without it the
 // caller has put them there (a captured graph replayed for a new camera).
@@ -592,7 +616,7 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     if ((st = ensure(c, P, M, want_keys, tiles)) != DGS_OK) return st;
     const uint32_t cap = (uint32_t)c->cap_keys;
     hipStream_t q = c->stream;
-    const bool overlap = cells && !c->timing && c->two_streams;
+    const bool overlap = cells && !c->timing && c->two_streams && ensure_aux(c);
     // buffers the backward replays: a saved frame's own, else the context's
     float* cell_v = save ? save->cell_v : c->cell_v;
     GRec* recs = save ? save->recs : c->recs;

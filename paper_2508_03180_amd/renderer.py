@@ -177,12 +177,16 @@ class Frame:
 
 
 class Renderer:
-    """One library context bound to a device and a stream."""
+    """One library context bound to a device and a stream.  overlap: run a
+    Duplex frame's member projection on a second stream beside the cell sort
+    (turn it off when several renderers already overlap whole frames)."""
 
-    def __init__(self, device=0, stream=None):
+    def __init__(self, device=0, stream=None, overlap=True):
         self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.ctx = capi.dgs_create(self.device.index or 0, self.stream.cuda_stream)
+        if not overlap:
+            capi.dgs_set_overlap(self.ctx, False)
 
     def close(self):
         if self.ctx:
