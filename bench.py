@@ -629,6 +629,10 @@ def main():
                                         / ((st_alpha["depth_sort"] + st_alpha["tile_sort"]) * 1e-3)
                                         / (PEAK_HBM_GBS * 1e9), 4)}
 
+    for rr, _, _ in flight:  # the later legs run on their own streams
+        rr.close()
+    flight.clear()
+
     # roofline of the dominant kernel, the Duplex compositor (plain FP32 ALU)
     comp_ms = st_dup["composite"]
     flops = (FLOP_BOX * cnt["n_box"] + FLOP_DUPLEX_MEMBER * cnt["n_rendered"]
