@@ -458,6 +458,5 @@ class L1SsimLoss(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g_loss):
-        g = ctx.g
-        ctx.g = None
+        g = ctx.g  # kept with the graph: a retained graph may be walked again
         return None, (g * g_loss if g is not None else None), None, None

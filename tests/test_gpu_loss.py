@@ -108,10 +108,13 @@ def test_autograd_function(r):
     x = torch.tensor(rng.random((3, 50, 80)), dtype=torch.float32, device="cuda", requires_grad=True)
     y = torch.tensor(rng.random((3, 50, 80)), dtype=torch.float32, device="cuda")
     loss = 3.0 * L1SsimLoss.apply(r, x, y, 0.2)
-    loss.backward()
+    loss.backward(retain_graph=True)
     _, g = r.loss_l1_ssim(x.detach(), y, 0.2)
     torch.cuda.synchronize()
     assert torch.allclose(x.grad, 3.0 * g, rtol=1e-6, atol=0)
+    loss.backward()  # a retained graph walked again adds the same gradient
+    torch.cuda.synchronize()
+    assert torch.allclose(x.grad, 6.0 * g, rtol=1e-6, atol=0)
 
 
 def test_invalid_arguments(r):
