@@ -189,6 +189,23 @@ dgs_status dgs_set_stream(dgs_ctx ctx, void* hip_stream);
  * holds one stream.  Results are identical either way. */
 dgs_status dgs_set_overlap(dgs_ctx ctx, int32_t enable);
 
+/* How a frame puts each tile's list in depth order (Sec. IV-B: the keys are
+ * sorted by tile, then by depth; ties by primitive id).  Both ways give the
+ * same lists bit for bit:
+ *   DGS_LIST_ORDER_GLOBAL: the primitives (cells, or Gaussians in
+ *     DGS_MODE_ALPHA) are radix-sorted by depth first and their keys emitted
+ *     in that order, then stably sorted on the tile bits;
+ *   DGS_LIST_ORDER_PER_TILE: the keys are emitted in primitive-id order,
+ *     stably sorted on the tile bits, and each tile's run is then sorted by
+ *     (depth, id) on its own (fast when the lists are short);
+ *   DGS_LIST_ORDER_AUTO (default): per tile for per-cell lists (Duplex,
+ *     LC-WSR) when the key capacity is at most 256 keys per screen tile,
+ *     else global (always for DGS_MODE_ALPHA).
+ * The setting holds for the context's later frames; it changes no result.
+ * Other values: DGS_ERR_INVALID_ARG. */
+enum { DGS_LIST_ORDER_AUTO = 0, DGS_LIST_ORDER_PER_TILE = 1, DGS_LIST_ORDER_GLOBAL = 2 };
+dgs_status dgs_set_list_order(dgs_ctx ctx, int32_t order);
+
 /* Sizes the workspace for up to max_keys (tile, primitive) keys,
  * max_prims cells or Gaussians and max_tiles screen tiles.  Allocates (and
  * synchronises) only when growing.  Render grows prims/tiles by itself;

@@ -127,6 +127,7 @@ _SIGS = {
     "dgs_read_gauss_rects": (C.c_int, [dgs_ctx, C.c_void_p]),
     "dgs_sort_pairs": (C.c_int, [dgs_ctx, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32]),
     "dgs_sort_pairs_noalloc": (C.c_int, [dgs_ctx, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32]),
+    "dgs_set_list_order": (C.c_int, [dgs_ctx, C.c_int32]),
     "dgs_set_overlap": (C.c_int, [dgs_ctx, C.c_int32]),
     "dgs_loss_l1_ssim": (C.c_int, [dgs_ctx, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_float,
                                    C.c_void_p, C.c_void_p]),
@@ -290,6 +291,14 @@ def dgs_loss_l1_ssim(ctx, image_ptr, target_ptr, channels, height, width, lam, l
 def dgs_sort_pairs_noalloc(ctx, keys_ptr, values_ptr, n, key_bits):
     """Returns the status (no raise): callers check DGS_ERR_INVALID_ARG for n above the maximum."""
     return lib().dgs_sort_pairs_noalloc(ctx, C.c_void_p(keys_ptr), C.c_void_p(values_ptr), int(n), int(key_bits))
+
+
+DGS_LIST_ORDER_AUTO, DGS_LIST_ORDER_PER_TILE, DGS_LIST_ORDER_GLOBAL = 0, 1, 2
+
+
+def dgs_set_list_order(ctx, order):
+    """Returns the status (no raise): invalid values give DGS_ERR_INVALID_ARG."""
+    return lib().dgs_set_list_order(ctx, int(order))
 
 
 def dgs_set_overlap(ctx, enable):

@@ -455,6 +455,14 @@ dgs_status dgs_destroy(dgs_ctx c) {
     return DGS_OK;
 }
 
+dgs_status dgs_set_list_order(dgs_ctx c, int32_t order) {
+    if (!c) return DGS_ERR_INVALID_ARG;
+    if (order != DGS_LIST_ORDER_AUTO && order != DGS_LIST_ORDER_PER_TILE && order != DGS_LIST_ORDER_GLOBAL)
+        return fail(c, DGS_ERR_INVALID_ARG, "list order must be DGS_LIST_ORDER_AUTO, _PER_TILE or _GLOBAL");
+    c->list_order = order;
+    return DGS_OK;
+}
+
 dgs_status dgs_set_overlap(dgs_ctx c, int32_t enable) {
     if (!c) return DGS_ERR_INVALID_ARG;
     c->two_streams = enable != 0;
@@ -568,6 +576,21 @@ dgs_status dgs_read_decoded(dgs_ctx c, float* means, float* scales, float* rots,
 
 }  // extern "C"
 
+// Per-cell tile lists (Duplex, LC-WSR) are put in depth order per tile
+// (launch_tile_depth_sort) when the key buffer holds at most this many keys
+// per tile on average: cells are few and their lists short, so sorting the
+// runs costs less than the depth sort of the cells.  Per-Gaussian lists are
+// several times longer per tile, with many runs past one wavefront's 256
+// entries: there the depth sort of the primitives, whose cost does not grow
+// with the lists, is cheaper.
+constexpr int64_t kPerTileOrderKeysPerTile = 256;
+
+static bool per_tile_order(dgs_ctx c, int64_t tiles, bool cells) {
+    if (c->list_order == DGS_LIST_ORDER_PER_TILE) return true;
+    if (c->list_order == DGS_LIST_ORDER_GLOBAL) return false;
+    return cells && c->cap_keys <= kPerTileOrderKeysPerTile * tiles;
+}
+
 // The context's second stream and its fork/join events, created on first
 // use.  Not while the context's stream is being captured into a graph (a
 // stream cannot be created inside a capture): such a frame runs on one
@@ -673,12 +696,18 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     }
     sm.mark(2);
     const uint64_t* prect = cells ? c->p_rect : c->grect;
-    // depth order of the primitives (ties by id), then key offsets over that order
-    launch_prim_keys(q, P, c->p_ntiles, c->p_depth, c->pk0, c->pv0, c->hist);
-    const SortScratch ps{c->hist, c->psort_status, c->misc + 2};
-    const bool pin1 = launch_radix_sort32(q, c->pk0, c->pv0, c->pk1, c->pv1, (uint32_t)P, ps, c->misc + 13, 1,
-                                          c->dev_err);
-    const uint32_t* order = pin1 ? c->pv1 : c->pv0;
+    // the lists' depth order: a depth sort of the primitives (ties by id)
+    // before the key emission, or, when the tile lists are short, a sort of
+    // each tile's run after the tile sort (the same order)
+    const bool per_tile = per_tile_order(c, tiles, cells);
+    const uint32_t* order = nullptr;  // null: keys emitted in primitive-id order
+    if (!per_tile) {
+        launch_prim_keys(q, P, c->p_ntiles, c->p_depth, c->pk0, c->pv0, c->hist);
+        const SortScratch ps{c->hist, c->psort_status, c->misc + 2};
+        const bool pin1 = launch_radix_sort32(q, c->pk0, c->pv0, c->pk1, c->pv1, (uint32_t)P, ps, c->misc + 13, 1,
+                                              c->dev_err);
+        order = pin1 ? c->pv1 : c->pv0;
+    }
     sm.mark(3);
     launch_exclusive_scan(q, c->p_ntiles, c->p_offsets, P, c->misc + 0, c->scan_status, c->misc + 13, c->misc + 1,
                           c->dev_err, order);
@@ -690,10 +719,13 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     const SortScratch ss{c->hist + 4 * 256, c->sort_status, c->misc + 6};
     const bool in1 = launch_radix_sort(q, c->keys0, c->vals0, c->keys1, c->vals1, c->misc + 0, cap, tbits, ss,
                                        c->misc + 13, c->dev_err, true, 32, 5);
-    const uint64_t* skeys = in1 ? c->keys1 : c->keys0;
-    const uint32_t* svals = in1 ? c->vals1 : c->vals0;
+    uint64_t* skeys = in1 ? c->keys1 : c->keys0;
+    uint32_t* svals = in1 ? c->vals1 : c->vals0;
     sm.mark(5);
-    launch_tile_ranges(q, skeys, c->misc + 0, cap, ranges, svals, save ? save->vals : nullptr);
+    launch_tile_ranges(q, skeys, c->misc + 0, cap, ranges, svals, save && !per_tile ? save->vals : nullptr);
+    if (per_tile)
+        launch_tile_depth_sort(q, ranges, tiles, skeys, svals, in1 ? c->keys0 : c->keys1, save ? save->vals : nullptr,
+                               c->misc + 9, c->tile_order);  // the work queue is built after it
     CompositeArgs a;
     a.ranges = ranges;
     a.vals = svals;
@@ -726,7 +758,7 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     c->cur_ranges = ranges;
     c->last_mode = mode;
     c->last_neural = nn != nullptr;
-    c->last_passes = (P > 0 ? sort_passes(32) : 0) + sort_passes(tbits);
+    c->last_passes = (P > 0 && !per_tile ? sort_passes(32) : 0) + sort_passes(tbits);
     c->last_prims = P;
     c->last_gauss = M;
     c->last_tiles = tiles;

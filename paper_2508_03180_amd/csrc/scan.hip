@@ -251,7 +251,7 @@ __global__ __launch_bounds__(256) void k_emit_keys(int P, const uint32_t* __rest
     // grid-stride over the depth order: a capped grid, so each workgroup adds
     // its histogram to the global one once
     for (int i0 = blockIdx.x * blockDim.x + threadIdx.x; i0 < P; i0 += gridDim.x * blockDim.x) {
-        const uint32_t p = order[i0];
+        const uint32_t p = order ? order[i0] : (uint32_t)i0;  // null order: id order
         if (p >= (uint32_t)P) continue;  // a permutation of [0, P) unless a sort wait timed out
         const uint32_t nt = ntiles[p];
         if (nt) {

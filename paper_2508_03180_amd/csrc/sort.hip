@@ -282,4 +282,271 @@ bool launch_radix_sort32(hipStream_t st, uint32_t* k0, uint32_t* v0, uint32_t* k
     return radix_sort(st, k0, v0, k1, v1, nullptr, n, 0, 32, s, epoch, tag0, err);
 }
 
+// ------------------------------------------------ per-tile depth order
+
+// The second way to the lists' order, for frames with short tile lists: the
+// keys are emitted in primitive-id order and sorted stably on their tile bits
+// only; then each tile's run is sorted by (depth bits, id) -- the
+// (tile, depth) order of Sec. IV-B with ties by id, as the depth sort
+// followed by the tile sort gives it.  The (depth bits, id) pairs of a run
+// are distinct, so any correct sort yields that order.
+//
+// Two kernels, one per kind of run.  Runs of up to 256 entries (nearly all
+// of them) are sorted by one wavefront in registers, entry lane + 64 m in
+// slot m of the lane (1, 2 or 4 slots): a bitonic network whose exchanges
+// between entries less than 64 apart are lane shuffles and the others moves
+// between a lane's own slots -- no LDS and no barrier.  That kernel also
+// lists the tiles with longer runs (a device counter, zeroed by the frame's
+// clear).  A fixed grid of workgroups then takes the listed tiles, one
+// workgroup per tile at a time: up to kTileSortLds entries by a bitonic
+// network whose exchanges stay in the workgroup's four wavefronts except
+// for three stages through LDS, and longer ones in chunks of kTileSortLds merged
+// in global memory, each element's place being its index in its run plus the
+// number of smaller elements in the other run (binary search); the two
+// buffers are the free ping-pong buffer of the tile sort and the run's own
+// key slots.  Runs are written back in place: key = tile << 32 | depth bits,
+// value = id, and the values also into vcopy when set.
+constexpr int kTileSortLds = 4096;
+constexpr int kTileSortThreads = 256;
+constexpr int kTileSortGroups = 512;  // workgroups taking the listed tiles
+
+__device__ __forceinline__ void put_sorted(uint64_t* kr, uint32_t* vr, uint32_t* vcopy, uint64_t tbits, int i, uint64_t v) {
+    kr[i] = tbits | (v >> 32);
+    vr[i] = (uint32_t)v;
+    if (vcopy) vcopy[i] = (uint32_t)v;
+}
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, 64);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// A run of at most 64 M entries sorted by one wavefront, entry lane + 64 m
+// in v[m] (the padding holds the largest value).
+template <int M>
+__device__ __forceinline__ void wave_sort_run(uint64_t* __restrict__ kr, uint32_t* __restrict__ vr, uint32_t* vc,
+                                     uint64_t tbits, int L, int lane) {
+    uint64_t v[M];
+#pragma unroll
+    for (int m = 0; m < M; m++) {
+        const int e = lane + 64 * m;
+        v[m] = e < L ? (kr[e] << 32) | vr[e] : ~0ull;  // (depth bits, id)
+    }
+#pragma unroll
+    for (int k = 2; k <= 64 * M; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= 64) {  // entries m and m ^ (j / 64) of the lane
+#pragma unroll
+                for (int m = 0; m < M; m++) {
+                    const int pm = m ^ (j >> 6);
+                    if (pm > m) {
+                        const bool up = ((lane + 64 * m) & k) == 0;
+                        const uint64_t a = v[m], b = v[pm];
+                        const bool sw = (a > b) == up;
+                        v[m] = sw ? b : a;
+                        v[pm] = sw ? a : b;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < M; m++) {
+                    const uint64_t o = shfl_xor_u64(v[m], j);
+                    const int e = lane + 64 * m;
+                    const bool low = (e & j) == 0, up = (e & k) == 0;
+                    v[m] = (low == up) ? (v[m] < o ? v[m] : o) : (v[m] < o ? o : v[m]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < M; m++) {
+        const int e = lane + 64 * m;
+        if (e < L) put_sorted(kr, vr, vc, tbits, e, v[m]);
+    }
+}
+
+// Runs of 1..256 entries: one wavefront per tile; longer runs are listed.
+__global__ __launch_bounds__(64) void k_tile_sort_wave(const uint32_t* __restrict__ ranges,
+                                                       uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                       uint32_t* __restrict__ vcopy, uint32_t* __restrict__ long_count,
+                                                       uint32_t* __restrict__ long_list) {
+    const int lane = threadIdx.x;
+    const uint32_t tile = blockIdx.x;
+    const uint32_t s = ranges[2 * tile];
+    const int L = (int)(ranges[2 * tile + 1] - s);
+    if (L > 256) {
+        if (lane == 0) long_list[atomicAdd(long_count, 1u)] = tile;
+        return;
+    }
+    if (L < 1) return;
+    uint64_t* kr = keys + s;
+    uint32_t* vr = vals + s;
+    uint32_t* vc = vcopy ? vcopy + s : nullptr;
+    const uint64_t tbits = (uint64_t)tile << 32;
+    if (L <= 64) wave_sort_run<1>(kr, vr, vc, tbits, L, lane);
+    else if (L <= 128) wave_sort_run<2>(kr, vr, vc, tbits, L, lane);
+    else wave_sort_run<4>(kr, vr, vc, tbits, L, lane);
+}
+
+// A run of at most 256 M entries sorted by the workgroup's four wavefronts:
+// wavefront w holds entries w 64 M + lane + 64 m in v[m] (the padding holds
+// the largest value).  Exchanges between entries less than 64 M apart stay
+// in the wavefront (lane shuffles, or moves between a lane's slots); only the
+// stages between wavefronts go through LDS (sd, 256 M entries): three of
+// them for any M.  With out set the sorted entries [0, L) go there instead
+// of back into the run.
+template <int M>
+__device__ __forceinline__ void group_sort_run(uint64_t* sd, uint64_t* __restrict__ kr, uint32_t* __restrict__ vr,
+                                      uint32_t* vc, uint64_t* out, uint64_t tbits, int L, int tid) {
+    constexpr int B = 64 * M, P = 4 * B;
+    const int w = tid >> 6, lane = tid & 63;
+    uint64_t v[M];
+#pragma unroll
+    for (int m = 0; m < M; m++) {
+        const int e = w * B + lane + 64 * m;
+        v[m] = e < L ? (kr[e] << 32) | vr[e] : ~0ull;  // (depth bits, id)
+    }
+#pragma unroll
+    for (int k = 2; k <= P; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= B) {  // partner in another wavefront
+#pragma unroll
+                for (int m = 0; m < M; m++) sd[w * B + lane + 64 * m] = v[m];
+                __syncthreads();
+#pragma unroll
+                for (int m = 0; m < M; m++) {
+                    const int e = w * B + lane + 64 * m;
+                    const uint64_t o = sd[e ^ j];
+                    const bool low = (e & j) == 0, up = (e & k) == 0;
+                    v[m] = (low == up) ? (v[m] < o ? v[m] : o) : (v[m] < o ? o : v[m]);
+                }
+                __syncthreads();
+            } else if (j >= 64) {  // slots m and m ^ (j / 64) of the lane
+#pragma unroll
+                for (int m = 0; m < M; m++) {
+                    const int pm = m ^ (j >> 6);
+                    if (pm > m) {
+                        const bool up = ((w * B + lane + 64 * m) & k) == 0;
+                        const uint64_t x = v[m], y = v[pm];
+                        const bool sw = (x > y) == up;
+                        v[m] = sw ? y : x;
+                        v[pm] = sw ? x : y;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < M; m++) {
+                    const uint64_t o = shfl_xor_u64(v[m], j);
+                    const int e = w * B + lane + 64 * m;
+                    const bool low = (e & j) == 0, up = (e & k) == 0;
+                    v[m] = (low == up) ? (v[m] < o ? v[m] : o) : (v[m] < o ? o : v[m]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < M; m++) {
+        const int e = w * B + lane + 64 * m;
+        if (e < L) {
+            if (out) out[e] = v[m];
+            else put_sorted(kr, vr, vc, tbits, e, v[m]);
+        }
+    }
+}
+
+__device__ __forceinline__ void group_sort_any(uint64_t* sd, uint64_t* kr, uint32_t* vr, uint32_t* vc, uint64_t* out,
+                                      uint64_t tbits, int L, int tid) {
+    if (L <= 512) group_sort_run<2>(sd, kr, vr, vc, out, tbits, L, tid);
+    else if (L <= 1024) group_sort_run<4>(sd, kr, vr, vc, out, tbits, L, tid);
+    else if (L <= 2048) group_sort_run<8>(sd, kr, vr, vc, out, tbits, L, tid);
+    else group_sort_run<16>(sd, kr, vr, vc, out, tbits, L, tid);
+}
+
+// Number of entries of the ascending array y[0, n) below v.
+__device__ __forceinline__ int count_below(const uint64_t* y, int n, uint64_t v) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int m = (lo + hi) >> 1;
+        if (y[m] < v) lo = m + 1;
+        else hi = m;
+    }
+    return lo;
+}
+
+// One run of more than 256 entries, by the whole workgroup (sd: its LDS).
+__device__ __forceinline__ void sort_long_run(uint64_t* sd, uint32_t tile, uint32_t s, int L, uint64_t* __restrict__ keys,
+                                     uint32_t* __restrict__ vals, uint64_t* __restrict__ spare,
+                                     uint32_t* __restrict__ vcopy, int tid) {
+    uint64_t* kr = keys + s;
+    uint32_t* vr = vals + s;
+    uint32_t* vc = vcopy ? vcopy + s : nullptr;
+    const uint64_t tbits = (uint64_t)tile << 32;
+    // A run of up to kTileSortLds entries is one chunk sorted straight back
+    // into place; a longer one is sorted in chunks into the spare buffer,
+    // then merged pairwise.  (One call site: the network is inlined once.)
+    const bool chunked = L > kTileSortLds;
+    uint64_t* a = spare + s;
+    for (int c0 = 0; c0 < L; c0 += kTileSortLds) {
+        group_sort_any(sd, kr + c0, vr + c0, vc, chunked ? a + c0 : nullptr, tbits, min(kTileSortLds, L - c0), tid);
+        __syncthreads();  // sd is reused by the next chunk
+    }
+    if (!chunked) return;
+    __threadfence_block();
+    __syncthreads();
+    uint64_t* src = a;
+    uint64_t* dst = kr;  // the run's own key slots (every key has been read)
+    for (int w = kTileSortLds; w < L; w <<= 1) {
+        for (int i = tid; i < L; i += kTileSortThreads) {
+            const int x0 = (i / (2 * w)) * (2 * w), y0 = x0 + w;
+            const uint64_t v = src[i];
+            if (i < y0) {  // in the first run of the pair
+                const int yn = y0 < L ? min(w, L - y0) : 0;
+                dst[i + count_below(src + y0, yn, v)] = v;
+            } else {
+                dst[x0 + (i - y0) + count_below(src + x0, w, v)] = v;
+            }
+        }
+        __threadfence_block();
+        __syncthreads();
+        uint64_t* t = src;
+        src = dst;
+        dst = t;
+    }
+    for (int i = tid; i < L; i += kTileSortThreads) put_sorted(kr, vr, vc, tbits, i, src[i]);
+}
+
+// The listed tiles (runs of more than 256 entries), one per workgroup at a
+// time.
+__global__ __launch_bounds__(kTileSortThreads) void k_tile_sort_group(const uint32_t* __restrict__ ranges,
+                                                                      uint64_t* __restrict__ keys,
+                                                                      uint32_t* __restrict__ vals,
+                                                                      uint64_t* __restrict__ spare,
+                                                                      uint32_t* __restrict__ vcopy,
+                                                                      const uint32_t* __restrict__ long_count,
+                                                                      const uint32_t* __restrict__ long_list) {
+    __shared__ uint64_t sd[kTileSortLds];
+    const int tid = threadIdx.x;
+    const uint32_t n = *long_count;
+    for (uint32_t e = blockIdx.x; e < n; e += gridDim.x) {
+        const uint32_t tile = long_list[e];
+        const uint32_t s = ranges[2 * tile];
+        const int L = (int)(ranges[2 * tile + 1] - s);
+        sort_long_run(sd, tile, s, L, keys, vals, spare, vcopy, tid);
+        __syncthreads();  // sd is reused by the next tile
+    }
+}
+
+void launch_tile_depth_sort(hipStream_t st, const uint32_t* ranges, int tiles, uint64_t* keys, uint32_t* vals,
+                            uint64_t* spare, uint32_t* vcopy, uint32_t* long_count, uint32_t* long_list) {
+    if (tiles <= 0) return;
+    hipLaunchKernelGGL(k_tile_sort_wave, dim3((unsigned)tiles), dim3(64), 0, st, ranges, keys, vals, vcopy,
+                       long_count, long_list);
+    const unsigned grid = (unsigned)(tiles < kTileSortGroups ? tiles : kTileSortGroups);
+    hipLaunchKernelGGL(k_tile_sort_group, dim3(grid), dim3(kTileSortThreads), 0, st, ranges, keys, vals, spare, vcopy,
+                       (const uint32_t*)long_count, (const uint32_t*)long_list);
+}
+
 }  // namespace dgs
