@@ -724,8 +724,8 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     sm.mark(5);
     launch_tile_ranges(q, skeys, c->misc + 0, cap, ranges, svals, save && !per_tile ? save->vals : nullptr);
     if (per_tile)
-        launch_tile_depth_sort(q, ranges, tiles, skeys, svals, in1 ? c->keys0 : c->keys1, save ? save->vals : nullptr,
-                               c->misc + 9, c->tile_order);  // the work queue is built after it
+        launch_tile_depth_sort(q, ranges, tiles, skeys, svals, in1 ? c->keys0 : c->keys1,
+                               save ? save->vals : nullptr);
     CompositeArgs a;
     a.ranges = ranges;
     a.vals = svals;

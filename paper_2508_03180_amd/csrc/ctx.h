@@ -88,8 +88,7 @@ struct dgs_ctx_s {
     int64_t cap_loss_coef = 0, cap_loss_part = 0;
     uint32_t* hist = nullptr;     // [8][256]: [0..3] primitive depth bytes, [4..6] key tile bytes
     uint32_t* misc = nullptr;     // [0] key total, [1] scan ticket, [2..5] depth sort tickets,
-                                  // [6..8] tile sort tickets, [9] per-tile order's long-run
-                                  // count, [10] sort count,
+                                  // [6..8] tile sort tickets, [9] spare, [10] sort count,
                                   // [11..12] compositor work-queue head and item count,
                                   // [13] look-back frame counter
     int* dev_err = nullptr;

@@ -87,10 +87,9 @@ void launch_emit_keys(hipStream_t st, int P, const uint32_t* order, const uint32
 // Per-tile depth order: each tile's run of the tile-sorted keys (emitted in
 // primitive-id order) sorted by (depth bits, id) in place; values also into
 // vcopy when set; spare: a free u64 buffer of the key capacity (used by runs
-// longer than what one workgroup sorts in LDS); long_count (zeroed
-// beforehand) and long_list [tiles]: scratch for the tiles with long runs.
+// longer than what one workgroup sorts in registers).
 void launch_tile_depth_sort(hipStream_t st, const uint32_t* ranges, int tiles, uint64_t* keys, uint32_t* vals,
-                            uint64_t* spare, uint32_t* vcopy, uint32_t* long_count, uint32_t* long_list);
+                            uint64_t* spare, uint32_t* vcopy);
 
 void launch_tile_ranges(hipStream_t st, const uint64_t* keys, const uint32_t* n_ptr, uint32_t cap,
                         uint32_t* ranges, const uint32_t* vin = nullptr, uint32_t* vout = nullptr);

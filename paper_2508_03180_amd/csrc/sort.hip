@@ -291,24 +291,30 @@ bool launch_radix_sort32(hipStream_t st, uint32_t* k0, uint32_t* v0, uint32_t* k
 // followed by the tile sort gives it.  The (depth bits, id) pairs of a run
 // are distinct, so any correct sort yields that order.
 //
-// Two kernels, one per kind of run.  Runs of up to 256 entries (nearly all
-// of them) are sorted by one wavefront in registers, entry lane + 64 m in
-// slot m of the lane (1, 2 or 4 slots): a bitonic network whose exchanges
-// between entries less than 64 apart are lane shuffles and the others moves
-// between a lane's own slots -- no LDS and no barrier.  That kernel also
-// lists the tiles with longer runs (a device counter, zeroed by the frame's
-// clear).  A fixed grid of workgroups then takes the listed tiles, one
-// workgroup per tile at a time: up to kTileSortLds entries by a bitonic
-// network whose exchanges stay in the workgroup's four wavefronts except
-// for three stages through LDS, and longer ones in chunks of kTileSortLds merged
-// in global memory, each element's place being its index in its run plus the
-// number of smaller elements in the other run (binary search); the two
-// buffers are the free ping-pong buffer of the tile sort and the run's own
-// key slots.  Runs are written back in place: key = tile << 32 | depth bits,
-// value = id, and the values also into vcopy when set.
-constexpr int kTileSortLds = 4096;
-constexpr int kTileSortThreads = 256;
-constexpr int kTileSortGroups = 512;  // workgroups taking the listed tiles
+// One launch of independent workgroups of 16 wavefronts.  Wavefront w of
+// workgroup b takes one tile (the tiles spread over the image, so that the
+// few long runs spread over the workgroups).  A run of up to 256 entries is
+// sorted by its wavefront alone, entry lane + 64 m in register slot m of
+// the lane (1, 2 or 4 slots): a bitonic network whose exchanges between
+// entries less than 64 apart are cross-lane moves (DPP and row swaps, no
+// LDS) and the others moves between a lane's own slots.  The workgroup then
+// sorts its longer runs with the same network spread over several
+// wavefronts, only the exchanges between wavefronts going through LDS: runs
+// of up to 512 entries two at a time, one on each half of the workgroup,
+// longer ones with all 16 wavefronts, up to 2048 entries (2 per lane: more
+// would spill registers at the 64 VGPRs that let two workgroups share a
+// CU).  Runs longer than that are sorted in chunks of 2048 into the free
+// ping-pong buffer of the tile sort and merged pairwise between that buffer
+// and the run's own key slots, each element's place being its index in its
+// half plus the number of smaller elements in the other half (binary
+// search).  Runs are written back in place: key = tile << 32 | depth bits,
+// value = id, the values also into vcopy when set.  Every helper is
+// inlined: the kernel makes no calls.
+constexpr int kTsWaves = 16;
+constexpr int kTsThreads = 64 * kTsWaves;
+constexpr int kTsShort = 256;              // longest run one wavefront sorts
+constexpr int kTsChunk = 2 * kTsThreads;  // longest run the workgroup sorts in registers
+constexpr int kTsHalf = kTsThreads / 2;   // longest run half of the workgroup sorts
 
 __device__ __forceinline__ void put_sorted(uint64_t* kr, uint32_t* vr, uint32_t* vcopy, uint64_t tbits, int i, uint64_t v) {
     kr[i] = tbits | (v >> 32);
@@ -316,120 +322,89 @@ __device__ __forceinline__ void put_sorted(uint64_t* kr, uint32_t* vr, uint32_t*
     if (vcopy) vcopy[i] = (uint32_t)v;
 }
 
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
-    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, 64);
-    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, 64);
+// The value that lane ^ J holds, for J a power of two below 64, without
+// LDS: DPP moves for partners inside a row of 16 lanes, gfx950's row swaps
+// for 16 and 32 (each returns the two operands after swapping the odd rows
+// of the first with the even rows of the second, resp. the upper half of
+// the first with the lower half of the second).
+template <int J>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v, int lane) {
+    if constexpr (J == 1) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+    } else if constexpr (J == 2) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+    } else if constexpr (J == 4) {
+        const int m = __builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, false);  // row_half_mirror: lane ^ 7
+        return (uint32_t)__builtin_amdgcn_mov_dpp(m, 0x1B, 0xF, 0xF, false);     // quad_perm [3,2,1,0]: ^ 3
+    } else if constexpr (J == 8) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, false);  // row_ror:8
+    } else if constexpr (J == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (lane & 16) ? r[0] : r[1];
+    } else {
+        static_assert(J == 32, "lane distance");
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (lane & 32) ? r[0] : r[1];
+    }
+}
+
+template <int J>
+__device__ __forceinline__ uint64_t lane_xor64(uint64_t v, int lane) {
+    const uint32_t lo = lane_xor<J>((uint32_t)v, lane), hi = lane_xor<J>((uint32_t)(v >> 32), lane);
     return ((uint64_t)hi << 32) | lo;
 }
 
-// A run of at most 64 M entries sorted by one wavefront, entry lane + 64 m
-// in v[m] (the padding holds the largest value).
-template <int M>
-__device__ __forceinline__ void wave_sort_run(uint64_t* __restrict__ kr, uint32_t* __restrict__ vr, uint32_t* vc,
-                                     uint64_t tbits, int L, int lane) {
-    uint64_t v[M];
-#pragma unroll
-    for (int m = 0; m < M; m++) {
-        const int e = lane + 64 * m;
-        v[m] = e < L ? (kr[e] << 32) | vr[e] : ~0ull;  // (depth bits, id)
-    }
-#pragma unroll
-    for (int k = 2; k <= 64 * M; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            if (j >= 64) {  // entries m and m ^ (j / 64) of the lane
-#pragma unroll
-                for (int m = 0; m < M; m++) {
-                    const int pm = m ^ (j >> 6);
-                    if (pm > m) {
-                        const bool up = ((lane + 64 * m) & k) == 0;
-                        const uint64_t a = v[m], b = v[pm];
-                        const bool sw = (a > b) == up;
-                        v[m] = sw ? b : a;
-                        v[pm] = sw ? a : b;
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int m = 0; m < M; m++) {
-                    const uint64_t o = shfl_xor_u64(v[m], j);
-                    const int e = lane + 64 * m;
-                    const bool low = (e & j) == 0, up = (e & k) == 0;
-                    v[m] = (low == up) ? (v[m] < o ? v[m] : o) : (v[m] < o ? o : v[m]);
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int m = 0; m < M; m++) {
-        const int e = lane + 64 * m;
-        if (e < L) put_sorted(kr, vr, vc, tbits, e, v[m]);
+// j is a constant once the networks' loops are unrolled
+__device__ __forceinline__ uint64_t lane_xor64(uint64_t v, int j, int lane) {
+    switch (j) {
+        case 1: return lane_xor64<1>(v, lane);
+        case 2: return lane_xor64<2>(v, lane);
+        case 4: return lane_xor64<4>(v, lane);
+        case 8: return lane_xor64<8>(v, lane);
+        case 16: return lane_xor64<16>(v, lane);
+        default: return lane_xor64<32>(v, lane);
     }
 }
 
-// Runs of 1..256 entries: one wavefront per tile; longer runs are listed.
-__global__ __launch_bounds__(64) void k_tile_sort_wave(const uint32_t* __restrict__ ranges,
-                                                       uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                                                       uint32_t* __restrict__ vcopy, uint32_t* __restrict__ long_count,
-                                                       uint32_t* __restrict__ long_list) {
-    const int lane = threadIdx.x;
-    const uint32_t tile = blockIdx.x;
-    const uint32_t s = ranges[2 * tile];
-    const int L = (int)(ranges[2 * tile + 1] - s);
-    if (L > 256) {
-        if (lane == 0) long_list[atomicAdd(long_count, 1u)] = tile;
-        return;
-    }
-    if (L < 1) return;
-    uint64_t* kr = keys + s;
-    uint32_t* vr = vals + s;
-    uint32_t* vc = vcopy ? vcopy + s : nullptr;
-    const uint64_t tbits = (uint64_t)tile << 32;
-    if (L <= 64) wave_sort_run<1>(kr, vr, vc, tbits, L, lane);
-    else if (L <= 128) wave_sort_run<2>(kr, vr, vc, tbits, L, lane);
-    else wave_sort_run<4>(kr, vr, vc, tbits, L, lane);
+// One bitonic compare-exchange of entry e (value v) with entry e ^ j, whose
+// value is o: the lower entry of the pair keeps the smaller value in an
+// ascending block, the larger in a descending one.  ej: bit j of e is set
+// (the upper entry); ek: bit k of e is set (a descending block of the k-merge).
+__device__ __forceinline__ uint64_t cx(uint64_t v, uint64_t o, bool ej, bool ek) {
+    return ((v < o) == (ej == ek)) ? v : o;
 }
 
-// A run of at most 256 M entries sorted by the workgroup's four wavefronts:
-// wavefront w holds entries w 64 M + lane + 64 m in v[m] (the padding holds
-// the largest value).  Exchanges between entries less than 64 M apart stay
-// in the wavefront (lane shuffles, or moves between a lane's slots); only the
-// stages between wavefronts go through LDS (sd, 256 M entries): three of
-// them for any M.  With out set the sorted entries [0, L) go there instead
-// of back into the run.
-template <int M>
-__device__ __forceinline__ void group_sort_run(uint64_t* sd, uint64_t* __restrict__ kr, uint32_t* __restrict__ vr,
-                                      uint32_t* vc, uint64_t* out, uint64_t tbits, int L, int tid) {
-    constexpr int B = 64 * M, P = 4 * B;
-    const int w = tid >> 6, lane = tid & 63;
-    uint64_t v[M];
+// Bits 0..5 of the lane index (each a lane mask the compiler can keep in
+// scalar registers).
+struct LaneBits {
+    bool b[6];
+    __device__ __forceinline__ explicit LaneBits(int lane) {
 #pragma unroll
-    for (int m = 0; m < M; m++) {
-        const int e = w * B + lane + 64 * m;
-        v[m] = e < L ? (kr[e] << 32) | vr[e] : ~0ull;  // (depth bits, id)
+        for (int i = 0; i < 6; i++) b[i] = (lane >> i) & 1;
     }
+    __device__ __forceinline__ bool operator[](int pow2) const { return b[__builtin_ctz(pow2)]; }
+};
+
+// The stages of a bitonic network over P entries held by consecutive
+// wavefronts, entry base + lane + 64 m in v[m] of wavefront base / (64 M)
+// (base a multiple of 64 M), that stay inside the wavefront: exchanges
+// 64 or more apart between a lane's slots, shorter ones across lanes.
+// Stages j >= 64 M need another wavefront's entries: xchg(k, j) does those.
+template <int M, class Xchg>
+__device__ __forceinline__ void bitonic(uint64_t (&v)[M], int P, int base, int lane, Xchg xchg) {
+    const LaneBits lb(lane);
 #pragma unroll
     for (int k = 2; k <= P; k <<= 1) {
 #pragma unroll
         for (int j = k >> 1; j > 0; j >>= 1) {
-            if (j >= B) {  // partner in another wavefront
-#pragma unroll
-                for (int m = 0; m < M; m++) sd[w * B + lane + 64 * m] = v[m];
-                __syncthreads();
-#pragma unroll
-                for (int m = 0; m < M; m++) {
-                    const int e = w * B + lane + 64 * m;
-                    const uint64_t o = sd[e ^ j];
-                    const bool low = (e & j) == 0, up = (e & k) == 0;
-                    v[m] = (low == up) ? (v[m] < o ? v[m] : o) : (v[m] < o ? o : v[m]);
-                }
-                __syncthreads();
+            if (j >= 64 * M) {
+                xchg(k, j);
             } else if (j >= 64) {  // slots m and m ^ (j / 64) of the lane
 #pragma unroll
                 for (int m = 0; m < M; m++) {
                     const int pm = m ^ (j >> 6);
                     if (pm > m) {
-                        const bool up = ((w * B + lane + 64 * m) & k) == 0;
+                        const bool up = ((base + 64 * m) & k) == 0;
                         const uint64_t x = v[m], y = v[pm];
                         const bool sw = (x > y) == up;
                         v[m] = sw ? y : x;
@@ -439,17 +414,66 @@ __device__ __forceinline__ void group_sort_run(uint64_t* sd, uint64_t* __restric
             } else {
 #pragma unroll
                 for (int m = 0; m < M; m++) {
-                    const uint64_t o = shfl_xor_u64(v[m], j);
-                    const int e = w * B + lane + 64 * m;
-                    const bool low = (e & j) == 0, up = (e & k) == 0;
-                    v[m] = (low == up) ? (v[m] < o ? v[m] : o) : (v[m] < o ? o : v[m]);
+                    const bool ek = k < 64 ? lb[k] : ((base + 64 * m) & k) != 0;
+                    v[m] = cx(v[m], lane_xor64(v[m], j, lane), lb[j], ek);
                 }
             }
         }
     }
+}
+
+// A run of at most P <= 64 M entries sorted by one wavefront (the padding
+// holds the largest value); with M = 1 and P < 64 the network stops at
+// blocks of P lanes.
+template <int M, int P = 64 * M>
+__device__ __forceinline__ void wave_sort_run(uint64_t* __restrict__ kr, uint32_t* __restrict__ vr, uint32_t* vc,
+                                              uint64_t tbits, int L, int lane) {
+    uint64_t v[M];
 #pragma unroll
     for (int m = 0; m < M; m++) {
-        const int e = w * B + lane + 64 * m;
+        const int e = lane + 64 * m;
+        v[m] = e < L ? (kr[e] << 32) | vr[e] : ~0ull;  // (depth bits, id)
+    }
+    bitonic<M>(v, P, 0, lane, [](int, int) {});
+#pragma unroll
+    for (int m = 0; m < M; m++) {
+        const int e = lane + 64 * m;
+        if (e < L) put_sorted(kr, vr, vc, tbits, e, v[m]);
+    }
+}
+
+// A run of at most 64 W M entries sorted by W wavefronts of the workgroup
+// (tid: the thread's index among them): wavefront w holds entries
+// w 64 M + lane + 64 m (the padding holds the largest value); the stages
+// between wavefronts go through LDS (sd, 64 W M entries).  With out set the
+// sorted entries [0, L) go there instead of back into the run.
+// Its barriers are the workgroup's: every wavefront of the workgroup runs
+// the same network at the same time.
+template <int M, int W = kTsWaves>
+__device__ __forceinline__ void group_sort_run(uint64_t* sd, uint64_t* __restrict__ kr, uint32_t* __restrict__ vr,
+                                               uint32_t* vc, uint64_t* out, uint64_t tbits, int L, int tid) {
+    constexpr int B = 64 * M;
+    const int w = tid >> 6, lane = tid & 63, base = w * B;
+    uint64_t v[M];
+#pragma unroll
+    for (int m = 0; m < M; m++) {
+        const int e = base + lane + 64 * m;
+        v[m] = e < L ? (kr[e] << 32) | vr[e] : ~0ull;  // (depth bits, id)
+    }
+    bitonic<M>(v, 64 * W * M, base, lane, [&](int k, int j) {
+#pragma unroll
+        for (int m = 0; m < M; m++) sd[base + lane + 64 * m] = v[m];
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < M; m++) {
+            const int e = base + lane + 64 * m;
+            v[m] = cx(v[m], sd[e ^ j], (e & j) != 0, (e & k) != 0);
+        }
+        __syncthreads();
+    });
+#pragma unroll
+    for (int m = 0; m < M; m++) {
+        const int e = base + lane + 64 * m;
         if (e < L) {
             if (out) out[e] = v[m];
             else put_sorted(kr, vr, vc, tbits, e, v[m]);
@@ -458,11 +482,9 @@ __device__ __forceinline__ void group_sort_run(uint64_t* sd, uint64_t* __restric
 }
 
 __device__ __forceinline__ void group_sort_any(uint64_t* sd, uint64_t* kr, uint32_t* vr, uint32_t* vc, uint64_t* out,
-                                      uint64_t tbits, int L, int tid) {
-    if (L <= 512) group_sort_run<2>(sd, kr, vr, vc, out, tbits, L, tid);
-    else if (L <= 1024) group_sort_run<4>(sd, kr, vr, vc, out, tbits, L, tid);
-    else if (L <= 2048) group_sort_run<8>(sd, kr, vr, vc, out, tbits, L, tid);
-    else group_sort_run<16>(sd, kr, vr, vc, out, tbits, L, tid);
+                                               uint64_t tbits, int L, int tid) {
+    if (L <= kTsThreads) group_sort_run<1>(sd, kr, vr, vc, out, tbits, L, tid);
+    else group_sort_run<2>(sd, kr, vr, vc, out, tbits, L, tid);
 }
 
 // Number of entries of the ascending array y[0, n) below v.
@@ -476,21 +498,21 @@ __device__ __forceinline__ int count_below(const uint64_t* y, int n, uint64_t v)
     return lo;
 }
 
-// One run of more than 256 entries, by the whole workgroup (sd: its LDS).
-__device__ __forceinline__ void sort_long_run(uint64_t* sd, uint32_t tile, uint32_t s, int L, uint64_t* __restrict__ keys,
-                                     uint32_t* __restrict__ vals, uint64_t* __restrict__ spare,
-                                     uint32_t* __restrict__ vcopy, int tid) {
+// One run of more than kTsHalf entries, by the whole workgroup (sd: its LDS).
+__device__ __forceinline__ void sort_long_run(uint64_t* sd, uint32_t tile, uint32_t s, int L,
+                                              uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                              uint64_t* __restrict__ spare, uint32_t* __restrict__ vcopy, int tid) {
     uint64_t* kr = keys + s;
     uint32_t* vr = vals + s;
     uint32_t* vc = vcopy ? vcopy + s : nullptr;
     const uint64_t tbits = (uint64_t)tile << 32;
-    // A run of up to kTileSortLds entries is one chunk sorted straight back
-    // into place; a longer one is sorted in chunks into the spare buffer,
-    // then merged pairwise.  (One call site: the network is inlined once.)
-    const bool chunked = L > kTileSortLds;
+    // A run of up to kTsChunk entries is one chunk sorted straight back into
+    // place; a longer one is sorted in chunks into the spare buffer, then
+    // merged pairwise.  (One call site: the network is inlined once.)
+    const bool chunked = L > kTsChunk;
     uint64_t* a = spare + s;
-    for (int c0 = 0; c0 < L; c0 += kTileSortLds) {
-        group_sort_any(sd, kr + c0, vr + c0, vc, chunked ? a + c0 : nullptr, tbits, min(kTileSortLds, L - c0), tid);
+    for (int c0 = 0; c0 < L; c0 += kTsChunk) {
+        group_sort_any(sd, kr + c0, vr + c0, vc, chunked ? a + c0 : nullptr, tbits, min(kTsChunk, L - c0), tid);
         __syncthreads();  // sd is reused by the next chunk
     }
     if (!chunked) return;
@@ -498,8 +520,8 @@ __device__ __forceinline__ void sort_long_run(uint64_t* sd, uint32_t tile, uint3
     __syncthreads();
     uint64_t* src = a;
     uint64_t* dst = kr;  // the run's own key slots (every key has been read)
-    for (int w = kTileSortLds; w < L; w <<= 1) {
-        for (int i = tid; i < L; i += kTileSortThreads) {
+    for (int w = kTsChunk; w < L; w <<= 1) {
+        for (int i = tid; i < L; i += kTsThreads) {
             const int x0 = (i / (2 * w)) * (2 * w), y0 = x0 + w;
             const uint64_t v = src[i];
             if (i < y0) {  // in the first run of the pair
@@ -515,38 +537,107 @@ __device__ __forceinline__ void sort_long_run(uint64_t* sd, uint32_t tile, uint3
         src = dst;
         dst = t;
     }
-    for (int i = tid; i < L; i += kTileSortThreads) put_sorted(kr, vr, vc, tbits, i, src[i]);
+    for (int i = tid; i < L; i += kTsThreads) put_sorted(kr, vr, vc, tbits, i, src[i]);
 }
 
-// The listed tiles (runs of more than 256 entries), one per workgroup at a
-// time.
-__global__ __launch_bounds__(kTileSortThreads) void k_tile_sort_group(const uint32_t* __restrict__ ranges,
-                                                                      uint64_t* __restrict__ keys,
-                                                                      uint32_t* __restrict__ vals,
-                                                                      uint64_t* __restrict__ spare,
-                                                                      uint32_t* __restrict__ vcopy,
-                                                                      const uint32_t* __restrict__ long_count,
-                                                                      const uint32_t* __restrict__ long_list) {
-    __shared__ uint64_t sd[kTileSortLds];
-    const int tid = threadIdx.x;
-    const uint32_t n = *long_count;
-    for (uint32_t e = blockIdx.x; e < n; e += gridDim.x) {
-        const uint32_t tile = long_list[e];
-        const uint32_t s = ranges[2 * tile];
-        const int L = (int)(ranges[2 * tile + 1] - s);
-        sort_long_run(sd, tile, s, L, keys, vals, spare, vcopy, tid);
-        __syncthreads();  // sd is reused by the next tile
+// The workgroup's long runs as lanes 0..15 of every wavefront hold them.
+struct LongRuns {
+    int tile, s, len;
+};
+
+// The runs of mask (lanes of q) sorted kTsWaves / W at a time, one per group
+// of W wavefronts, each by a network of 64 W entries; a group left without
+// a run in the last round runs the network on padding only.
+template <int W>
+__device__ __forceinline__ void sort_in_groups(uint64_t mask, const LongRuns& q, uint64_t* sd,
+                                               uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                               uint32_t* __restrict__ vcopy, int tid) {
+    constexpr int NG = kTsWaves / W;
+    const int g = (tid >> 6) / W;
+    while (mask) {
+        const int first = __builtin_ctzll(mask);
+        int mine = -1;
+#pragma unroll
+        for (int r = 0; r < NG; r++) {
+            if (mask) {
+                const int i = __builtin_ctzll(mask);
+                mask &= mask - 1;
+                if (r == g) mine = i;
+            }
+        }
+        const int ic = mine < 0 ? first : mine;
+        const uint32_t rt = (uint32_t)__shfl(q.tile, ic, 64), rs = (uint32_t)__shfl(q.s, ic, 64);
+        const int rl = mine < 0 ? 0 : __shfl(q.len, ic, 64);
+        group_sort_run<1, W>(sd + g * 64 * W, keys + rs, vals + rs, vcopy ? vcopy + rs : nullptr, nullptr,
+                             (uint64_t)rt << 32, rl, tid - g * 64 * W);
+        __syncthreads();  // sd is reused by the next round
     }
 }
 
+// two workgroups per CU: 64 VGPRs at most
+__global__ __launch_bounds__(kTsThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_tile_sort(
+    const uint32_t* __restrict__ ranges, int tiles, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+    uint64_t* __restrict__ spare, uint32_t* __restrict__ vcopy) {
+    __shared__ uint64_t sd[kTsChunk];
+    __shared__ int lt_tile[kTsWaves], lt_s[kTsWaves], lt_len[kTsWaves];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    // wavefront w takes a tile of the w-th band of gridDim.x tiles, at an
+    // offset that moves by a fixed stride from band to band
+    const int G = (int)gridDim.x;
+    const int t = w * G + (int)(((int64_t)blockIdx.x + (int64_t)w * (G * 5 / 8 + 1)) % G);
+    uint32_t s = 0;
+    int L = 0;
+    if (t < tiles) {
+        s = ranges[2 * t];
+        L = (int)(ranges[2 * t + 1] - s);
+    }
+    if (L > kTsShort) {  // sorted below, by the workgroup
+        if (lane == 0) {
+            lt_tile[w] = t;
+            lt_s[w] = (int)s;
+            lt_len[w] = L;
+        }
+    } else {
+        if (lane == 0) lt_tile[w] = -1;
+        const uint64_t tbits = (uint64_t)(uint32_t)t << 32;
+        uint64_t* kr = keys + s;
+        uint32_t* vr = vals + s;
+        uint32_t* vc = vcopy ? vcopy + s : nullptr;
+        if (L == 1) {  // in place; only its value copy is due
+            if (vc && lane == 0) vc[0] = vr[0];
+        } else if (L > 1) {
+            if (L <= 16) wave_sort_run<1, 16>(kr, vr, vc, tbits, L, lane);
+            else if (L <= 32) wave_sort_run<1, 32>(kr, vr, vc, tbits, L, lane);
+            else if (L <= 64) wave_sort_run<1>(kr, vr, vc, tbits, L, lane);
+            else if (L <= 128) wave_sort_run<2>(kr, vr, vc, tbits, L, lane);
+            else wave_sort_run<4>(kr, vr, vc, tbits, L, lane);
+        }
+    }
+    __syncthreads();
+    // the long runs, from the lists in LDS read once into lanes 0..15:
+    // runs longer than kTsHalf one at a time with the whole workgroup, the
+    // others two at a time on the two halves of the workgroup (a network of
+    // kTsHalf entries each)
+    const int li = lane & (kTsWaves - 1);
+    const LongRuns q{lt_tile[li], lt_s[li], lt_len[li]};
+    const uint64_t has = __ballot(lane < kTsWaves && q.tile >= 0);
+    const uint64_t whole0 = has & ~__ballot(q.len <= kTsHalf);
+    uint64_t whole = whole0;
+    while (whole) {
+        const int i = __builtin_ctzll(whole);
+        whole &= whole - 1;
+        sort_long_run(sd, (uint32_t)__shfl(q.tile, i, 64), (uint32_t)__shfl(q.s, i, 64), __shfl(q.len, i, 64), keys,
+                      vals, spare, vcopy, tid);
+        __syncthreads();  // sd is reused by the next run
+    }
+    sort_in_groups<kTsWaves / 2>(has & ~whole0, q, sd, keys, vals, vcopy, tid);
+}
+
 void launch_tile_depth_sort(hipStream_t st, const uint32_t* ranges, int tiles, uint64_t* keys, uint32_t* vals,
-                            uint64_t* spare, uint32_t* vcopy, uint32_t* long_count, uint32_t* long_list) {
+                            uint64_t* spare, uint32_t* vcopy) {
     if (tiles <= 0) return;
-    hipLaunchKernelGGL(k_tile_sort_wave, dim3((unsigned)tiles), dim3(64), 0, st, ranges, keys, vals, vcopy,
-                       long_count, long_list);
-    const unsigned grid = (unsigned)(tiles < kTileSortGroups ? tiles : kTileSortGroups);
-    hipLaunchKernelGGL(k_tile_sort_group, dim3(grid), dim3(kTileSortThreads), 0, st, ranges, keys, vals, spare, vcopy,
-                       (const uint32_t*)long_count, (const uint32_t*)long_list);
+    const unsigned grid = (unsigned)((tiles + kTsWaves - 1) / kTsWaves);
+    hipLaunchKernelGGL(k_tile_sort, dim3(grid), dim3(kTsThreads), 0, st, ranges, tiles, keys, vals, spare, vcopy);
 }
 
 }  // namespace dgs

@@ -34,7 +34,8 @@ def rs():
 def crowded_tile_scene(n=6000, seed=5):
     """n small cells in front of a 32 x 16 image (two tiles), most of them
     covering tile 0, half of them at one depth: runs longer than a
-    workgroup sorts in LDS, with thousands of exact depth ties."""
+    workgroup sorts in registers (2,048 entries), with thousands of exact
+    depth ties."""
     rng = np.random.default_rng(seed)
     s = scenes.make_tiny_scene(seed, n_cells=n, K=2)
     z = np.where(rng.random(n) < 0.5, 3.0, rng.uniform(2.0, 4.0, n)).astype(np.float32)
@@ -90,7 +91,7 @@ def test_both_orders_give_the_oracle_lists(rs, case):
     # 8160 tiles), global for per-Gaussian lists and for small images
     assert passes["auto"] == passes["per_tile" if case.startswith("mid") else "global"], (case, passes)
     if case == "crowded":
-        assert int((oranges[:, 1] - oranges[:, 0]).max()) > 4096  # the chunked-merge runs were exercised
+        assert int((oranges[:, 1] - oranges[:, 0]).max()) > 4096  # chunks merged over two rounds
     for k in ("color", "D", "T", "last"):
         assert torch.equal(images["per_tile"][k], images["global"][k]), (case, k)
         assert torch.equal(images["auto"][k], images["global"][k]), (case, k)
