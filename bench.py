@@ -48,14 +48,26 @@ FLOP_DUPLEX_MEMBER = 11
 FLOP_DUPLEX_CELL = 10
 FLOP_ALPHA_HIT = 9
 
-def sort_traffic(prims, keys, tiles):
-    """Algorithmic bytes of the two-stage sort: depth keys written (key and
-    value, 8 B per primitive), four 8-bit passes over them (16 B read and
-    written per primitive and pass), and the passes over the (tile, depth)
-    keys on their tile bits (u64 key + u32 value read and written: 24 B per
-    key and pass)."""
-    tile_passes = (max(1, (tiles - 1).bit_length()) + 7) // 8
-    return prims * (8 + 4 * 16) + keys * 24 * tile_passes
+def tile_sort_passes(tiles):
+    return (max(1, (tiles - 1).bit_length()) + 7) // 8
+
+
+def sort_traffic(prims, keys, tiles, per_tile):
+    """Algorithmic bytes of the sort: the passes over the (tile, depth) keys
+    on their tile bits (u64 key + u32 value read and written: 24 B per key
+    and pass), and either the depth order of the primitives before them --
+    depth keys written (key and value, 8 B per primitive) and four 8-bit
+    passes over them (16 B read and written per primitive and pass) -- or,
+    with the per-tile order, the sort of each tile's run after them (24 B
+    per key)."""
+    tile_bytes = keys * 24 * tile_sort_passes(tiles)
+    return tile_bytes + (keys * 24 if per_tile else prims * (8 + 4 * 16))
+
+
+def sort_stage_ms(st):
+    """The sort's stages: depth order of the primitives, tile sort, per-tile
+    depth order (one of the depth stages is empty)."""
+    return st["depth_sort"] + st["tile_sort"] + st["tile_depth_order"]
 
 
 # algorithmic bytes of the Gaussian projection, per projected Gaussian:
@@ -584,13 +596,15 @@ def main():
         return {k: v / nfr for k, v in zip(capi.STAGE_NAMES, ms)}
 
     def counters(mode, idx):
-        tot = dict(n_val=0, n_rendered=0, n_box=0, n_cell_hits=0, n_cell_pixels=0, keys=0, projected=0)
+        tot = dict(n_val=0, n_rendered=0, n_box=0, n_cell_hits=0, n_cell_pixels=0, keys=0, projected=0,
+                   per_tile=0)
         for i in idx:
             r.render(ds, cams[i], out=out, mode=mode, stats=True)
             s = r.stats()
             for k in ("n_val", "n_rendered", "n_box", "n_cell_hits", "n_cell_pixels"):
                 tot[k] += s[k]
             tot["keys"] += s["num_keys"]
+            tot["per_tile"] += s["sort_passes"] == tile_sort_passes(TILES)  # no depth-sort passes
             if mode == "duplex":
                 _, _, nt = r.read_prims(ds.N)
                 tot["projected"] += int((nt > 0).sum().item()) * ds.K
@@ -623,11 +637,11 @@ def main():
                  "stages_ms": {k: round(v, 4) for k, v in st_alpha.items()},
                  "keys_mean": float(np.mean(keys_alpha)),
                  "composite_tflops": round(flops_a / (comp_a * 1e-3) / 1e12, 3),
-                 "sort_ms": round(st_alpha["depth_sort"] + st_alpha["tile_sort"], 4),
-                 "sort_keys_per_s": round(cnt_a["keys"] / ((st_alpha["depth_sort"] + st_alpha["tile_sort"]) * 1e-3), 1),
-                 "sort_hbm_frac": round(sort_traffic(ds.M, cnt_a["keys"], TILES)
-                                        / ((st_alpha["depth_sort"] + st_alpha["tile_sort"]) * 1e-3)
-                                        / (PEAK_HBM_GBS * 1e9), 4)}
+                 "sort_ms": round(sort_stage_ms(st_alpha), 4),
+                 "sort_keys_per_s": round(cnt_a["keys"] / (sort_stage_ms(st_alpha) * 1e-3), 1),
+                 "sort_hbm_frac": round(sort_traffic(ds.M, cnt_a["keys"], TILES, cnt_a["per_tile"] > 0.5)
+                                        / (sort_stage_ms(st_alpha) * 1e-3) / (PEAK_HBM_GBS * 1e9), 4),
+                 "list_order": "per_tile" if cnt_a["per_tile"] > 0.5 else "global"}
 
     for rr, _, _ in flight:  # the later legs run on their own streams
         rr.close()
@@ -706,10 +720,11 @@ def main():
         "stages_ms": {k: round(v, 4) for k, v in st_dup.items()},
         "keys_mean": float(np.mean(keys_dup)),
         "key_reduction_vs_alpha": None if alpha is None else round(1 - np.mean(keys_dup) / alpha["keys_mean"], 4),
-        "sort_ms": round(st_dup["depth_sort"] + st_dup["tile_sort"], 4),
-        "sort_keys_per_s": round(cnt["keys"] / ((st_dup["depth_sort"] + st_dup["tile_sort"]) * 1e-3), 1),
-        "sort_hbm_frac": round(sort_traffic(ds.N, cnt["keys"], TILES) / ((st_dup["depth_sort"] + st_dup["tile_sort"]) * 1e-3)
-                               / (PEAK_HBM_GBS * 1e9), 4),
+        "sort_ms": round(sort_stage_ms(st_dup), 4),
+        "sort_keys_per_s": round(cnt["keys"] / (sort_stage_ms(st_dup) * 1e-3), 1),
+        "sort_hbm_frac": round(sort_traffic(ds.N, cnt["keys"], TILES, cnt["per_tile"] > 0.5)
+                               / (sort_stage_ms(st_dup) * 1e-3) / (PEAK_HBM_GBS * 1e9), 4),
+        "list_order": "per_tile" if cnt["per_tile"] > 0.5 else "global",
         "projection_hbm_gbs": round(proj_gbs, 1),
         "projection_hbm_frac": round(proj_gbs / PEAK_HBM_GBS, 4),
         "termination_ratio": round(1 - cnt["n_rendered"] / max(cnt["n_val"], 1), 4),

@@ -199,8 +199,11 @@ dgs_status dgs_set_overlap(dgs_ctx ctx, int32_t enable);
  *     stably sorted on the tile bits, and each tile's run is then sorted by
  *     (depth, id) on its own (fast when the lists are short);
  *   DGS_LIST_ORDER_AUTO (default): per tile for per-cell lists (Duplex,
- *     LC-WSR) when the key capacity is at most 256 keys per screen tile,
- *     else global (always for DGS_MODE_ALPHA).
+ *     LC-WSR) when the context's last such frame had at most 128 keys per
+ *     screen tile (the device leaves that count in pinned host memory as
+ *     the frame's lists are built; before any such frame: when the key
+ *     capacity is at most 256 keys per tile), else global (always for
+ *     DGS_MODE_ALPHA).
  * The setting holds for the context's later frames; it changes no result.
  * Other values: DGS_ERR_INVALID_ARG. */
 enum { DGS_LIST_ORDER_AUTO = 0, DGS_LIST_ORDER_PER_TILE = 1, DGS_LIST_ORDER_GLOBAL = 2 };
@@ -341,10 +344,11 @@ dgs_status dgs_read_decoded(dgs_ctx ctx, float* means, float* scales, float* rot
  * context stream at the boundaries of its stages (and runs all of a frame on
  * that stream, so the stages do not overlap):
  *   0 cell preprocess (or nothing in alpha mode), 1 Gaussian projection,
- *   2 depth sort of the primitives, 3 scan + key emission, 4 radix sort of
- *   the keys on their tile bits, 5 tile ranges + compositor work queue,
- *   6 the compositor kernel alone. */
-#define DGS_NUM_STAGES 7
+ *   2 depth sort of the primitives (empty with the per-tile list order),
+ *   3 scan + key emission, 4 radix sort of the keys on their tile bits,
+ *   5 tile ranges, 6 per-tile depth order (empty with the global list
+ *   order), 7 compositor work queue, 8 the compositor kernel alone. */
+#define DGS_NUM_STAGES 9
 dgs_status dgs_set_timing(dgs_ctx ctx, int32_t enable);
 
 /* Synchronises; writes the summed milliseconds of each stage over the renders

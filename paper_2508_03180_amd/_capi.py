@@ -149,9 +149,9 @@ _SIGS = {
     "dgs_server_destroy": (C.c_int, [dgs_server]),
 }
 
-DGS_NUM_STAGES = 7
-STAGE_NAMES = ["cell_preprocess", "gauss_project", "depth_sort", "scan_emit", "tile_sort", "tile_ranges_queue",
-               "composite"]
+DGS_NUM_STAGES = 9
+STAGE_NAMES = ["cell_preprocess", "gauss_project", "depth_sort", "scan_emit", "tile_sort", "tile_ranges",
+               "tile_depth_order", "work_queue", "composite"]
 
 _lib = None
 

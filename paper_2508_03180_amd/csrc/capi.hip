@@ -415,9 +415,15 @@ dgs_status dgs_create(int device, void* hip_stream, dgs_ctx* out) {
         hipMalloc((void**)&c->misc, 16 * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc((void**)&c->dev_err, sizeof(int)) != hipSuccess ||
         hipMalloc((void**)&c->counters, 5 * sizeof(unsigned long long)) != hipSuccess ||
-        hipMalloc((void**)&c->frame, sizeof(FrameK)) != hipSuccess) {
+        hipMalloc((void**)&c->frame, sizeof(FrameK)) != hipSuccess ||
+        hipHostMalloc((void**)&c->load_host, sizeof(uint64_t), hipHostMallocMapped) != hipSuccess) {
         dgs_destroy(c);
         return DGS_ERR_OOM;
+    }
+    *c->load_host = 0;
+    if (hipHostGetDevicePointer((void**)&c->load_dev, c->load_host, 0) != hipSuccess) {
+        dgs_destroy(c);
+        return DGS_ERR_DEVICE;
     }
     // the frame's second stream is created by the first frame that uses it
     // (ensure_aux), so contexts that never overlap inside a frame hold one
@@ -452,6 +458,7 @@ dgs_status dgs_destroy(dgs_ctx c) {
                     c->hist, c->misc, c->dev_err, c->counters, c->frame};
     for (void* p : ptrs)
         if (p) hipFree(p);
+    if (c->load_host) hipHostFree(c->load_host);
     delete c;
     return DGS_OK;
 }
@@ -578,18 +585,23 @@ dgs_status dgs_read_decoded(dgs_ctx c, float* means, float* scales, float* rots,
 }  // extern "C"
 
 // Per-cell tile lists (Duplex, LC-WSR) are put in depth order per tile
-// (launch_tile_depth_sort) when the key buffer holds at most this many keys
-// per tile on average: cells are few and their lists short, so sorting the
-// runs costs less than the depth sort of the cells.  Per-Gaussian lists are
-// several times longer per tile, with many runs past one wavefront's 256
-// entries: there the depth sort of the primitives, whose cost does not grow
-// with the lists, is cheaper.
-constexpr int64_t kPerTileOrderKeysPerTile = 256;
+// (launch_tile_depth_sort) when the context's last cell frame had at most
+// this many keys per tile on average (before any, when the key buffer holds
+// at most twice as many): cells are few and their lists short, so sorting
+// the runs costs less than the depth sort of the cells.  Per-Gaussian lists
+// are several times longer per tile, with many runs past one wavefront's
+// 256 entries: there the depth sort of the primitives, whose cost does not
+// grow with the lists, is cheaper.
+constexpr int64_t kPerTileOrderKeysPerTile = 128;
 
 static bool per_tile_order(dgs_ctx c, int64_t tiles, bool cells) {
     if (c->list_order == DGS_LIST_ORDER_PER_TILE) return true;
     if (c->list_order == DGS_LIST_ORDER_GLOBAL) return false;
-    return cells && c->cap_keys <= kPerTileOrderKeysPerTile * tiles;
+    if (!cells) return false;
+    const uint64_t load = __atomic_load_n(c->load_host, __ATOMIC_RELAXED);
+    const uint64_t lt = load >> 32, lk = load & 0xffffffffull;
+    if (lt) return lk <= (uint64_t)kPerTileOrderKeysPerTile * lt;
+    return c->cap_keys <= 2 * kPerTileOrderKeysPerTile * tiles;
 }
 
 // The context's second stream and its fork/join events, created on first
@@ -727,7 +739,9 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     uint64_t* skeys = in1 ? c->keys1 : c->keys0;
     uint32_t* svals = in1 ? c->vals1 : c->vals0;
     sm.mark(5);
-    launch_tile_ranges(q, skeys, c->misc + 0, cap, ranges, svals, save && !per_tile ? save->vals : nullptr);
+    launch_tile_ranges(q, skeys, c->misc + 0, cap, ranges, svals, save && !per_tile ? save->vals : nullptr,
+                       cells ? c->load_dev : nullptr, (uint32_t)tiles);
+    sm.mark(6);
     if (order_on_aux) {
         hipEventRecord(c->ev_ranges, q);
         hipStreamWaitEvent(c->aux, c->ev_ranges, 0);
@@ -737,6 +751,7 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     if (per_tile)
         launch_tile_depth_sort(q, ranges, tiles, skeys, svals, in1 ? c->keys0 : c->keys1,
                                save ? save->vals : nullptr);
+    sm.mark(7);
     CompositeArgs a;
     a.ranges = ranges;
     a.vals = svals;
@@ -757,14 +772,14 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     a.save = save != nullptr;
     if (!order_on_aux) launch_tile_order(q, ranges, tiles, cells ? kSplitLenCells : kSplitLenGauss, torder, queue);
     if (overlap) hipStreamWaitEvent(q, c->ev_join, 0);  // the projected members (and the work queue)
-    sm.mark(6);
+    sm.mark(8);
     if (mode == DGS_MODE_DUPLEX)
         launch_composite_duplex(q, a);
     else if (mode == DGS_MODE_LCWSR)
         launch_composite_lcwsr(q, a);
     else
         launch_composite_alpha(q, a);
-    sm.mark(7);
+    sm.mark(9);
     if (save) hipLaunchKernelGGL(k_frame_info, dim3(1), dim3(64), 0, q, c->misc, c->counters, save->info);
     c->cur_ranges = ranges;
     c->last_mode = mode;

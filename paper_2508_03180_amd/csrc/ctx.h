@@ -57,6 +57,12 @@ struct dgs_ctx_s {
     // overlap whole frames.
     bool two_streams = true;
     int list_order = DGS_LIST_ORDER_AUTO;  // how the tile lists get their depth order
+    // The last cell frame's load, tiles << 32 | keys (0: none yet), written
+    // by the device into pinned host memory (load_dev: its device address)
+    // as the frame's tile ranges are built; read by the next frame's choice
+    // of list order.
+    uint64_t* load_host = nullptr;
+    uint64_t* load_dev = nullptr;
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipEvent_t ev_ranges = nullptr;  // the tile ranges are written (the work queue is built beside the per-tile sort)

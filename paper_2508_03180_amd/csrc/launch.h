@@ -91,8 +91,10 @@ void launch_emit_keys(hipStream_t st, int P, const uint32_t* order, const uint32
 void launch_tile_depth_sort(hipStream_t st, const uint32_t* ranges, int tiles, uint64_t* keys, uint32_t* vals,
                             uint64_t* spare, uint32_t* vcopy);
 
+// load (nullable, pinned host memory): receives tiles << 32 | key count.
 void launch_tile_ranges(hipStream_t st, const uint64_t* keys, const uint32_t* n_ptr, uint32_t cap,
-                        uint32_t* ranges, const uint32_t* vin = nullptr, uint32_t* vout = nullptr);
+                        uint32_t* ranges, const uint32_t* vin = nullptr, uint32_t* vout = nullptr,
+                        uint64_t* load = nullptr, uint32_t tiles = 0);
 
 // Onesweep LSD radix sort of (u64 key, u32 value) pairs on key bits
 // [first_bit, first_bit + bits).  The count is read on the device from

@@ -333,8 +333,11 @@ void launch_emit_keys(hipStream_t st, int P, const uint32_t* order, const uint32
 __global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t* __restrict__ keys,
                                                      const uint32_t* __restrict__ n_ptr, uint32_t cap,
                                                      uint32_t* __restrict__ ranges,
-                                                     const uint32_t* __restrict__ vin, uint32_t* __restrict__ vout) {
+                                                     const uint32_t* __restrict__ vin, uint32_t* __restrict__ vout,
+                                                     uint64_t* load, uint32_t tiles) {
     uint32_t n = *n_ptr;
+    if (load && blockIdx.x == 0 && threadIdx.x == 0)  // the frame's load, for the host (pinned memory)
+        __hip_atomic_store(load, ((uint64_t)tiles << 32) | n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     if (n > cap) n = cap;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         uint32_t t = (uint32_t)(keys[i] >> 32);
@@ -345,11 +348,11 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t* __restrict_
 }
 
 void launch_tile_ranges(hipStream_t st, const uint64_t* keys, const uint32_t* n_ptr, uint32_t cap,
-                        uint32_t* ranges, const uint32_t* vin, uint32_t* vout) {
+                        uint32_t* ranges, const uint32_t* vin, uint32_t* vout, uint64_t* load, uint32_t tiles) {
     unsigned grid = (unsigned)((cap + 255) / 256);
     if (grid > 2048) grid = 2048;
     if (grid == 0) grid = 1;
-    hipLaunchKernelGGL(k_tile_ranges, dim3(grid), dim3(256), 0, st, keys, n_ptr, cap, ranges, vin, vout);
+    hipLaunchKernelGGL(k_tile_ranges, dim3(grid), dim3(256), 0, st, keys, n_ptr, cap, ranges, vin, vout, load, tiles);
 }
 
 }  // namespace dgs
