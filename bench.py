@@ -77,10 +77,10 @@ BYTES_PROJECT_SH3 = 12 + 12 + 16 + 4 + 192 + 48 + 8
 
 # HBM traffic of one Duplex compositor launch on this workload, from two
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) scaled by a 1 GiB copy
-# kernel's reading (profiles/composite_traffic_1080p_1M_pmc.md): 204.474 MB
-# read + 51.056 MB written.  Valid for the compositor sources it was taken
+# kernel's reading (profiles/composite_traffic_1080p_1M_pmc.md): 201.868 MB
+# read + 51.058 MB written.  Valid for the compositor sources it was taken
 # on; reported as null once one of them changes.
-COMPOSITE_TRAFFIC_BYTES = 204.474e6 + 51.056e6
+COMPOSITE_TRAFFIC_BYTES = 201.868e6 + 51.058e6
 COMPOSITE_TRAFFIC_SOURCES = {
     "paper_2508_03180_amd/csrc/composite.hip": "880a5e30c6876b272e088d548c1ed6b585834f2d60fda517b485f0fe3ca3a799",
     "paper_2508_03180_amd/csrc/common.h": "ba55af4abcd758f5c95eae4b782ec45303dc4fdba45ac22ae5f538575a823139",
