@@ -347,7 +347,9 @@ dgs_status dgs_read_decoded(dgs_ctx ctx, float* means, float* scales, float* rot
  *   2 depth sort of the primitives (empty with the per-tile list order),
  *   3 scan + key emission, 4 radix sort of the keys on their tile bits,
  *   5 tile ranges, 6 per-tile depth order (empty with the global list
- *   order), 7 compositor work queue, 8 the compositor kernel alone. */
+ *   order; it also builds the compositor's work queue), 7 compositor work
+ *   queue (empty with the per-tile list order), 8 the compositor kernel
+ *   alone. */
 #define DGS_NUM_STAGES 9
 dgs_status dgs_set_timing(dgs_ctx ctx, int32_t enable);
 

@@ -446,7 +446,6 @@ dgs_status dgs_destroy(dgs_ctx c) {
     }
     if (c->ev_fork) hipEventDestroy(c->ev_fork);
     if (c->ev_join) hipEventDestroy(c->ev_join);
-    if (c->ev_ranges) hipEventDestroy(c->ev_ranges);
     for (auto& a : c->events)
         for (auto& e : a) hipEventDestroy(e);
     for (dgs_frame_s* f : c->frames) free_frame(f);
@@ -617,8 +616,7 @@ static bool ensure_aux(dgs_ctx c) {
         return false;
     }
     if (hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_ranges, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
         if (c->ev_fork) hipEventDestroy(c->ev_fork);
         if (c->ev_join) hipEventDestroy(c->ev_join);
         hipStreamDestroy(c->aux);
@@ -660,7 +658,6 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     // each tile's run after the tile sort (the same order); with the second
     // stream, the work queue is then built there beside the per-tile sort
     const bool per_tile = per_tile_order(c, tiles, cells);
-    const bool order_on_aux = overlap && per_tile;
     // buffers the backward replays: a saved frame's own, else the context's
     float* cell_v = save ? save->cell_v : c->cell_v;
     GRec* recs = save ? save->recs : c->recs;
@@ -708,7 +705,7 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
         // Gaussian g is g / K); ragged cells: every Gaussian is projected
         launch_gauss_project(pq, M, K, s->means, s->scales, s->rots, s->opacities, s->sh, s->sh_degree, c->frame,
                              s->cell_offsets ? nullptr : c->p_ntiles, recs, c->grect, nullptr, nullptr, overlap);
-        if (overlap && !order_on_aux) hipEventRecord(c->ev_join, c->aux);
+        if (overlap) hipEventRecord(c->ev_join, c->aux);
     } else {
         if (nn) launch_decode(q, decode_args(c, *nn, nullptr));
         sm.mark(1);
@@ -742,15 +739,10 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     launch_tile_ranges(q, skeys, c->misc + 0, cap, ranges, svals, save && !per_tile ? save->vals : nullptr,
                        cells ? c->load_dev : nullptr, (uint32_t)tiles);
     sm.mark(6);
-    if (order_on_aux) {
-        hipEventRecord(c->ev_ranges, q);
-        hipStreamWaitEvent(c->aux, c->ev_ranges, 0);
-        launch_tile_order(c->aux, ranges, tiles, kSplitLenCells, torder, queue);
-        hipEventRecord(c->ev_join, c->aux);
-    }
+    // per tile: the same launch also builds the work queue
     if (per_tile)
         launch_tile_depth_sort(q, ranges, tiles, skeys, svals, in1 ? c->keys0 : c->keys1,
-                               save ? save->vals : nullptr);
+                               save ? save->vals : nullptr, cells ? kSplitLenCells : kSplitLenGauss, torder, queue);
     sm.mark(7);
     CompositeArgs a;
     a.ranges = ranges;
@@ -770,8 +762,8 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     a.order = torder;
     a.queue = queue;
     a.save = save != nullptr;
-    if (!order_on_aux) launch_tile_order(q, ranges, tiles, cells ? kSplitLenCells : kSplitLenGauss, torder, queue);
-    if (overlap) hipStreamWaitEvent(q, c->ev_join, 0);  // the projected members (and the work queue)
+    if (!per_tile) launch_tile_order(q, ranges, tiles, cells ? kSplitLenCells : kSplitLenGauss, torder, queue);
+    if (overlap) hipStreamWaitEvent(q, c->ev_join, 0);  // the projected members
     sm.mark(8);
     if (mode == DGS_MODE_DUPLEX)
         launch_composite_duplex(q, a);

@@ -65,7 +65,6 @@ struct dgs_ctx_s {
     uint64_t* load_dev = nullptr;
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    hipEvent_t ev_ranges = nullptr;  // the tile ranges are written (the work queue is built beside the per-tile sort)
     int64_t cap_prims = 0, cap_gauss = 0, cap_keys = 0, cap_tiles = 0;
     uint64_t generation = 0;  // bumped whenever a workspace buffer moves (captured graphs go stale)
     uint32_t *p_depth = nullptr, *p_ntiles = nullptr, *p_offsets = nullptr;

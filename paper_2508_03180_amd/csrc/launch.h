@@ -87,9 +87,10 @@ void launch_emit_keys(hipStream_t st, int P, const uint32_t* order, const uint32
 // Per-tile depth order: each tile's run of the tile-sorted keys (emitted in
 // primitive-id order) sorted by (depth bits, id) in place; values also into
 // vcopy when set; spare: a free u64 buffer of the key capacity (used by runs
-// longer than what one workgroup sorts in registers).
+// longer than what one workgroup sorts in registers).  The same launch
+// builds the compositor's work queue (as launch_tile_order).
 void launch_tile_depth_sort(hipStream_t st, const uint32_t* ranges, int tiles, uint64_t* keys, uint32_t* vals,
-                            uint64_t* spare, uint32_t* vcopy);
+                            uint64_t* spare, uint32_t* vcopy, uint32_t split_len, uint32_t* order, uint32_t* queue);
 
 // load (nullable, pinned host memory): receives tiles << 32 | key count.
 void launch_tile_ranges(hipStream_t st, const uint64_t* keys, const uint32_t* n_ptr, uint32_t cap,

@@ -13,6 +13,7 @@
 // host round trip.
 #include "common.h"
 #include "launch.h"
+#include "order.h"
 
 namespace dgs {
 
@@ -574,16 +575,28 @@ __device__ __forceinline__ void sort_in_groups(uint64_t mask, const LongRuns& q,
     }
 }
 
-// two workgroups per CU: 64 VGPRs at most
+// The work queue's LDS (order.h) or the sort's exchange buffer.
+constexpr int kTsSharedBytes = kOrderClasses * 4 + 1024 * 4 > kTsChunk * 8 ? kOrderClasses * 4 + 1024 * 4 : kTsChunk * 8;
+
+// two workgroups per CU: 64 VGPRs at most.  The last workgroup builds the
+// compositor's work queue (it needs the tile ranges only) while the others
+// sort the runs.
 __global__ __launch_bounds__(kTsThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_tile_sort(
     const uint32_t* __restrict__ ranges, int tiles, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
-    uint64_t* __restrict__ spare, uint32_t* __restrict__ vcopy) {
-    __shared__ uint64_t sd[kTsChunk];
+    uint64_t* __restrict__ spare, uint32_t* __restrict__ vcopy, uint32_t split_len, uint32_t* __restrict__ order,
+    uint32_t* __restrict__ queue) {
+    __shared__ __align__(16) unsigned char smem[kTsSharedBytes];
     __shared__ int lt_tile[kTsWaves], lt_s[kTsWaves], lt_len[kTsWaves];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    // wavefront w takes a tile of the w-th band of gridDim.x tiles, at an
-    // offset that moves by a fixed stride from band to band
-    const int G = (int)gridDim.x;
+    const int G = (int)gridDim.x - 1;  // workgroups sorting runs
+    if ((int)blockIdx.x == G) {
+        uint32_t* s_cnt = reinterpret_cast<uint32_t*>(smem);
+        build_work_queue(ranges, tiles, split_len, order, queue, s_cnt, s_cnt + kOrderClasses, tid);
+        return;
+    }
+    uint64_t* sd = reinterpret_cast<uint64_t*>(smem);
+    // wavefront w takes a tile of the w-th band of G tiles, at an offset
+    // that moves by a fixed stride from band to band
     const int t = w * G + (int)(((int64_t)blockIdx.x + (int64_t)w * (G * 5 / 8 + 1)) % G);
     uint32_t s = 0;
     int L = 0;
@@ -634,10 +647,11 @@ __global__ __launch_bounds__(kTsThreads) __attribute__((amdgpu_waves_per_eu(8)))
 }
 
 void launch_tile_depth_sort(hipStream_t st, const uint32_t* ranges, int tiles, uint64_t* keys, uint32_t* vals,
-                            uint64_t* spare, uint32_t* vcopy) {
+                            uint64_t* spare, uint32_t* vcopy, uint32_t split_len, uint32_t* order, uint32_t* queue) {
     if (tiles <= 0) return;
-    const unsigned grid = (unsigned)((tiles + kTsWaves - 1) / kTsWaves);
-    hipLaunchKernelGGL(k_tile_sort, dim3(grid), dim3(kTsThreads), 0, st, ranges, tiles, keys, vals, spare, vcopy);
+    const unsigned grid = (unsigned)((tiles + kTsWaves - 1) / kTsWaves) + 1;  // + the work queue's
+    hipLaunchKernelGGL(k_tile_sort, dim3(grid), dim3(kTsThreads), 0, st, ranges, tiles, keys, vals, spare, vcopy,
+                       split_len, order, queue);
 }
 
 }  // namespace dgs
