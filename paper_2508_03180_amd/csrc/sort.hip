@@ -309,8 +309,10 @@ bool launch_radix_sort32(hipStream_t st, uint32_t* k0, uint32_t* v0, uint32_t* k
 // and the run's own key slots, each element's place being its index in its
 // half plus the number of smaller elements in the other half (binary
 // search).  Runs are written back in place: key = tile << 32 | depth bits,
-// value = id, the values also into vcopy when set.  Every helper is
-// inlined: the kernel makes no calls.
+// value = id, the values also into vcopy when set.  One more workgroup of
+// the launch builds the compositor's work queue from the tile ranges
+// (build_work_queue, order.h) meanwhile.  Every helper is inlined: the
+// kernel makes no calls.
 constexpr int kTsWaves = 16;
 constexpr int kTsThreads = 64 * kTsWaves;
 constexpr int kTsShort = 256;              // longest run one wavefront sorts
@@ -575,8 +577,10 @@ __device__ __forceinline__ void sort_in_groups(uint64_t mask, const LongRuns& q,
     }
 }
 
-// The work queue's LDS (order.h) or the sort's exchange buffer.
-constexpr int kTsSharedBytes = kOrderClasses * 4 + 1024 * 4 > kTsChunk * 8 ? kOrderClasses * 4 + 1024 * 4 : kTsChunk * 8;
+// A workgroup's LDS: the work queue's counts and partial sums (order.h), or
+// the sort's exchange buffer.
+constexpr int kQueueBytes = (kOrderClasses + 1024) * 4;
+constexpr int kTsSharedBytes = kQueueBytes > kTsChunk * 8 ? kQueueBytes : kTsChunk * 8;
 
 // two workgroups per CU: 64 VGPRs at most.  The last workgroup builds the
 // compositor's work queue (it needs the tile ranges only) while the others
