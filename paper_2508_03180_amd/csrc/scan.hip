@@ -339,11 +339,17 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t* __restrict_
     if (load && blockIdx.x == 0 && threadIdx.x == 0)  // the frame's load, for the host (pinned memory)
         __hip_atomic_store(load, ((uint64_t)tiles << 32) | n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     if (n > cap) n = cap;
+    // the tile words of the neighbours (at clamped indexes) and the value
+    // are loaded at once, before any of them is compared
+    const uint32_t* tw = reinterpret_cast<const uint32_t*>(keys) + 1;  // tile of key i: tw[2 i]
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        uint32_t t = (uint32_t)(keys[i] >> 32);
-        if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != t) ranges[2 * t] = i;
-        if (i == n - 1 || (uint32_t)(keys[i + 1] >> 32) != t) ranges[2 * t + 1] = i + 1;
-        if (vout) vout[i] = vin[i];
+        const uint32_t t = tw[2 * (size_t)i];
+        const uint32_t tp = tw[2 * (size_t)(i > 0 ? i - 1 : 0)];
+        const uint32_t tn = tw[2 * (size_t)(i + 1 < n ? i + 1 : i)];
+        const uint32_t v = vout ? vin[i] : 0u;
+        if (i == 0 || tp != t) ranges[2 * t] = i;
+        if (i == n - 1 || tn != t) ranges[2 * t + 1] = i + 1;
+        if (vout) vout[i] = v;
     }
 }
 
