@@ -333,9 +333,13 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
             // w alpha go straight into N and D (no per-cell sums A, B); in the
             // Duplex walk al below is v alpha and w alpha = T (v alpha)
             float wj[NS], P[NS];
-            bool hc[NS];  // some member of this cell passed both gates at the pixel
+            // some member of this cell passed both gates at the pixel (0 / 1 in
+            // a vector register: a lane-mask bool carried through the member
+            // loop is merged with the exec mask by scalar instructions every
+            // iteration)
+            uint32_t hc[NS];
 #pragma unroll
-            for (int j = 0; j < NS; j++) { wj[j] = LC ? v : T[j]; P[j] = 1.0f; hc[j] = false; }
+            for (int j = 0; j < NS; j++) { wj[j] = LC ? v : T[j]; P[j] = 1.0f; hc[j] = 0u; }
             for (uint32_t rem = any; rem; rem &= rem - 1) {
                 const int k = __builtin_ctz(rem);
                 const RecView e = read_rec(lb, base + k);
@@ -374,7 +378,7 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
                     N2[j] = fmaf(wa, e.b, N2[j]);
                     D[j] += wa;
                     if constexpr (!LC) P[j] = fmaf(-P[j], al, P[j]);
-                    hc[j] = hc[j] | hit;
+                    hc[j] = hit ? 1u : hc[j];
                 }
             }
             // no branch: a pixel that no longer blends had threshold +inf in
@@ -384,13 +388,13 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
                 if (!mj[j]) continue;  // scalar: nothing of this cell in strip j
                 const int32_t idx = (int32_t)(pos + c - start + 1);
                 if constexpr (SAVE) {
-                    const bool rep = hc[j] && T[j] >= kMinReplayT;
+                    const bool rep = hc[j] != 0u && T[j] >= kMinReplayT;
                     rlast[j] = rep ? idx : rlast[j];
                     rT[j] = rep ? T[j] : rT[j];
                 }
                 if constexpr (!LC) T[j] *= P[j];
-                last[j] = hc[j] ? idx : last[j];
-                if (STATS) cn.cellhit += hc[j];
+                last[j] = hc[j] != 0u ? idx : last[j];
+                if (STATS) cn.cellhit += hc[j] != 0u;
             }
         }
         pos = next;
