@@ -157,17 +157,23 @@ __device__ inline RecView read_rec(uint32_t lb, int i) {
 
 // The frame's values the compositors use, loaded once per wavefront from the
 // device frame record (scalar registers; the kernel argument is left as is).
+// The output pointers are global-memory pointers: stored through generic
+// pointers, they became flat stores, which the compiler counts as possible
+// LDS accesses too, so every later wait for an LDS read had to wait for all
+// of them.
+typedef __attribute__((address_space(1))) float GFloat;
+typedef __attribute__((address_space(1))) int32_t GInt;
 struct FrameView {
     int TX, W, H;
     float eps, th, amax, bg0, bg1, bg2;
-    float* color;
-    float* D;
-    float* T;
-    int32_t* last;
-    float* sv_color;  // saved state of the frame for its backward (SAVE walks only)
-    float* sv_D;
-    float* sv_T;
-    int32_t* sv_last;
+    GFloat* color;
+    GFloat* D;
+    GFloat* T;
+    GInt* last;
+    GFloat* sv_color;  // saved state of the frame for its backward (SAVE walks only)
+    GFloat* sv_D;
+    GFloat* sv_T;
+    GInt* sv_last;
 };
 
 __device__ inline FrameView frame_view(const FrameK* fr) {
@@ -181,14 +187,14 @@ __device__ inline FrameView frame_view(const FrameK* fr) {
     f.bg0 = fr->o.bg[0];
     f.bg1 = fr->o.bg[1];
     f.bg2 = fr->o.bg[2];
-    f.color = fr->color;
-    f.D = fr->D;
-    f.T = fr->T;
-    f.last = fr->last;
-    f.sv_color = fr->sv_color;
-    f.sv_D = fr->sv_D;
-    f.sv_T = fr->sv_T;
-    f.sv_last = fr->sv_last;
+    f.color = (GFloat*)fr->color;
+    f.D = (GFloat*)fr->D;
+    f.T = (GFloat*)fr->T;
+    f.last = (GInt*)fr->last;
+    f.sv_color = (GFloat*)fr->sv_color;
+    f.sv_D = (GFloat*)fr->sv_D;
+    f.sv_T = (GFloat*)fr->sv_T;
+    f.sv_last = (GInt*)fr->sv_last;
     return f;
 }
 
