@@ -249,6 +249,12 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
         inb[j] = px < f.W && py0 + 4 * j < f.H;
         thj[j] = inb[j] ? th : INFINITY;
     }
+    // the per-cell ballots below are ballots of single compares, combined
+    // with these as scalar masks (a ballot of a combination of lane masks
+    // is rebuilt through a vector register first)
+    uint64_t inbm[NS];  // strip j's pixels in the image
+#pragma unroll
+    for (int j = 0; j < NS; j++) inbm[j] = __ballot(inb[j]);
 
     Chunk q;
     if (start < end) load_cell_chunk<RAGGED>(a, start, end, lane, q);
@@ -305,13 +311,14 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
 #pragma unroll
             for (int j = 0; j < NS; j++) act[j] = LC ? inb[j] : inb[j] && !(T[j] < eps);
             if constexpr (!LC) {
-                bool anyact = false;
+                uint64_t am[NS], amall = 0;  // ballots of act
 #pragma unroll
                 for (int j = 0; j < NS; j++) {
                     thj[j] = act[j] ? thc : INFINITY;
-                    anyact = anyact || act[j];
+                    am[j] = __ballot(!(T[j] < eps)) & inbm[j];
+                    amall |= am[j];
                 }
-                if (!STATS && !__any(anyact)) {
+                if (!STATS && !amall) {
                     alive = false;
                     break;
                 }
@@ -322,13 +329,13 @@ __device__ inline void duplex_tile(const CompositeArgs& a, const FrameView& f, i
                     uint32_t live = 0;
 #pragma unroll
                     for (int j = 0; j < NS; j++) {
-                        const uint64_t am = __ballot(act[j]);
-                        if (am == __ballot(inb[j])) {  // every pixel of strip j still blends
+                        if (am[j] == inbm[j]) {  // every pixel of strip j still blends
                             live |= mj[j];
                             continue;
                         }
-                        const uint32_t ac = active_columns(am);
-                        mj[j] = (uint32_t)(__ballot(((rsm >> j) & 1u) && (rcols & ac)) >> base) & cm;
+                        // B[j]: the records touching strip j
+                        const uint32_t ac = active_columns(am[j]);
+                        mj[j] = (uint32_t)((__ballot((rcols & ac) != 0u) & B[j]) >> base) & cm;
                         live |= mj[j];
                     }
                     any = live;
@@ -451,6 +458,9 @@ __device__ inline void alpha_tile(const CompositeArgs& a, const FrameView& f, in
         T[j] = 1.0f; C0[j] = C1[j] = C2[j] = 0.0f; last[j] = 0;
         inb[j] = px < f.W && py0 + 4 * j < f.H;
     }
+    uint64_t inbm[NS];  // strip j's pixels in the image (ballots of single compares below)
+#pragma unroll
+    for (int j = 0; j < NS; j++) inbm[j] = __ballot(inb[j]);
     const uint32_t lb = lds_base(lds);
     Chunk q;
     if (start < end) load_gauss_chunk(a, start, end, lane, q);
@@ -475,17 +485,17 @@ __device__ inline void alpha_tile(const CompositeArgs& a, const FrameView& f, in
             // blending pixel, so dropping it changes no output)
             if (!STATS && ++since_check == 8) {
                 since_check = 0;
-                bool anyact = false;
-                uint64_t live = 0;
+                uint64_t amall = 0, live = 0;
 #pragma unroll
                 for (int j = 0; j < NS; j++) {
-                    const bool actj = inb[j] && !(T[j] < eps);
-                    anyact = anyact || actj;
-                    // the column ballot runs on every lane, outside the &&
-                    const uint32_t ac = active_columns(__ballot(actj));
-                    live |= __ballot(((rsm >> j) & 1u) && (rcols & ac));
+                    // every ballot runs on every lane; B[j]: the records
+                    // touching strip j
+                    const uint64_t am = __ballot(!(T[j] < eps)) & inbm[j];
+                    amall |= am;
+                    const uint32_t ac = active_columns(am);
+                    live |= __ballot((rcols & ac) != 0u) & B[j];
                 }
-                if (!__any(anyact)) {
+                if (!amall) {
                     alive = false;
                     break;
                 }
