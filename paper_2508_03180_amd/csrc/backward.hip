@@ -213,7 +213,8 @@ __device__ inline void duplex_tile_bwd(const BwdArgs& a, int tile, int s0, int l
             const uint32_t cm = RAGGED ? member_mask(lane_value(ch.cnt, c)) : kmask;
             const int p = lo_c + c;  // list position (0-based) of this cell
             uint32_t mj[NS], mm = 0;
-            bool act[NS], anyact = false;
+            bool act[NS];
+            uint64_t am[NS], amall = 0;  // ballots of act (ballots of single compares)
             float thj[NS];  // gate threshold, +inf where the pixel does not reach this cell
             const float v = __int_as_float(lane_value(__float_as_int(ch.vc), c));
             const float lv = fold_log2_weight(v);  // as the forward stages it
@@ -224,9 +225,10 @@ __device__ inline void duplex_tile_bwd(const BwdArgs& a, int tile, int s0, int l
                 mm |= mj[j];
                 act[j] = p < last[j];
                 thj[j] = act[j] ? thc : INFINITY;
-                anyact = anyact || act[j];
+                am[j] = __ballot(p < last[j]);
+                amall |= am[j];
             }
-            if (!mm || !__any(anyact)) continue;  // no member touches the owned rows / no pixel reaches the cell
+            if (!mm || !amall) continue;  // no member touches the owned rows / no pixel reaches the cell
             {
                 // drop the members whose box misses every pixel that reaches
                 // this cell: they change nothing there (the other pixels have
@@ -234,11 +236,11 @@ __device__ inline void duplex_tile_bwd(const BwdArgs& a, int tile, int s0, int l
                 uint32_t live = 0;
 #pragma unroll
                 for (int j = 0; j < NS; j++) {
-                    const uint64_t am = __ballot(act[j]);
-                    if (am != ~0ull) {
-                        uint32_t ac = (uint32_t)(am | (am >> 32));
+                    if (am[j] != ~0ull) {
+                        uint32_t ac = (uint32_t)(am[j] | (am[j] >> 32));
                         ac = (ac | (ac >> 16)) & 0xffffu;  // columns (lane & 15) with a pixel reaching the cell
-                        mj[j] = (uint32_t)(__ballot(((sm >> j) & 1u) && (rcols & ac)) >> base) & cm;
+                        // Bm[j]: the records touching strip j
+                        mj[j] = (uint32_t)((__ballot((rcols & ac) != 0u) & Bm[j]) >> base) & cm;
                     }
                     live |= mj[j];
                 }
