@@ -378,6 +378,12 @@ __global__ __launch_bounds__(256) void k_composite_bwd(BwdArgs a) {
         if (t >= nitems) break;
         const uint32_t item = a.order[t];
         const int tile = (int)(item >> 3), mode = (int)(item & 7u);
+        // half-tile items (the tiles with the longest lists, which set the
+        // kernel's span) issue ahead of whole-tile items on their SIMD
+        if (mode != 0)
+            __builtin_amdgcn_s_setprio(3);
+        else
+            __builtin_amdgcn_s_setprio(0);
         if (mode == 0)
             duplex_tile_bwd<4, RAGGED>(a, tile, 0, lane, lds);
         else
