@@ -416,11 +416,11 @@ dgs_status dgs_create(int device, void* hip_stream, dgs_ctx* out) {
         hipMalloc((void**)&c->dev_err, sizeof(int)) != hipSuccess ||
         hipMalloc((void**)&c->counters, 5 * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc((void**)&c->frame, sizeof(FrameK)) != hipSuccess ||
-        hipHostMalloc((void**)&c->load_host, sizeof(uint64_t), hipHostMallocMapped) != hipSuccess) {
+        hipHostMalloc((void**)&c->load_host, 2 * sizeof(uint64_t), hipHostMallocMapped) != hipSuccess) {
         dgs_destroy(c);
         return DGS_ERR_OOM;
     }
-    *c->load_host = 0;
+    c->load_host[0] = c->load_host[1] = 0;
     if (hipHostGetDevicePointer((void**)&c->load_dev, c->load_host, 0) != hipSuccess) {
         dgs_destroy(c);
         return DGS_ERR_DEVICE;
@@ -584,23 +584,30 @@ dgs_status dgs_read_decoded(dgs_ctx c, float* means, float* scales, float* rots,
 }  // extern "C"
 
 // Per-cell tile lists (Duplex, LC-WSR) are put in depth order per tile
-// (launch_tile_depth_sort) when the context's last cell frame had at most
-// this many keys per tile on average (before any, when the key buffer holds
-// at most twice as many): cells are few and their lists short, so sorting
-// the runs costs less than the depth sort of the cells.  Per-Gaussian lists
-// are several times longer per tile, with many runs past one wavefront's
-// 256 entries: there the depth sort of the primitives, whose cost does not
-// grow with the lists, is cheaper.
-constexpr int64_t kPerTileOrderKeysPerTile = 128;
+// (launch_tile_depth_sort) when the context's last cell frame had at most 8
+// keys per cell, at most 1024 keys per tile on
+// average, and at most a tenth of its keys in runs of more than 2048
+// entries (which the per-tile sort handles by chunked merges in global
+// memory); before any cell frame, when the key buffer holds at most 256
+// keys per tile.  The per-tile sort's cost grows with the keys and their
+// run lengths, the depth sort's with the cells only.  Per-Gaussian lists
+// always take the depth sort of the primitives.
+constexpr uint64_t kPerTileOrderKeysPerCell = 8;
+constexpr int64_t kPerTileOrderMaxMean = 1024;      // keys per tile
+constexpr uint64_t kPerTileOrderLongShare = 10;     // at most 1 / this of the keys in long runs
+constexpr int64_t kPerTileOrderCapacity = 256;      // keys per tile, before any cell frame
 
 static bool per_tile_order(dgs_ctx c, int64_t tiles, bool cells) {
     if (c->list_order == DGS_LIST_ORDER_PER_TILE) return true;
     if (c->list_order == DGS_LIST_ORDER_GLOBAL) return false;
     if (!cells) return false;
     const uint64_t load = __atomic_load_n(c->load_host, __ATOMIC_RELAXED);
-    const uint64_t lt = load >> 32, lk = load & 0xffffffffull;
-    if (lt) return lk <= (uint64_t)kPerTileOrderKeysPerTile * lt;
-    return c->cap_keys <= 2 * kPerTileOrderKeysPerTile * tiles;
+    const uint64_t lng = __atomic_load_n(c->load_host + 1, __ATOMIC_RELAXED);
+    const uint64_t lt = load >> 32, lk = load & 0xffffffffull, lp = lng >> 32, ll = lng & 0xffffffffull;
+    if (lt)
+        return lk <= kPerTileOrderKeysPerCell * lp && lk <= (uint64_t)kPerTileOrderMaxMean * lt &&
+               kPerTileOrderLongShare * ll <= lk;
+    return c->cap_keys <= kPerTileOrderCapacity * tiles;
 }
 
 // The context's second stream and its fork/join events, created on first
@@ -742,7 +749,8 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     // per tile: the same launch also builds the work queue
     if (per_tile)
         launch_tile_depth_sort(q, ranges, tiles, skeys, svals, in1 ? c->keys0 : c->keys1,
-                               save ? save->vals : nullptr, cells ? kSplitLenCells : kSplitLenGauss, torder, queue);
+                               save ? save->vals : nullptr, cells ? kSplitLenCells : kSplitLenGauss, torder, queue,
+                               cells ? c->load_dev + 1 : nullptr, (uint32_t)P);
     sm.mark(7);
     CompositeArgs a;
     a.ranges = ranges;
@@ -762,7 +770,9 @@ dgs_status dgs_internal_render(dgs_ctx c, const dgs_scene* s, const dgs_camera* 
     a.order = torder;
     a.queue = queue;
     a.save = save != nullptr;
-    if (!per_tile) launch_tile_order(q, ranges, tiles, cells ? kSplitLenCells : kSplitLenGauss, torder, queue);
+    if (!per_tile)
+        launch_tile_order(q, ranges, tiles, cells ? kSplitLenCells : kSplitLenGauss, torder, queue,
+                          cells ? c->load_dev + 1 : nullptr, (uint32_t)P);
     if (overlap) hipStreamWaitEvent(q, c->ev_join, 0);  // the projected members
     sm.mark(8);
     if (mode == DGS_MODE_DUPLEX)

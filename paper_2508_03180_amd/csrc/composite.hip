@@ -609,10 +609,11 @@ __global__ __launch_bounds__(256) void k_composite(CompositeArgs a) {
 // Builds the work queue (build_work_queue, order.h) in one workgroup.
 __global__ __launch_bounds__(1024) void k_tile_order(const uint32_t* __restrict__ ranges, int ntiles,
                                                      uint32_t split_len, uint32_t* __restrict__ order,
-                                                     uint32_t* __restrict__ queue) {
+                                                     uint32_t* __restrict__ queue, uint64_t* long_stat,
+                                                     uint32_t prims) {
     __shared__ uint32_t s_cnt[kOrderClasses];
     __shared__ uint32_t s_part[1024];
-    build_work_queue(ranges, ntiles, split_len, order, queue, s_cnt, s_part, (int)threadIdx.x);
+    build_work_queue(ranges, ntiles, split_len, order, queue, s_cnt, s_part, (int)threadIdx.x, long_stat, prims);
 }
 
 static unsigned persistent_grid(int tiles) {
@@ -622,9 +623,10 @@ static unsigned persistent_grid(int tiles) {
 }
 
 void launch_tile_order(hipStream_t st, const uint32_t* ranges, int tiles, uint32_t split_len, uint32_t* order,
-                       uint32_t* queue) {
+                       uint32_t* queue, uint64_t* long_stat, uint32_t prims) {
     if (tiles <= 0) return;
-    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, st, ranges, tiles, split_len, order, queue);
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, st, ranges, tiles, split_len, order, queue, long_stat,
+                       prims);
 }
 
 template <int MODE, bool SAVE, bool RAGGED>

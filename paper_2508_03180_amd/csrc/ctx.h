@@ -57,10 +57,11 @@ struct dgs_ctx_s {
     // overlap whole frames.
     bool two_streams = true;
     int list_order = DGS_LIST_ORDER_AUTO;  // how the tile lists get their depth order
-    // The last cell frame's load, tiles << 32 | keys (0: none yet), written
-    // by the device into pinned host memory (load_dev: its device address)
-    // as the frame's tile ranges are built; read by the next frame's choice
-    // of list order.
+    // The last cell frame's load in pinned host memory (load_dev: its device
+    // address), written by the device and read by the next frame's choice of
+    // list order: [0] tiles << 32 | keys (0: none yet), as the frame's tile
+    // ranges are built; [1] its primitives << 32 | its keys in runs of more
+    // than 2048 entries, as its work queue is built.
     uint64_t* load_host = nullptr;
     uint64_t* load_dev = nullptr;
     hipStream_t aux = nullptr;

@@ -89,8 +89,10 @@ void launch_emit_keys(hipStream_t st, int P, const uint32_t* order, const uint32
 // vcopy when set; spare: a free u64 buffer of the key capacity (used by runs
 // longer than what one workgroup sorts in registers).  The same launch
 // builds the compositor's work queue (as launch_tile_order).
+// long_stat, prims: as for launch_tile_order.
 void launch_tile_depth_sort(hipStream_t st, const uint32_t* ranges, int tiles, uint64_t* keys, uint32_t* vals,
-                            uint64_t* spare, uint32_t* vcopy, uint32_t split_len, uint32_t* order, uint32_t* queue);
+                            uint64_t* spare, uint32_t* vcopy, uint32_t split_len, uint32_t* order, uint32_t* queue,
+                            uint64_t* long_stat = nullptr, uint32_t prims = 0);
 
 // load (nullable, pinned host memory): receives tiles << 32 | key count.
 void launch_tile_ranges(hipStream_t st, const uint64_t* keys, const uint32_t* n_ptr, uint32_t cap,
@@ -142,8 +144,10 @@ struct CompositeArgs {
 // Work queue of the compositor (costliest-first tile / half-tile items);
 // must precede launch_composite_*.  Tiles with at least split_len entries
 // become two half-tile items.
+// long_stat (nullable, pinned host memory): receives prims << 32 | the
+// number of keys in runs of more than 2048 entries.
 void launch_tile_order(hipStream_t st, const uint32_t* ranges, int tiles, uint32_t split_len, uint32_t* order,
-                       uint32_t* queue);
+                       uint32_t* queue, uint64_t* long_stat = nullptr, uint32_t prims = 0);
 // Split lengths, measured: lists of cells (each entry K members) and lists
 // of Gaussians.
 constexpr uint32_t kSplitLenCells = 32;

@@ -14,8 +14,12 @@ namespace dgs {
 // entry's member costs over the item's strips -- and laid out costliest
 // first, so the longest walks start at once (order within a cost class is
 // arbitrary: it only affects scheduling, never results).
-// queue[0] = head (reset), queue[1] = item count.  One workgroup.
+// queue[0] = head (reset), queue[1] = item count.  One workgroup.  With
+// long_stat set (pinned host memory), also stores prims << 32 | the number
+// of keys in runs of more than kLongRunKeys entries, for the host's choice
+// of list order.
 constexpr int kOrderClasses = 4096;
+constexpr uint32_t kLongRunKeys = 2048;
 
 __device__ __forceinline__ void tile_items(uint32_t len, uint32_t split_len, uint32_t& n, uint32_t& cls) {
     // vector instructions per member of a whole-tile (4 strips) and a half
@@ -30,15 +34,24 @@ __device__ __forceinline__ void tile_items(uint32_t len, uint32_t split_len, uin
 // s_part [1024]: the threads' partial sums (LDS of the calling workgroup).
 __device__ __forceinline__ void build_work_queue(const uint32_t* __restrict__ ranges, int ntiles, uint32_t split_len,
                                         uint32_t* __restrict__ order, uint32_t* __restrict__ queue,
-                                        uint32_t* s_cnt, uint32_t* s_part, int tid) {
+                                        uint32_t* s_cnt, uint32_t* s_part, int tid,
+                                        uint64_t* long_stat = nullptr, uint32_t prims = 0) {
+    __shared__ uint32_t s_long;
     for (int i = tid; i < kOrderClasses; i += 1024) s_cnt[i] = 0;
+    if (tid == 0) s_long = 0;
     __syncthreads();
+    uint32_t lng = 0;  // keys of this thread's tiles in runs longer than kLongRunKeys
     for (int t = tid; t < ntiles; t += 1024) {
         uint32_t n, cls;
-        tile_items(ranges[2 * t + 1] - ranges[2 * t], split_len, n, cls);
+        const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+        tile_items(len, split_len, n, cls);
         atomicAdd(&s_cnt[cls], n);
+        lng += len > kLongRunKeys ? len : 0u;
     }
+    if (long_stat && lng) atomicAdd(&s_long, lng);
     __syncthreads();
+    if (long_stat && tid == 0)
+        __hip_atomic_store(long_stat, ((uint64_t)prims << 32) | s_long, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     // costliest first: thread i owns classes 4095 - 4i .. 4092 - 4i
     constexpr int kPer = kOrderClasses / 1024;
     uint32_t loc[kPer], run = 0;

@@ -588,14 +588,14 @@ constexpr int kTsSharedBytes = kQueueBytes > kTsChunk * 8 ? kQueueBytes : kTsChu
 __global__ __launch_bounds__(kTsThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_tile_sort(
     const uint32_t* __restrict__ ranges, int tiles, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
     uint64_t* __restrict__ spare, uint32_t* __restrict__ vcopy, uint32_t split_len, uint32_t* __restrict__ order,
-    uint32_t* __restrict__ queue) {
+    uint32_t* __restrict__ queue, uint64_t* long_stat, uint32_t prims) {
     __shared__ __align__(16) unsigned char smem[kTsSharedBytes];
     __shared__ int lt_tile[kTsWaves], lt_s[kTsWaves], lt_len[kTsWaves];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int G = (int)gridDim.x - 1;  // workgroups sorting runs
     if ((int)blockIdx.x == G) {
         uint32_t* s_cnt = reinterpret_cast<uint32_t*>(smem);
-        build_work_queue(ranges, tiles, split_len, order, queue, s_cnt, s_cnt + kOrderClasses, tid);
+        build_work_queue(ranges, tiles, split_len, order, queue, s_cnt, s_cnt + kOrderClasses, tid, long_stat, prims);
         return;
     }
     uint64_t* sd = reinterpret_cast<uint64_t*>(smem);
@@ -651,11 +651,12 @@ __global__ __launch_bounds__(kTsThreads) __attribute__((amdgpu_waves_per_eu(8)))
 }
 
 void launch_tile_depth_sort(hipStream_t st, const uint32_t* ranges, int tiles, uint64_t* keys, uint32_t* vals,
-                            uint64_t* spare, uint32_t* vcopy, uint32_t split_len, uint32_t* order, uint32_t* queue) {
+                            uint64_t* spare, uint32_t* vcopy, uint32_t split_len, uint32_t* order, uint32_t* queue,
+                            uint64_t* long_stat, uint32_t prims) {
     if (tiles <= 0) return;
     const unsigned grid = (unsigned)((tiles + kTsWaves - 1) / kTsWaves) + 1;  // + the work queue's
     hipLaunchKernelGGL(k_tile_sort, dim3(grid), dim3(kTsThreads), 0, st, ranges, tiles, keys, vals, spare, vcopy,
-                       split_len, order, queue);
+                       split_len, order, queue, long_stat, prims);
 }
 
 }  // namespace dgs

@@ -127,9 +127,11 @@ def tile_passes(cam):
 
 def test_default_order_follows_the_last_frame():
     """DGS_LIST_ORDER_AUTO: per tile when the context's last cell frame had
-    at most 128 keys per tile, else global; before any frame, by the key
-    capacity (at most 256 keys per tile).  The frames are synchronised, so
-    each choice sees the frame before it."""
+    at most 8 keys per cell, at most 1024 keys per tile
+    and at most a tenth of its keys in runs of more than 2048 entries, else
+    global; before any frame, by the key capacity (at most 256 keys per
+    tile).  The frames are synchronised, so each choice sees the frame
+    before it."""
     from paper_2508_03180_amd.renderer import DeviceScene, Renderer
     tiny, tcam, _ = scene_for("tiny")
     mid, mcam, _ = scene_for("mid0")
@@ -140,7 +142,7 @@ def test_default_order_follows_the_last_frame():
         steps = [(dt, tcam, False),  # capacity 2^20 keys over 256 tiles
                  (dm, mcam, True),   # tiny: 22 keys per tile
                  (dc, ccam, True),   # 1080p orbit frame: 64 keys per tile
-                 (dm, mcam, False),  # crowded: 3,958 keys per tile
+                 (dm, mcam, False),  # crowded: 3,958 keys per tile, all in runs over 2048
                  (dm, mcam, True)]
         images = []
         for i, (ds, cam, per_tile) in enumerate(steps):
