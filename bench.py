@@ -77,12 +77,12 @@ BYTES_PROJECT_SH3 = 12 + 12 + 16 + 4 + 192 + 48 + 8
 
 # HBM traffic of one Duplex compositor launch on this workload, from two
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) scaled by a 1 GiB copy
-# kernel's reading (profiles/composite_traffic_1080p_1M_pmc.md): 201.229 MB
-# read + 51.117 MB written.  Valid for the compositor sources it was taken
+# kernel's reading (profiles/composite_traffic_1080p_1M_pmc.md): 200.352 MB
+# read + 51.105 MB written.  Valid for the compositor sources it was taken
 # on; reported as null once one of them changes.
-COMPOSITE_TRAFFIC_BYTES = 201.229e6 + 51.117e6
+COMPOSITE_TRAFFIC_BYTES = 200.352e6 + 51.105e6
 COMPOSITE_TRAFFIC_SOURCES = {
-    "paper_2508_03180_amd/csrc/composite.hip": "50933a1ba15238ec07b9b1d6184347622dd9214e4cdbf6b32cdccbe82e1c07f8",
+    "paper_2508_03180_amd/csrc/composite.hip": "9b908b67f959c8916ad4c0dcc83857436caea24a95f6f3b7a36644380df5d4dc",
     "paper_2508_03180_amd/csrc/common.h": "ba55af4abcd758f5c95eae4b782ec45303dc4fdba45ac22ae5f538575a823139",
     "paper_2508_03180_amd/csrc/cells.h": "462a33024d920aee0b8df89a3c7d1e57d0c202a65220e8a5e209d45b9729cb2d",
 }
