@@ -201,8 +201,8 @@ dgs_status dgs_set_overlap(dgs_ctx ctx, int32_t enable);
  *   DGS_LIST_ORDER_AUTO (default): per tile for per-cell lists (Duplex,
  *     LC-WSR) when the context's last such frame had at most 8 keys per
  *     cell, at most 1024 keys per screen tile on
- *     average and at most a tenth of its keys in tile runs of more than 2048
- *     entries (the device leaves those counts in pinned host memory as the
+ *     average and at most a twentieth of its keys in tile runs of more than
+ *     4096 entries (the device leaves those counts in pinned host memory as the
  *     frame's lists are built; before any such frame: when the key capacity
  *     is at most 256 keys per tile), else global (always for
  *     DGS_MODE_ALPHA).

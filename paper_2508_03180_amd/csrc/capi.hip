@@ -586,15 +586,15 @@ dgs_status dgs_read_decoded(dgs_ctx c, float* means, float* scales, float* rots,
 // Per-cell tile lists (Duplex, LC-WSR) are put in depth order per tile
 // (launch_tile_depth_sort) when the context's last cell frame had at most 8
 // keys per cell, at most 1024 keys per tile on
-// average, and at most a tenth of its keys in runs of more than 2048
+// average, and at most a twentieth of its keys in runs of more than 4096
 // entries (which the per-tile sort handles by chunked merges in global
-// memory); before any cell frame, when the key buffer holds at most 256
-// keys per tile.  The per-tile sort's cost grows with the keys and their
+// memory over several rounds); before any cell frame, when the key buffer
+// holds at most 256 keys per tile.  The per-tile sort's cost grows with the keys and their
 // run lengths, the depth sort's with the cells only.  Per-Gaussian lists
 // always take the depth sort of the primitives.
 constexpr uint64_t kPerTileOrderKeysPerCell = 8;
 constexpr int64_t kPerTileOrderMaxMean = 1024;      // keys per tile
-constexpr uint64_t kPerTileOrderLongShare = 10;     // at most 1 / this of the keys in long runs
+constexpr uint64_t kPerTileOrderLongShare = 20;     // at most 1 / this of the keys in long runs
 constexpr int64_t kPerTileOrderCapacity = 256;      // keys per tile, before any cell frame
 
 static bool per_tile_order(dgs_ctx c, int64_t tiles, bool cells) {

@@ -61,7 +61,7 @@ struct dgs_ctx_s {
     // address), written by the device and read by the next frame's choice of
     // list order: [0] tiles << 32 | keys (0: none yet), as the frame's tile
     // ranges are built; [1] its primitives << 32 | its keys in runs of more
-    // than 2048 entries, as its work queue is built.
+    // than 4096 entries, as its work queue is built.
     uint64_t* load_host = nullptr;
     uint64_t* load_dev = nullptr;
     hipStream_t aux = nullptr;

@@ -145,7 +145,7 @@ struct CompositeArgs {
 // must precede launch_composite_*.  Tiles with at least split_len entries
 // become two half-tile items.
 // long_stat (nullable, pinned host memory): receives prims << 32 | the
-// number of keys in runs of more than 2048 entries.
+// number of keys in runs of more than 4096 entries.
 void launch_tile_order(hipStream_t st, const uint32_t* ranges, int tiles, uint32_t split_len, uint32_t* order,
                        uint32_t* queue, uint64_t* long_stat = nullptr, uint32_t prims = 0);
 // Split lengths, measured: lists of cells (each entry K members) and lists

@@ -19,7 +19,7 @@ namespace dgs {
 // of keys in runs of more than kLongRunKeys entries, for the host's choice
 // of list order.
 constexpr int kOrderClasses = 4096;
-constexpr uint32_t kLongRunKeys = 2048;
+constexpr uint32_t kLongRunKeys = 4096;
 
 __device__ __forceinline__ void tile_items(uint32_t len, uint32_t split_len, uint32_t& n, uint32_t& cls) {
     // vector instructions per member of a whole-tile (4 strips) and a half

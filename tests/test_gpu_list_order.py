@@ -128,7 +128,7 @@ def tile_passes(cam):
 def test_default_order_follows_the_last_frame():
     """DGS_LIST_ORDER_AUTO: per tile when the context's last cell frame had
     at most 8 keys per cell, at most 1024 keys per tile
-    and at most a tenth of its keys in runs of more than 2048 entries, else
+    and at most a twentieth of its keys in runs of more than 4096 entries, else
     global; before any frame, by the key capacity (at most 256 keys per
     tile).  The frames are synchronised, so each choice sees the frame
     before it."""
@@ -142,7 +142,7 @@ def test_default_order_follows_the_last_frame():
         steps = [(dt, tcam, False),  # capacity 2^20 keys over 256 tiles
                  (dm, mcam, True),   # tiny: 22 keys per tile
                  (dc, ccam, True),   # 1080p orbit frame: 64 keys per tile
-                 (dm, mcam, False),  # crowded: 3,958 keys per tile, all in runs over 2048
+                 (dm, mcam, False),  # crowded: 3,958 keys per tile, 69% in a run over 4096
                  (dm, mcam, True)]
         images = []
         for i, (ds, cam, per_tile) in enumerate(steps):
